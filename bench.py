@@ -1,0 +1,200 @@
+#!/usr/bin/env python3
+"""Benchmark of the GridFF hot path on one MI355X.
+
+Workload (default): 16 384 replicas of the 38-atom planar molecule on the 2x2-cell,
+3-plane rock-salt slab, grids 112 x 112 x 150 x 3 built and fitted on the GPU (FP64)
+and stored in FP32; velocity-Verlet NVE, dt = 0.5 fs, 300 K start, FP64 drift
+accounting every step.  One benchmark step = one gff_relax_batch launch that advances
+every replica by 5000 MD steps (grid interpolation + intramolecular field + integrator,
+all inside the kernel).  value = replica-steps/s over the K timed launches.
+
+Prints one JSON line.  See the design doc for the roofline accounting.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--md-steps", type=int, default=5000, help="MD steps per relax_batch launch")
+    ap.add_argument("--replicas", type=int, default=16384)
+    ap.add_argument("--storage", choices=["f32", "f16"], default="f32")
+    ap.add_argument("--block", type=int, default=0, help="block threads (0: autotuned default)")
+    ap.add_argument("--compare-f16", action="store_true", help="also time the FP16-grid variant")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run a 1 GiB device copy first (reference for HBM counter scaling)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "replicas are independent, so more GPUs would each run their own share", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2508_15522_amd import configs, device as D, gridff as G, synth as S
+    D.require_gpu()
+    wl = configs.C2_PAH_NVE
+    cfg = wl.grid
+    sub = cfg.substrate()
+    spec = D.spec_for(cfg)
+    mol = S.mol_pah38()
+    mols = [mol]
+    n_rep = args.replicas
+    block = args.block or 256
+
+    def setup(storage):
+        grid = D.build_physical_grid(sub, spec, storage)
+        return grid
+
+    log("building grid (FP64 build + fit on GPU)")
+    t0 = time.time()
+    grid = setup(G.STORE_F16 if args.storage == "f16" else G.STORE_F32)
+    torch.cuda.synchronize()
+    build_s = time.time() - t0
+    topo = G.Topology(mols)
+    plan = G.Plan(topo, np.zeros(n_rep, np.int32), block_threads=block)
+    pos0 = S.place_replicas(mol, n_rep, sub, S.SEED_PLACE * 2)
+    vel0 = S.mb_velocities(mol.mass, n_rep, 300.0, S.SEED_NVE)
+    st0 = D.fire_state(plan, pos0, vel_per_rep=vel0)
+    out = D.outputs(plan)
+    prm = G.relax_params(G.MODE_NVE, args.md_steps, True, dt=0.5, drift_every=1)
+    stream = torch.cuda.current_stream()
+
+    def run_once(g, st):
+        G.relax_batch(g.desc, topo, plan, prm, st, out["E"], out["fnorm"], out["steps"], out["drift"], stream)
+
+    def fresh_state():
+        return {k: v.clone() for k, v in st0.items()}
+
+    def timed(g, K, W):
+        for _ in range(W):
+            run_once(g, fresh_state())
+        torch.cuda.synchronize()
+        states = [fresh_state() for _ in range(K)]
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * K)]
+        torch.cuda.synchronize()
+        t = time.time()
+        for k in range(K):
+            ev[2 * k].record(stream)
+            run_once(g, states[k])
+            ev[2 * k + 1].record(stream)
+        torch.cuda.synchronize()
+        wall = time.time() - t
+        per = [ev[2 * k].elapsed_time(ev[2 * k + 1]) / 1e3 for k in range(K)]
+        return wall, per, states[-1]
+
+    if args.copy_probe:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    log(f"warmup {args.warmup}, timing {args.steps} launches of {args.md_steps} MD steps x {n_rep} replicas")
+    wall, per, st_last = timed(grid, args.steps, args.warmup)
+    rs = n_rep * args.md_steps
+    value = rs * args.steps / wall
+    kern_avg = float(np.mean(per))
+    drift = out["drift"].cpu().numpy()
+    status = st_last["status"].cpu().numpy()
+    # algorithmic bytes: 64 stencil nodes x 3 channels per atom per force evaluation
+    bpn = 4 if args.storage == "f32" else 2
+    evals = args.md_steps + 1
+    alg_bytes = n_rep * mol.n * evals * 64 * 3 * bpn
+    achieved = alg_bytes / kern_avg / 1e9
+    res = {
+        "metric": "replica-steps/s",
+        "value": value,
+        "unit": "replica-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.storage,
+        "data": "synthetic",
+        "config": {
+            "workload": f"pah38-nve-{n_rep}",
+            "substrate": "rock-salt 2x2 cells x 3 planes (48 atoms), a=5.64 A, +-0.7 e",
+            "grid": f"{cfg.nx}x{cfg.ny}x{cfg.nz}x3 {args.storage} (0.1 A)",
+            "replicas": n_rep, "atoms_per_replica": mol.n, "md_steps_per_launch": args.md_steps,
+            "dt_fs": 0.5, "block_threads": block, "drift_fp64_every": 1,
+        },
+        "interpolations_per_s": n_rep * mol.n * evals * args.steps / wall,
+        "kernel_avg_s": kern_avg,
+        "grid_build_fit_s": build_s,
+        "nve_max_abs_drift_eV": float(np.nanmax(drift[:, 2])),
+        "nonfinite_replicas": int(((status & G.REP_NONFINITE) != 0).sum()),
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": f"k_replicas<{args.storage},NVE>",
+                     "bytes_per_launch": alg_bytes},
+    }
+    if args.compare_f16 and args.storage == "f32":
+        g16 = setup(G.STORE_F16)
+        w16, p16, _ = timed(g16, args.steps, 1)
+        res["f16_value"] = rs * args.steps / w16
+        res["f16_kernel_avg_s"] = float(np.mean(p16))
+        res["f16_vs_f32"] = res["f16_value"] / value
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(mol, cfg, args.cpu_seconds)
+    print(json.dumps(res), flush=True)
+
+
+def cpu_baseline(mol, cfg, budget_s):
+    """The FP64 oracle on the host cores: NVE of the same molecule on a grid of the same
+    size (random coefficients from the seeded generator -- the oracle's cost does not
+    depend on the coefficient values), on a bounded sample of replicas and steps."""
+    import oracle as O
+    from paper_2508_15522_amd import synth as S
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    B = S.random_coefficients(cfg.nx, cfg.ny, cfg.nz, 1, (1e-3, 1e-2, 1e-1))
+    geo = dict(nx=cfg.nx, ny=cfg.ny, nz=cfg.nz, x0=0.0, y0=0.0, z0=cfg.z0, dx=2 * S.SLAB_A / cfg.nx,
+               dy=2 * S.SLAB_A / cfg.ny, dz=cfg.dz)
+    sub = S.rocksalt_slab(2, 3)
+    # calibrate
+    n_rep, n_steps = max(threads, 16), 4
+    pos = S.place_replicas(mol, n_rep, sub, 77).reshape(-1, 3)
+    vel = S.mb_velocities(mol.mass, n_rep, 300.0, 7).reshape(-1, 3)
+    t = time.time()
+    O.nve_batch(B, geo, [mol], np.zeros(n_rep, np.int32), pos, vel, n_steps)
+    dt = max(time.time() - t, 1e-3)
+    per = dt / (n_rep * n_steps)
+    # fill the budget: up to 16384 replicas (the workload's count), then more steps
+    total = budget_s / per
+    n_rep = int(min(16384, max(threads, total / 20)))
+    n_rep = max(threads, (n_rep // threads) * threads)
+    n_steps = int(max(4, min(5000, total / n_rep)))
+    pos = S.place_replicas(mol, n_rep, sub, 78).reshape(-1, 3)
+    vel = S.mb_velocities(mol.mass, n_rep, 300.0, 8).reshape(-1, 3)
+    t = time.time()
+    O.nve_batch(B, geo, [mol], np.zeros(n_rep, np.int32), pos, vel, n_steps)
+    el = time.time() - t
+    return {"value": n_rep * n_steps / el, "unit": "replica-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n_rep} replicas x {n_steps} NVE steps of the 38-atom molecule, FP64 B-spline model + "
+                      f"intramolecular field, {el:.1f} s"}
+
+
+if __name__ == "__main__":
+    main()

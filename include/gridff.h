@@ -1,0 +1,249 @@
+/*
+ * gridff.h -- C ABI of the MI355X (gfx950) GridFF hot path.
+ *
+ * GridFF (Mal, Koci, Nicolini & Hapala, arXiv 2508.15522) replaces the molecule-
+ * substrate interaction by three precomputed grids -- Pauli V^P, London V^L and
+ * Coulomb V^C -- that carry no molecular types or charges (Section "Principles",
+ * Eqs. E, E_Coulomb, E_Morse, V_Morse).  Each atom's energy is the tricubic
+ * B-spline interpolant of the grids mixed with the atom's own coefficients,
+ *     E_i = P_i V^P(r_i) + L_i V^L(r_i) + Q_i V^C(r_i),
+ *     P_i = eps_i exp(2 alpha R_i),  L_i = -2 eps_i exp(alpha R_i),  Q_i = charge,
+ * and forces are the analytic gradient of that interpolant (Section
+ * "Interpolation", Eqs. Bspline1D, Bspline).  The library builds the grids,
+ * fits the B-spline coefficients, evaluates energies and forces, and relaxes
+ * (FIRE) or integrates (velocity-Verlet NVE) thousands of independent molecule
+ * replicas at once, with the whole step loop on the GPU (Section "Configuration
+ * sampling on GPU").
+ *
+ * Conventions for every entry point:
+ *  - Units: energy eV, length Angstrom, charge e, mass amu, time fs (NVE) or the
+ *    unit-mass FIRE time unit.
+ *  - Pointers named d_* are device memory owned by the caller; *_h pointers are
+ *    host memory owned by the caller.  Opaque handles (gff_topology, gff_plan) own
+ *    device memory they allocate at creation and free on destroy.  No entry point
+ *    that takes a stream allocates device memory.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).  Calls
+ *    only enqueue work; outputs are valid once the stream has synchronised.
+ *  - Arguments are validated before anything is enqueued; a negative gff_status
+ *    means nothing was enqueued.  GFF_EHIP reports a HIP launch/runtime error.
+ *  - Per-replica physics problems are not errors: they are GFF_REP_* status bits.
+ *  - Results are deterministic: identical inputs give bitwise-identical outputs
+ *    (no floating-point atomics; every reduction has a fixed order).
+ *  - Per-atom arrays are structure-of-arrays [3][n_atoms_total] (x block, then y,
+ *    then z).  Replica r owns atoms atom_off[r] .. atom_off[r+1]-1 where atom_off is
+ *    the prefix sum of the replicas' atom counts in replica order.
+ */
+#ifndef GRIDFF_H
+#define GRIDFF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GFF_OK = 0,
+    GFF_EINVAL = -1,          /* invalid argument (null pointer, bad size, inconsistent grid) */
+    GFF_EUNSUPPORTED = -2,    /* valid request the library does not implement (e.g. > 128 atoms) */
+    GFF_EHIP = -3,            /* HIP runtime or launch error */
+    GFF_EWORKSPACE = -4,      /* workspace smaller than the *_workspace_bytes query */
+    GFF_ENOMEM = -5           /* allocation failed inside a create call */
+} gff_status;
+
+enum { GFF_STORE_F32 = 0, GFF_STORE_F16 = 1 };
+
+/* per-replica status bits */
+enum {
+    GFF_REP_CONVERGED = 1,     /* FIRE: |F|_2 over the replica's 3N force vector < f_conv; frozen */
+    GFF_REP_OUT_OF_DOMAIN = 2, /* an atom was below the first grid plane (evaluated on that plane) */
+    GFF_REP_NONFINITE = 4,     /* a non-finite force/energy/coordinate appeared; replica frozen */
+    GFF_REP_MAXSTEPS = 8       /* FIRE with f_conv > 0 ended without converging */
+};
+
+enum { GFF_MODE_FIRE = 0, GFF_MODE_NVE = 1 };
+
+const char *gff_status_string(int status);
+
+/* ------------------------------------------------------------------ grid build and fit */
+
+/* Rigid substrate, host FP64, periodic in x and y with an orthorhombic Lx x Ly cell.
+ * The lateral periodicity is the substrate's only (Section "Periodicity and long-range
+ * electrostatics"): the molecule never meets its own images. */
+typedef struct {
+    int n_atoms;
+    const double *pos_h;   /* [n_atoms][3] */
+    const double *q_h;     /* [n_atoms] charges; the slab must be neutral with zero z-dipole */
+    const double *eps_h;   /* [n_atoms] Morse eps_j (pair depth eps_i eps_j) */
+    const double *R_h;     /* [n_atoms] Morse R_j (pair separation R_i + R_j) */
+    double Lx, Ly;
+} gff_substrate;
+
+/* Grid geometry and build physics.  Node (i,j,k) sits at
+ * (x0 + i Lx/nx, y0 + j Ly/ny, z0 + k dz); x and y are periodic, so the node spacing is
+ * dx = Lx/nx, dy = Ly/ny.  z0 must lie above every substrate atom (the Coulomb channel is
+ * built with the above-slab Fourier form of the 2D lattice sum). */
+typedef struct {
+    int nx, ny, nz;          /* >= 4 each */
+    double x0, y0, z0, dz;
+    double alpha;            /* Morse alpha [1/A] (the paper uses one alpha for all pairs) */
+    double rcut;             /* direct-sum cutoff of the Pauli/London image sums [A] */
+    double k_e;              /* Coulomb constant; <= 0 selects 14.3996454784 eV A/e^2 */
+} gff_grid_spec;
+
+/* V[c][i][j][k], c = 0 Pauli, 1 London, 2 Coulomb, FP64, z fastest:
+ *   V^P(r) = sum_j sum_n eps_j exp(-2 alpha(|r - r_j - n| - R_j))   (images n, |.| < rcut)
+ *   V^L(r) = sum_j sum_n eps_j exp(-alpha(|r - r_j - n| - R_j))
+ *   V^C(r) = k_e sum_{G != 0} (2 pi / A) sum_j Q_j cos(G.(rho - rho_j)) exp(-|G|(z - z_j)) / |G|
+ * (Eq. V_Morse; Section "Periodicity and long-range electrostatics": the exact
+ * 2D-periodic Coulomb lattice sum above a neutral zero-dipole slab, V^C -> 0 far above;
+ * the paper's reciprocal-space Poisson solve approximates the same potential).
+ * d_work: at least gff_build_grid_workspace_bytes(spec, sub) bytes of device memory. */
+size_t gff_build_grid_workspace_bytes(const gff_grid_spec *spec, const gff_substrate *sub);
+gff_status gff_build_grid(const gff_substrate *sub, const gff_grid_spec *spec, double *d_V,
+                          void *d_work, size_t work_bytes, void *stream);
+
+/* Exact B-spline coefficients B[3][nx][ny][nz] (FP64) of V[3][nx][ny][nz]: the tricubic
+ * B-spline model reproduces V at every node (Section "Interpolation", fitting paragraph;
+ * the paper fits this linear system by gradient descent, here it is solved exactly by
+ * separable tridiagonal solves: cyclic along x and y, even-mirror rows along z, i.e.
+ * (4 b_0 + 2 b_1)/6 = V_0 and (2 b_{n-2} + 4 b_{n-1})/6 = V_{n-1}).  d_B may not alias d_V.
+ * d_work: gff_fit_workspace_bytes(spec) bytes. */
+size_t gff_fit_workspace_bytes(const gff_grid_spec *spec);
+gff_status gff_fit_bspline(const gff_grid_spec *spec, const double *d_V, double *d_B,
+                           void *d_work, size_t work_bytes, void *stream);
+
+/* Storage cast of fitted coefficients into the evaluation layout:
+ * coef[i][j][p][c4], p = 0 .. nz+2 holds z node p-1 with even-mirror padding
+ * (node -1 -> 1, node nz -> nz-2, node nz+1 -> nz-3), c4 = (Pauli, London, Coulomb, 0).
+ * GFF_STORE_F32: float; GFF_STORE_F16: IEEE half of b / s_c (round to nearest even), with
+ * per-channel scale s_c = 2^(ceil(log2 max|b_c|) - 15) written to d_scale[0..2]
+ * (d_scale[3] = 0).  For F32, d_scale (if not NULL) receives 1,1,1,0.
+ * d_coef: gff_grid_bytes(spec, storage) bytes. */
+size_t gff_grid_bytes(const gff_grid_spec *spec, int storage);
+gff_status gff_pack_grid(const gff_grid_spec *spec, const double *d_B, int storage,
+                         void *d_coef, float *d_scale, void *stream);
+
+/* ------------------------------------------------------------------ evaluation */
+
+/* A fitted, device-resident grid in the gff_pack_grid layout.  The lateral period is
+ * nx*dx by ny*dy.  Coordinates below z0 are evaluated on the z0 plane (and flagged);
+ * coordinates strictly above the last node z0 + (nz-1) dz contribute zero. */
+typedef struct {
+    int storage;             /* GFF_STORE_F32 or GFF_STORE_F16 */
+    int nx, ny, nz;
+    float x0, y0, z0, dx, dy, dz;
+    const void *d_coef;
+    const float *d_scale;    /* [4] decode scale (F16); NULL for F32 means 1 */
+} gff_grid;
+
+/* One molecule type, host arrays, FP32.  Intramolecular field (synthetic, explicit):
+ *   bond 1/2 k (r - r0)^2; angle 1/2 k (cos th - cos0)^2 (vertex = middle index);
+ *   torsion 1/2 V (1 - cos(n phi - phi0)), phi the IUPAC dihedral of (i,j,k,l);
+ *   non-bonded for pairs more than two bonds apart: Morse with depth eps_i eps_j at
+ *   R_i + R_j and the grid's alpha, plus k_e Q_i Q_j / r.
+ * The rotatable torsions (rot_quads, rot_mask) and ref_pos are only used by pose
+ * construction and may be empty/NULL otherwise. */
+typedef struct {
+    int n_atoms;                         /* 1 .. 128 */
+    const float *eps, *R, *q, *mass;     /* [n_atoms] */
+    int n_bonds;  const int *bonds;  const float *bond_k, *bond_r0;       /* bonds [n][2] */
+    int n_angles; const int *angles; const float *angle_k, *angle_cos0;  /* angles [n][3] */
+    int n_tors;   const int *tors;   const float *tors_V; const int *tors_n; const float *tors_phi0; /* [n][4] */
+    int n_rot;    const int *rot_quads; const unsigned char *rot_mask;   /* [n_rot][4], [n_rot][n_atoms] */
+    const float *ref_pos;                /* [n_atoms][3] reference geometry */
+} gff_mol_type;
+
+typedef struct gff_topology_s gff_topology;
+
+/* Builds the device tables of a set of molecule types (mixing coefficients P, L, Q from
+ * (eps, R, q) and alpha; per-atom incidence lists of bonded terms; 1-2/1-3 exclusion
+ * masks).  Allocates device memory; not stream-ordered (synchronous upload). */
+gff_status gff_topology_create(const gff_mol_type *types_h, int n_types, float alpha, float k_e,
+                               gff_topology **out);
+void gff_topology_destroy(gff_topology *topo);
+
+/* Launch shape of the replica kernels.  block_threads: multiple of 64 in [64, 1024];
+ * replicas of one type are packed densely into blocks, one lane per atom, floor(block/n)
+ * replicas per block (at most reps_per_block if > 0).  grid_blocks <= 0: one block per pack. */
+typedef struct {
+    int block_threads;
+    int reps_per_block;
+    int grid_blocks;
+} gff_launch;
+
+typedef struct gff_plan_s gff_plan;
+
+/* Work list for a batch of n_rep replicas with types rep_type_h[r]: packs of same-type
+ * replicas, sorted largest type first.  Allocates device memory (synchronous). */
+gff_status gff_plan_create(const gff_topology *topo, int n_rep, const int *rep_type_h,
+                           const gff_launch *launch /* NULL = default */, gff_plan **out);
+void gff_plan_destroy(gff_plan *plan);
+int gff_plan_n_atoms(const gff_plan *plan);
+int gff_plan_n_packs(const gff_plan *plan);
+/* atom_off_h[n_rep+1]: the replica atom offsets of the per-atom arrays */
+gff_status gff_plan_atom_offsets(const gff_plan *plan, int *atom_off_h);
+
+/* Energy and forces at fixed positions.  d_F [3][N] = -grad E (grid part plus, if
+ * include_intra, the intramolecular field); d_E_atom [N] (nullable) the per-atom grid
+ * energy E_i; d_E_rep [n_rep] (nullable) the replica's total energy, summed in FP64;
+ * d_status [n_rep] (nullable) OUT_OF_DOMAIN / NONFINITE bits. */
+gff_status gff_eval_forces(const gff_grid *grid, const gff_topology *topo, const gff_plan *plan,
+                           int include_intra, const float *d_pos, float *d_F, float *d_E_atom,
+                           double *d_E_rep, unsigned *d_status, void *stream);
+
+/* Plain per-point interpolation (no molecules): d_pos [3][n], d_plq [3][n] = (P, L, Q)
+ * per point, outputs d_F [3][n] and d_E [n] (nullable). */
+gff_status gff_interp_points(const gff_grid *grid, int n, const float *d_pos, const float *d_plq,
+                             float *d_F, float *d_E, void *stream);
+
+/* ------------------------------------------------------------------ relaxation / dynamics */
+
+typedef struct {
+    int mode;                 /* GFF_MODE_FIRE or GFF_MODE_NVE */
+    int n_steps;              /* moves (FIRE) or time steps (NVE); >= 0 */
+    int include_intra;
+    float dt;                 /* NVE time step [fs]; FIRE: unused (per-replica dt is state) */
+    float f_conv;             /* FIRE convergence on |F|_2 [eV/A]; <= 0: never */
+    float max_disp;           /* FIRE per-atom displacement cap per step [A] */
+    float fire_finc, fire_fdec, fire_alpha0, fire_falpha, fire_dtmax;
+    int fire_nmin;
+    int drift_every;          /* NVE: FP64 total-energy sample every k steps (>= 1) */
+} gff_relax_params;
+
+/* Caller-owned replica state (in/out). */
+typedef struct {
+    float *d_pos;             /* [3][N] */
+    float *d_vel;             /* [3][N]; FIRE: unit-mass velocities, NVE: A/fs */
+    float *d_fire_dt;         /* [n_rep] FIRE time step (initialise to dt0) */
+    float *d_fire_alpha;      /* [n_rep] FIRE mixing (initialise to alpha0) */
+    int *d_fire_npos;         /* [n_rep] steps since P <= 0 (initialise to 0) */
+    unsigned *d_status;       /* [n_rep] GFF_REP_* bits (initialise to 0) */
+} gff_state;
+
+/* FIRE (Bitzek et al. 2006) per replica with unit masses, every step on the GPU:
+ * evaluate F, E at x; if |F|_2 < f_conv set CONVERGED and freeze; P = F.v;
+ * v <- (1-a) v + a |v| F/|F|; if P > 0 { npos++; if npos > nmin: dt <- min(dt finc, dtmax),
+ * a <- a falpha } else { dt <- dt fdec; a <- alpha0; v <- 0; npos <- 0 }; v <- v + F dt;
+ * dx = v dt scaled per atom to |dx_i| <= max_disp; x <- x + dx.  After n_steps moves the
+ * final state is evaluated once more.  Replicas converged on entry are evaluated, not moved.
+ *
+ * NVE: velocity Verlet with masses in amu, a = F/(m 103.6427) [A/fs^2]; forces at the
+ * entry positions are evaluated first.  Every drift_every steps the total energy
+ * E_pot + sum m v^2/2 is formed in FP64 and accumulated in d_drift_rep[r][6] =
+ * {E(0), E(last sample), max|E(s)-E(0)|, sum dE, sum s dE, samples}; non-finite energies
+ * freeze the replica at those samples.
+ *
+ * Outputs: d_E_rep [n_rep] (FP64 total energy at the last evaluation), d_fnorm_rep
+ * [n_rep] (|F|_2 there, FP32), d_steps_rep [n_rep] (moves made), d_drift_rep nullable.
+ * One kernel launch runs the whole step loop. */
+gff_status gff_relax_batch(const gff_grid *grid, const gff_topology *topo, const gff_plan *plan,
+                           const gff_relax_params *params, const gff_state *state,
+                           double *d_E_rep, float *d_fnorm_rep, int *d_steps_rep,
+                           double *d_drift_rep, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GRIDFF_H */

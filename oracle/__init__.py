@@ -331,8 +331,11 @@ def eval_batch(B, spec, mols, rep_type, pos, intra_on=True, alpha=1.6):
     return F, Er, Ea, st
 
 
+# dt_max = 0.1: the stiffest bond modes (unit masses, k = 20 eV/A^2, up to three bonds per
+# atom) put the semi-implicit Euler stability limit near 0.18; larger steps keep FIRE
+# resetting and it stalls
 FIRE_DEFAULTS = dict(dt0=0.05, f_conv=1e-4, max_disp=0.1, finc=1.1, fdec=0.5, alpha0=0.1,
-                     falpha=0.99, dtmax=0.5, nmin=5)
+                     falpha=0.99, dtmax=0.1, nmin=5)
 
 
 def fire_batch(B, spec, mols, rep_type, pos, n_steps, vel=None, state=None, intra_on=True,

@@ -1,0 +1,244 @@
+// Host side of libgridff: molecule-type tables, replica work lists, status strings.
+#include "gff_internal.hpp"
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+using namespace gff;
+
+extern "C" const char *gff_status_string(int s) {
+    switch (s) {
+        case GFF_OK: return "ok";
+        case GFF_EINVAL: return "invalid argument";
+        case GFF_EUNSUPPORTED: return "unsupported request";
+        case GFF_EHIP: return "HIP runtime or launch error";
+        case GFF_EWORKSPACE: return "workspace too small";
+        case GFF_ENOMEM: return "device allocation failed";
+        default: return "unknown status";
+    }
+}
+
+namespace {
+
+template <class T>
+gff_status upload(std::vector<void *> &owned, const std::vector<T> &h, const T **out) {
+    size_t bytes = std::max<size_t>(1, h.size()) * sizeof(T);
+    void *d = nullptr;
+    if (hipMalloc(&d, bytes) != hipSuccess) return GFF_ENOMEM;
+    owned.push_back(d);
+    if (!h.empty() && hipMemcpy(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+        return GFF_EHIP;
+    *out = static_cast<const T *>(d);
+    return GFF_OK;
+}
+
+void free_all(std::vector<void *> &owned) {
+    for (void *p : owned) (void)hipFree(p);
+    owned.clear();
+}
+
+bool valid_type(const gff_mol_type &m) {
+    if (m.n_atoms < 1 || m.n_atoms > kMaxAtoms) return false;
+    if (!m.eps || !m.R || !m.q || !m.mass) return false;
+    auto in = [&](int i) { return i >= 0 && i < m.n_atoms; };
+    if (m.n_bonds < 0 || (m.n_bonds > 0 && (!m.bonds || !m.bond_k || !m.bond_r0))) return false;
+    for (int b = 0; b < m.n_bonds; ++b)
+        if (!in(m.bonds[2 * b]) || !in(m.bonds[2 * b + 1]) || m.bonds[2 * b] == m.bonds[2 * b + 1]) return false;
+    if (m.n_angles < 0 || (m.n_angles > 0 && (!m.angles || !m.angle_k || !m.angle_cos0))) return false;
+    for (int a = 0; a < 3 * m.n_angles; ++a) if (!in(m.angles[a])) return false;
+    if (m.n_tors < 0 || (m.n_tors > 0 && (!m.tors || !m.tors_V || !m.tors_n || !m.tors_phi0))) return false;
+    for (int t = 0; t < 4 * m.n_tors; ++t) if (!in(m.tors[t])) return false;
+    for (int t = 0; t < m.n_tors; ++t) if (m.tors_n[t] < 1 || m.tors_n[t] > 12) return false;
+    if (m.n_rot < 0 || (m.n_rot > 0 && (!m.rot_quads || !m.rot_mask))) return false;
+    for (int t = 0; t < 4 * m.n_rot; ++t) if (!in(m.rot_quads[t])) return false;
+    for (int a = 0; a < m.n_atoms; ++a)
+        if (!(m.mass[a] > 0.f) || !std::isfinite(m.eps[a]) || !std::isfinite(m.R[a]) || !std::isfinite(m.q[a]))
+            return false;
+    return true;
+}
+
+}  // namespace
+
+extern "C" gff_status gff_topology_create(const gff_mol_type *types, int n_types, float alpha, float k_e,
+                                          gff_topology **out) {
+    if (!types || n_types < 1 || !out || !(alpha > 0.f)) return GFF_EINVAL;
+    for (int t = 0; t < n_types; ++t) if (!valid_type(types[t])) return GFF_EINVAL;
+    auto *T = new gff_topology_s();
+    T->n_types = n_types;
+    T->alpha = alpha;
+    T->ke = k_e > 0.f ? k_e : (float)kDefaultKe;
+    std::vector<TypeInfo> ti(n_types);
+    std::vector<float4> plqm, refpos;
+    std::vector<float> khalf;
+    std::vector<uint4> excl;
+    std::vector<int4> incA, rotq;
+    std::vector<int2> incT, rotinfo(n_types);
+    std::vector<BondInc> bnd;
+    std::vector<AngInc> ang;
+    std::vector<TorInc> tor;
+    std::vector<uint4> rotm;
+    for (int t = 0; t < n_types; ++t) {
+        const gff_mol_type &m = types[t];
+        const int n = m.n_atoms;
+        ti[t] = TypeInfo{n, (int)plqm.size(), 0, 0};
+        T->natoms.push_back(n);
+        T->nrot.push_back(m.n_rot);
+        // adjacency and exclusions (self, 1-2, 1-3)
+        std::vector<std::vector<char>> adj(n, std::vector<char>(n, 0));
+        for (int b = 0; b < m.n_bonds; ++b) {
+            int i = m.bonds[2 * b], j = m.bonds[2 * b + 1];
+            adj[i][j] = adj[j][i] = 1;
+        }
+        for (int a = 0; a < n; ++a) {
+            const double eps = m.eps[a], R = m.R[a];
+            const double P = eps * std::exp(2.0 * alpha * R), L = -2.0 * eps * std::exp(alpha * R);
+            const double macc = (double)m.mass[a] * kEvPerAmuA2Fs2;
+            plqm.push_back(make_float4((float)P, (float)L, m.q[a], (float)(1.0 / macc)));
+            khalf.push_back((float)(0.5 * macc));
+            unsigned w[4] = {0, 0, 0, 0};
+            for (int b = 0; b < n; ++b) {
+                bool e = (a == b) || adj[a][b];
+                for (int c = 0; c < n && !e; ++c) if (adj[a][c] && adj[c][b]) e = true;
+                if (e) w[b >> 5] |= 1u << (b & 31);
+            }
+            excl.push_back(make_uint4(w[0], w[1], w[2], w[3]));
+            const float *rp = m.ref_pos;
+            refpos.push_back(rp ? make_float4(rp[3 * a], rp[3 * a + 1], rp[3 * a + 2], 0.f) : make_float4(0, 0, 0, 0));
+            // incident terms
+            int4 ia;
+            ia.x = (int)bnd.size();
+            for (int b = 0; b < m.n_bonds; ++b) {
+                int i = m.bonds[2 * b], j = m.bonds[2 * b + 1];
+                if (i == a) bnd.push_back(BondInc{j, 0, m.bond_k[b], m.bond_r0[b]});
+                else if (j == a) bnd.push_back(BondInc{i, 1, m.bond_k[b], m.bond_r0[b]});
+            }
+            ia.y = (int)bnd.size() - ia.x;
+            ia.z = (int)ang.size();
+            for (int q = 0; q < m.n_angles; ++q) {
+                const int *A3 = m.angles + 3 * q;
+                for (int s = 0; s < 3; ++s)
+                    if (A3[s] == a) { ang.push_back(AngInc{A3[0], A3[1], A3[2], s, m.angle_k[q], m.angle_cos0[q], 0, 0}); break; }
+            }
+            ia.w = (int)ang.size() - ia.z;
+            incA.push_back(ia);
+            int2 it;
+            it.x = (int)tor.size();
+            for (int q = 0; q < m.n_tors; ++q) {
+                const int *Q4 = m.tors + 4 * q;
+                for (int s = 0; s < 4; ++s)
+                    if (Q4[s] == a) {
+                        const int packed = Q4[0] | (Q4[1] << 8) | (Q4[2] << 16) | (Q4[3] << 24);
+                        const double ph = m.tors_phi0[q];
+                        tor.push_back(TorInc{packed, s, m.tors_n[q], m.tors_V[q], (float)std::cos(ph), (float)std::sin(ph), 0, 0});
+                        break;
+                    }
+            }
+            it.y = (int)tor.size() - it.x;
+            incT.push_back(it);
+        }
+        rotinfo[t] = make_int2((int)rotq.size(), m.n_rot);
+        for (int k = 0; k < m.n_rot; ++k) {
+            const int *q = m.rot_quads + 4 * k;
+            rotq.push_back(make_int4(q[0], q[1], q[2], q[3]));
+            unsigned w[4] = {0, 0, 0, 0};
+            for (int a = 0; a < n; ++a) if (m.rot_mask[(size_t)k * n + a]) w[a >> 5] |= 1u << (a & 31);
+            rotm.push_back(make_uint4(w[0], w[1], w[2], w[3]));
+        }
+    }
+    gff_status rc = GFF_OK;
+    auto &o = T->allocations;
+    DevTopo &d = T->dev;
+    if ((rc = upload(o, ti, &d.types)) || (rc = upload(o, plqm, &d.plqm)) || (rc = upload(o, khalf, &d.khalf)) ||
+        (rc = upload(o, excl, &d.excl)) || (rc = upload(o, incA, &d.incA)) || (rc = upload(o, incT, &d.incT)) ||
+        (rc = upload(o, bnd, &d.bnd)) || (rc = upload(o, ang, &d.ang)) || (rc = upload(o, tor, &d.tor)) ||
+        (rc = upload(o, refpos, &d.refpos)) || (rc = upload(o, rotq, &d.rotq)) || (rc = upload(o, rotm, &d.rotm)) ||
+        (rc = upload(o, rotinfo, &d.rotinfo))) {
+        free_all(o);
+        delete T;
+        return rc;
+    }
+    *out = T;
+    return GFF_OK;
+}
+
+extern "C" void gff_topology_destroy(gff_topology *T) {
+    if (!T) return;
+    free_all(T->allocations);
+    delete T;
+}
+
+extern "C" gff_status gff_plan_create(const gff_topology *topo, int n_rep, const int *rep_type_h,
+                                      const gff_launch *launch, gff_plan **out) {
+    if (!topo || n_rep < 0 || (n_rep > 0 && !rep_type_h) || !out) return GFF_EINVAL;
+    int BT = 256, rpb_cap = 0, grid = 0;
+    if (launch) {
+        BT = launch->block_threads > 0 ? launch->block_threads : 256;
+        rpb_cap = launch->reps_per_block;
+        grid = launch->grid_blocks;
+    }
+    if (BT % 64 != 0 || BT < 64 || BT > 1024) return GFF_EINVAL;
+    std::vector<int> atom_off(n_rep + 1, 0);
+    int max_n = 0;
+    for (int r = 0; r < n_rep; ++r) {
+        const int t = rep_type_h[r];
+        if (t < 0 || t >= topo->n_types) return GFF_EINVAL;
+        atom_off[r + 1] = atom_off[r] + topo->natoms[t];
+        max_n = std::max(max_n, topo->natoms[t]);
+    }
+    if (max_n > BT) return GFF_EUNSUPPORTED;
+    // packs of same-type replicas, densest packing of one lane per atom
+    std::vector<std::vector<int>> by_type(topo->n_types);
+    for (int r = 0; r < n_rep; ++r) by_type[rep_type_h[r]].push_back(r);
+    std::vector<int> order(topo->n_types);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return topo->natoms[a] > topo->natoms[b]; });
+    std::vector<int4> packs;
+    std::vector<int> reps;
+    for (int t : order) {
+        const int n = topo->natoms[t];
+        int rpb = BT / n;
+        if (rpb_cap > 0) rpb = std::min(rpb, rpb_cap);
+        const auto &L = by_type[t];
+        for (size_t s = 0; s < L.size(); s += rpb) {
+            const int cnt = (int)std::min<size_t>(rpb, L.size() - s);
+            packs.push_back(make_int4(t, cnt, (int)reps.size(), 0));
+            for (int k = 0; k < cnt; ++k) reps.push_back(L[s + k]);
+        }
+    }
+    auto *P = new gff_plan_s();
+    P->n_rep = n_rep; P->n_atoms = atom_off[n_rep]; P->n_packs = (int)packs.size();
+    P->block_threads = BT; P->grid_blocks = grid; P->max_n = max_n;
+    P->atom_off_h = atom_off;
+    P->rep_type_h.assign(rep_type_h, rep_type_h + n_rep);
+    std::vector<void *> owned;
+    const int4 *dp; const int *dr, *da;
+    gff_status rc;
+    if ((rc = upload(owned, packs, &dp)) || (rc = upload(owned, reps, &dr)) || (rc = upload(owned, atom_off, &da))) {
+        free_all(owned);
+        delete P;
+        return rc;
+    }
+    P->d_packs = const_cast<int4 *>(dp);
+    P->d_pack_reps = const_cast<int *>(dr);
+    P->d_atom_off = const_cast<int *>(da);
+    *out = P;
+    return GFF_OK;
+}
+
+extern "C" void gff_plan_destroy(gff_plan *P) {
+    if (!P) return;
+    (void)hipFree(P->d_packs);
+    (void)hipFree(P->d_pack_reps);
+    (void)hipFree(P->d_atom_off);
+    delete P;
+}
+
+extern "C" int gff_plan_n_atoms(const gff_plan *P) { return P ? P->n_atoms : -1; }
+extern "C" int gff_plan_n_packs(const gff_plan *P) { return P ? P->n_packs : -1; }
+
+extern "C" gff_status gff_plan_atom_offsets(const gff_plan *P, int *atom_off_h) {
+    if (!P || !atom_off_h) return GFF_EINVAL;
+    std::memcpy(atom_off_h, P->atom_off_h.data(), sizeof(int) * P->atom_off_h.size());
+    return GFF_OK;
+}

@@ -1,0 +1,67 @@
+// Internal types of libgridff: device tables of molecule types and work lists.
+// Not part of the public ABI (see include/gridff.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <vector>
+#include <cstdint>
+#include "gridff.h"
+
+namespace gff {
+
+constexpr int kMaxAtoms = 128;             // atoms per molecule type (4 x 32-bit exclusion words)
+constexpr float kEvPerAmuA2Fs2 = 103.6426965268f;  // 1 amu A^2 / fs^2 in eV
+constexpr double kDefaultKe = 14.3996454784;
+
+struct TypeInfo {              // per molecule type
+    int n;                     // atoms
+    int abase;                 // first entry in the per-type-atom arrays
+    int pad0, pad1;
+};
+
+// One entry per (atom, incident term).  `slot` is the atom's position in the term; the
+// slot-0 entry carries the term's energy so every term is counted once.
+struct BondInc { int other; int slot; float k; float r0; };
+struct AngInc  { int a, b, c, slot; float k, cos0, pad0, pad1; };        // b = vertex
+struct TorInc  { int ijkl; int slot; int n; float V; float c0, s0, pad0, pad1; }; // ijkl: 4 bytes
+
+struct DevTopo {
+    const TypeInfo *types;
+    const float4 *plqm;        // [type atoms] P, L, Q, 1/(m * 103.6427)
+    const float *khalf;        // [type atoms] m * 103.6427 / 2
+    const uint4 *excl;         // [type atoms] bit j: pair excluded (self, 1-2, 1-3)
+    const int4 *incA;          // [type atoms] bond start, bond count, angle start, angle count
+    const int2 *incT;          // [type atoms] torsion start, torsion count
+    const BondInc *bnd;
+    const AngInc *ang;
+    const TorInc *tor;
+    const float4 *refpos;      // [type atoms] reference geometry (pose construction)
+    const int4 *rotq;          // [rotatable torsions of all types] quad
+    const uint4 *rotm;         // [same] 128-bit moving mask
+    const int2 *rotinfo;       // [types] first rotatable torsion, count
+};
+
+}  // namespace gff
+
+struct gff_topology_s {
+    int n_types;
+    float alpha, ke;
+    std::vector<int> natoms;
+    std::vector<int> nrot;
+    gff::DevTopo dev;
+    std::vector<void *> allocations;
+};
+
+struct gff_plan_s {
+    int n_rep, n_atoms, n_packs;
+    int block_threads, grid_blocks, max_n;
+    int4 *d_packs;             // type, replicas in pack, first entry in d_pack_reps, pad
+    int *d_pack_reps;          // replica ids in pack order
+    int *d_atom_off;           // [n_rep+1]
+    std::vector<int> atom_off_h;
+    std::vector<int> rep_type_h;
+};
+
+namespace gff {
+inline gff_status hip_status(hipError_t e) { return e == hipSuccess ? GFF_OK : GFF_EHIP; }
+}

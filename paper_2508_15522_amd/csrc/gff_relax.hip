@@ -1,0 +1,569 @@
+// GridFF replica kernels for gfx950: per-atom tricubic B-spline interpolation of the
+// Pauli/London/Coulomb grids mixed with the atom's (P, L, Q) (Section "Interpolation",
+// Eqs. Bspline1D/Bspline; Section "Principles", Eqs. E, E_Coulomb, E_Morse, V_Morse),
+// fused with the intramolecular field and a FIRE or velocity-Verlet step, with the whole
+// step loop inside one launch (Section "Configuration sampling on GPU").
+//
+// Mapping: a block holds a pack of same-type replicas, one lane per atom, replicas
+// packed densely (no lane rounding to powers of two).  Positions are exchanged through
+// LDS (double-buffered, so one barrier per step suffices for them); per-replica sums
+// (|F|^2, F.v, |v|^2, energies) are formed by every lane of the replica from LDS in the
+// same fixed order, so results are deterministic and identical on all lanes.
+#include "gff_internal.hpp"
+#include <cstring>
+#include <algorithm>
+
+namespace gff {
+
+enum { MODE_EVAL = 0, MODE_FIRE = 1, MODE_NVE = 2 };
+
+struct GridView {
+    const void *coef;
+    float x0, y0, z0, idx, idy, idz;
+    float dx, dy, dz, zmax;              // zmax = nz - 1
+    int nx, ny, nzp;                     // nzp = nz + 3 padded planes
+    float s0, s1, s2;                    // per-channel decode scales (filled on the device)
+    const float *scale;                  // F16: device scales [4]; NULL for F32
+};
+
+// Decode scales of an F16 grid are read on the device (no host round trip).
+__device__ __forceinline__ void fetch_scales(GridView &g) {
+    if (g.scale) { g.s0 = g.scale[0]; g.s1 = g.scale[1]; g.s2 = g.scale[2]; }
+}
+
+struct KArgs {
+    GridView g;
+    DevTopo t;
+    float alpha_l2e, alpha, ke;
+    const int4 *packs; const int *pack_reps; const int *atom_off;
+    int n_packs, N;
+    float *pos, *vel;
+    float *fdt, *falpha; int *fnpos; unsigned *status;
+    float *F; float *E_atom; double *E_rep; float *fnorm; int *steps; double *drift;
+    int n_steps, include_intra, drift_every, nmin;
+    float dt, f_conv, max_disp, finc, fdec, a0, falpha_f, dtmax;
+};
+
+__device__ __forceinline__ void lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Cubic B-spline weights of the four nodes i-1..i+2 for t in [0,1] and their t-derivatives
+// (B(t+1), B(t), B(1-t), B(2-t) of Eq. Bspline).
+__device__ __forceinline__ void bspline_weights(float t, float w[4], float d[4]) {
+    const float s = 1.f - t, t2 = t * t, s2 = s * s;
+    w[0] = s2 * s * (1.f / 6.f);
+    w[1] = 2.f / 3.f - t2 + 0.5f * t2 * t;
+    w[2] = 2.f / 3.f - s2 + 0.5f * s2 * s;
+    w[3] = t2 * t * (1.f / 6.f);
+    d[0] = -0.5f * s2;
+    d[1] = t * (1.5f * t - 2.f);
+    d[2] = s * (2.f - 1.5f * s);
+    d[3] = 0.5f * t2;
+}
+
+template <int STORE>
+__device__ __forceinline__ float4 load_node(const void *coef, int node) {
+    if constexpr (STORE == GFF_STORE_F32) {
+        return reinterpret_cast<const float4 *>(coef)[node];
+    } else {
+        uint2 h = reinterpret_cast<const uint2 *>(coef)[node];
+        __half2 a = *reinterpret_cast<__half2 *>(&h.x), b = *reinterpret_cast<__half2 *>(&h.y);
+        float2 fa = __half22float2(a), fb = __half22float2(b);
+        return make_float4(fa.x, fa.y, fb.x, fb.y);
+    }
+}
+
+// Cell index q and in-cell offset t in [0,1] of a coordinate r (relative to the grid origin)
+// on an axis with spacing h.  The remainder r - q h is formed with a single rounding (fma),
+// so t carries no error proportional to |r| / h (far lateral images stay accurate).
+__device__ __forceinline__ float cell_split(float r, float h, float ih, float &t) {
+    float q = floorf(r * ih);
+    float rem = fmaf(-q, h, r);
+    if (rem < 0.f) { q -= 1.f; rem += h; }
+    else if (rem >= h) { q += 1.f; rem -= h; }
+    t = rem * ih;
+    return q;
+}
+
+// Exact periodic wrap of an integer-valued cell index into [0, n).
+__device__ __forceinline__ int wrap_index(float q, int n) {
+    int i = (int)fminf(fmaxf(q, -1073741824.f), 1073741824.f);
+    if (i < 0 || i >= n) { i %= n; if (i < 0) i += n; }
+    return i;
+}
+
+// Grid energy E = P V^P + L V^L + Q V^C at (x,y,z) and its gradient.  Channels are
+// pre-mixed per node (linearity), then contracted along z (16 columns), y (4 rows), x.
+// Index arithmetic never leaves the grid: x,y wrap, z is clamped to the first plane
+// below (flag OUT_OF_DOMAIN), points above the last plane contribute zero, and
+// non-finite coordinates skip the gather and return NaN.
+template <int STORE>
+__device__ __forceinline__ float grid_eval(const GridView &g, float x, float y, float z,
+                                           float P, float L, float Q,
+                                           float &gx, float &gy, float &gz, unsigned &fl) {
+    gx = gy = gz = 0.f;
+    if (!(__builtin_isfinite(x) && __builtin_isfinite(y) && __builtin_isfinite(z))) {
+        fl |= GFF_REP_NONFINITE;
+        gx = gy = gz = __builtin_nanf("");
+        return __builtin_nanf("");
+    }
+    float tx, ty, tz;
+    const float qx = cell_split(x - g.x0, g.dx, g.idx, tx);
+    const float qy = cell_split(y - g.y0, g.dy, g.idy, ty);
+    float qz = cell_split(z - g.z0, g.dz, g.idz, tz);
+    if (qz < 0.f) { qz = 0.f; tz = 0.f; fl |= GFF_REP_OUT_OF_DOMAIN; }     // evaluated on z0
+    if (qz > g.zmax || (qz == g.zmax && tz > 0.f)) return 0.f;            // above the grid
+    float wx[4], dx[4], wy[4], dy[4], wz[4], dz[4];
+    bspline_weights(tx, wx, dx);
+    bspline_weights(ty, wy, dy);
+    bspline_weights(tz, wz, dz);
+    const int i = wrap_index(qx, g.nx), j = wrap_index(qy, g.ny), k = (int)qz;   // k in [0, nz-1]
+    int ix[4], jy[4];
+    ix[0] = (i == 0 ? g.nx : i) - 1; ix[1] = i;
+    ix[2] = (i + 1 == g.nx) ? 0 : i + 1; ix[3] = (i + 2 >= g.nx) ? i + 2 - g.nx : i + 2;
+    jy[0] = (j == 0 ? g.ny : j) - 1; jy[1] = j;
+    jy[2] = (j + 1 == g.ny) ? 0 : j + 1; jy[3] = (j + 2 >= g.ny) ? j + 2 - g.ny : j + 2;
+    const float Ps = P * g.s0, Ls = L * g.s1, Qs = Q * g.s2;
+    float E = 0.f, Ex = 0.f, Ey = 0.f, Ez = 0.f;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        float yv = 0.f, yy = 0.f, yz = 0.f;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int col = (ix[a] * g.ny + jy[b]) * g.nzp + k;   // padded plane k holds node k-1
+            float m[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const float4 q = load_node<STORE>(g.coef, col + c);
+                m[c] = Ps * q.x + Ls * q.y + Qs * q.z;
+            }
+            const float zv = wz[0] * m[0] + wz[1] * m[1] + wz[2] * m[2] + wz[3] * m[3];
+            const float zd = dz[0] * m[0] + dz[1] * m[1] + dz[2] * m[2] + dz[3] * m[3];
+            yv += wy[b] * zv; yy += dy[b] * zv; yz += wy[b] * zd;
+        }
+        E += wx[a] * yv; Ex += dx[a] * yv; Ey += wx[a] * yy; Ez += wx[a] * yz;
+    }
+    gx = Ex * g.idx; gy = Ey * g.idy; gz = Ez * g.idz;
+    return E;
+}
+
+__device__ __forceinline__ float3 f3(const float4 &p) { return make_float3(p.x, p.y, p.z); }
+__device__ __forceinline__ float3 operator-(float3 a, float3 b) { return make_float3(a.x - b.x, a.y - b.y, a.z - b.z); }
+__device__ __forceinline__ float3 operator+(float3 a, float3 b) { return make_float3(a.x + b.x, a.y + b.y, a.z + b.z); }
+__device__ __forceinline__ float3 operator*(float s, float3 a) { return make_float3(s * a.x, s * a.y, s * a.z); }
+__device__ __forceinline__ float dot(float3 a, float3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ float3 cross(float3 a, float3 b) {
+    return make_float3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+
+// Intramolecular force on this lane's atom and its energy share: pairs more than two
+// bonds apart (Morse with depth eps_i eps_j at R_i + R_j, factorised as
+// P_i P_j e^{-2 alpha r} - L_i L_j e^{-alpha r}/2, plus k_e Q_i Q_j / r; half the pair
+// energy to each atom), then the bonded terms incident to the atom (each term evaluated
+// by every participant for its own slot; the slot-0 participant carries the energy).
+__device__ __forceinline__ float intra_atom(const KArgs &A, const float4 *sp, int rbase, int n,
+                                            int abase, int at, float3 xi, float4 me, uint4 ex,
+                                            float3 &F) {
+    float e = 0.f;
+    float fx = 0.f, fy = 0.f, fz = 0.f;
+    const float4 *prm = A.t.plqm + abase;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        const int jb = w * 32;
+        if (jb >= n) break;
+        const unsigned m = w == 0 ? ex.x : (w == 1 ? ex.y : (w == 2 ? ex.z : ex.w));
+        const int je = min(n, jb + 32);
+        for (int j = jb; j < je; ++j) {
+            const float4 pj = sp[rbase + j];
+            const float4 qj = prm[j];
+            const float ddx = xi.x - pj.x, ddy = xi.y - pj.y, ddz = xi.z - pj.z;
+            const float r2 = ddx * ddx + ddy * ddy + ddz * ddz;
+            const bool skip = (m >> (j - jb)) & 1u;
+            const float rinv = __builtin_amdgcn_rsqf(skip ? 1.f : r2);
+            const float r = r2 * rinv;
+            const float u = __builtin_amdgcn_exp2f(-A.alpha_l2e * r);
+            const float PP = me.x * qj.x, LL = me.y * qj.y, QQ = A.ke * me.z * qj.z;
+            const float eu = PP * u * u, el = 0.5f * LL * u, ec = QQ * rinv;
+            const float epair = eu - el + ec;
+            const float dEdr = A.alpha * (el - 2.f * eu) - ec * rinv;
+            const float s = skip ? 0.f : -dEdr * rinv;
+            fx += s * ddx; fy += s * ddy; fz += s * ddz;
+            e += skip ? 0.f : 0.5f * epair;
+        }
+    }
+    const int4 ia = A.t.incA[abase + at];
+    for (int b = ia.x; b < ia.x + ia.y; ++b) {
+        const BondInc bi = A.t.bnd[b];
+        const float3 d = xi - f3(sp[rbase + bi.other]);
+        const float r = sqrtf(dot(d, d));
+        const float dr = r - bi.r0;
+        const float g = bi.k * dr / r;
+        fx -= g * d.x; fy -= g * d.y; fz -= g * d.z;
+        if (bi.slot == 0) e += 0.5f * bi.k * dr * dr;
+    }
+    for (int q = ia.z; q < ia.z + ia.w; ++q) {
+        const AngInc ai = A.t.ang[q];
+        const float3 pa = f3(sp[rbase + ai.a]), pb = f3(sp[rbase + ai.b]), pc = f3(sp[rbase + ai.c]);
+        const float3 u = pa - pb, v = pc - pb;
+        const float uu = dot(u, u), vv = dot(v, v);
+        const float inv = __builtin_amdgcn_rsqf(uu * vv);
+        const float cs = dot(u, v) * inv;
+        const float de = ai.k * (cs - ai.cos0);
+        const float3 ga = inv * v - (cs / uu) * u;
+        const float3 gc = inv * u - (cs / vv) * v;
+        float3 gs = ai.slot == 0 ? ga : (ai.slot == 2 ? gc : make_float3(-ga.x - gc.x, -ga.y - gc.y, -ga.z - gc.z));
+        fx -= de * gs.x; fy -= de * gs.y; fz -= de * gs.z;
+        if (ai.slot == 0) e += 0.5f * ai.k * (cs - ai.cos0) * (cs - ai.cos0);
+    }
+    const int2 it = A.t.incT[abase + at];
+    for (int q = it.x; q < it.x + it.y; ++q) {
+        const TorInc ti = A.t.tor[q];
+        const int i0 = ti.ijkl & 0xff, i1 = (ti.ijkl >> 8) & 0xff, i2 = (ti.ijkl >> 16) & 0xff, i3 = (ti.ijkl >> 24) & 0xff;
+        const float3 p0 = f3(sp[rbase + i0]), p1 = f3(sp[rbase + i1]), p2 = f3(sp[rbase + i2]), p3 = f3(sp[rbase + i3]);
+        const float3 b1 = p1 - p0, b2 = p2 - p1, b3 = p3 - p2;
+        const float3 mm = cross(b1, b2), nn = cross(b2, b3);
+        const float m2 = dot(mm, mm), n2 = dot(nn, nn), bb = dot(b2, b2);
+        if (m2 < 1e-12f || n2 < 1e-12f) continue;        // collinear: dihedral undefined
+        const float lb = sqrtf(bb);
+        const float inv = __builtin_amdgcn_rsqf(m2 * n2);
+        const float c1 = dot(mm, nn) * inv, s1 = lb * dot(b1, nn) * inv;  // cos phi, sin phi
+        float cn = c1, sn = s1;
+        for (int r = 1; r < ti.n; ++r) {                  // (cos n phi, sin n phi)
+            const float c2 = cn * c1 - sn * s1;
+            sn = sn * c1 + cn * s1; cn = c2;
+        }
+        const float carg = cn * ti.c0 + sn * ti.s0, sarg = sn * ti.c0 - cn * ti.s0;
+        const float dEdphi = 0.5f * ti.V * (float)ti.n * sarg;
+        const float3 gi = (-lb / m2) * mm, gl = (lb / n2) * nn;
+        const float p = dot(b1, b2) / bb, qq = dot(b3, b2) / bb;
+        float3 gs;
+        if (ti.slot == 0) gs = gi;
+        else if (ti.slot == 3) gs = gl;
+        else if (ti.slot == 1) gs = (-(1.f + p)) * gi + qq * gl;
+        else gs = p * gi + (-(1.f + qq)) * gl;
+        fx -= dEdphi * gs.x; fy -= dEdphi * gs.y; fz -= dEdphi * gs.z;
+        if (ti.slot == 0) e += 0.5f * ti.V * (1.f - carg);
+    }
+    F = make_float3(fx, fy, fz);
+    return e;
+}
+
+template <int STORE, int MODE>
+__global__ void __launch_bounds__(1024) k_replicas(KArgs A) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int BT = blockDim.x, tid = threadIdx.x;
+    // LDS: two position buffers, one reduction buffer used as float4 (FIRE sums) or double2
+    // (FP64 energy sums; flags at the end) -- never both between two barriers -- and a flag pair
+    float4 *s_pos0 = reinterpret_cast<float4 *>(smem);
+    float4 *s_pos1 = s_pos0 + BT;
+    float4 *s_red = s_pos1 + BT;
+    double2 *s_red64 = reinterpret_cast<double2 *>(s_red);
+    int *s_any = reinterpret_cast<int *>(s_red + BT);
+    const int N = A.N;
+    GridView gv = A.g;
+    fetch_scales(gv);
+
+    for (int pk = blockIdx.x; pk < A.n_packs; pk += gridDim.x) {
+        const int4 pinfo = A.packs[pk];
+        const TypeInfo ti = A.t.types[pinfo.x];
+        const int n = ti.n, nrep = pinfo.y, abase = ti.abase;
+        const int lr = tid / n, at = tid - lr * n;
+        const bool active = lr < nrep;
+        const int rbase = active ? lr * n : 0;
+        int rep = 0, g = 0;
+        float3 x = make_float3(0.f, 0.f, 0.f), v = make_float3(0.f, 0.f, 0.f);
+        float4 me = make_float4(0.f, 0.f, 0.f, 0.f);
+        uint4 ex = make_uint4(0u, 0u, 0u, 0u);
+        float khalf = 0.f;
+        float fdt = 0.f, fal = 0.f; int fnp = 0; unsigned st = GFF_REP_NONFINITE;
+        if (active) {
+            rep = A.pack_reps[pinfo.z + lr];
+            g = A.atom_off[rep] + at;
+            x = make_float3(A.pos[g], A.pos[g + N], A.pos[g + 2 * N]);
+            if (MODE != MODE_EVAL) v = make_float3(A.vel[g], A.vel[g + N], A.vel[g + 2 * N]);
+            me = A.t.plqm[abase + at];
+            ex = A.t.excl[abase + at];
+            khalf = A.t.khalf[abase + at];
+            st = MODE == MODE_EVAL ? 0u : A.status[rep];
+            if (MODE == MODE_FIRE) { fdt = A.fdt[rep]; fal = A.falpha[rep]; fnp = A.fnpos[rep]; }
+        }
+        if (tid == 0) { s_any[0] = 0; s_any[1] = 0; }
+        lds_sync();
+
+        unsigned fl = 0;                 // per-lane sticky flags (out of domain)
+        float3 F = make_float3(0.f, 0.f, 0.f);
+        float e_atom = 0.f, e_grid = 0.f, fnorm = 0.f;
+        int steps = 0;
+        const bool entered_conv = (st & GFF_REP_CONVERGED) != 0;
+        bool live = active && !(st & GFF_REP_NONFINITE);
+        double dr0 = 0, dr1 = 0, dr2 = 0, dr3 = 0, dr4 = 0, dr5 = 0;
+
+        // evaluation of the current positions: F, e_atom, e_grid
+        auto evaluate = [&](const float4 *sp) {
+            float gx, gy, gz;
+            e_grid = grid_eval<STORE>(gv, x.x, x.y, x.z, me.x, me.y, me.z, gx, gy, gz, fl);
+            F = make_float3(-gx, -gy, -gz);
+            e_atom = e_grid;
+            if (A.include_intra) {
+                float3 Fi;
+                e_atom += intra_atom(A, sp, rbase, n, abase, at, x, me, ex, Fi);
+                F = F + Fi;
+            }
+        };
+
+        const int total = (MODE == MODE_EVAL) ? 0 : A.n_steps;
+        for (int it = 0; it <= total; ++it) {
+            const int par = it & 1;
+            float4 *sp = par ? s_pos1 : s_pos0;
+            if (MODE == MODE_NVE && it > 0 && live) {       // velocity Verlet: half kick, drift
+                v = v + (0.5f * A.dt * me.w) * F;
+                x = x + A.dt * v;
+            }
+            if (live) s_any[par] = 1;
+            if (tid == 0) s_any[par ^ 1] = 0;
+            sp[tid] = make_float4(x.x, x.y, x.z, 0.f);
+            lds_sync();
+            if (s_any[par] == 0) break;                 // every replica of the pack is done
+            if (live) evaluate(sp);
+
+            if (MODE == MODE_EVAL) break;
+
+            if (MODE == MODE_FIRE) {
+                s_red[tid] = make_float4(dot(F, F), dot(F, v), dot(v, v), 0.f);
+                lds_sync();
+                if (live) {
+                    float ff = 0.f, fv = 0.f, vv = 0.f;
+                    for (int j = 0; j < n; ++j) {
+                        const float4 r = s_red[rbase + j];
+                        ff += r.x; fv += r.y; vv += r.z;
+                    }
+                    fnorm = sqrtf(ff);
+                    if (!__builtin_isfinite(ff) || !__builtin_isfinite(fv) || !__builtin_isfinite(vv)) {
+                        st |= GFF_REP_NONFINITE; live = false;
+                    } else if (entered_conv) {
+                        live = false;
+                    } else if (fnorm < A.f_conv) {
+                        st |= GFF_REP_CONVERGED; live = false;
+                    } else if (it < total) {
+                        float a = fal, dt = fdt;
+                        const float vn = sqrtf(vv);
+                        const float mix = a * vn / fnorm;
+                        v = (1.f - a) * v + mix * F;
+                        if (fv > 0.f) {
+                            fnp += 1;
+                            if (fnp > A.nmin) { dt = fminf(dt * A.finc, A.dtmax); a *= A.falpha_f; }
+                        } else {
+                            dt *= A.fdec; a = A.a0; fnp = 0;
+                            v = make_float3(0.f, 0.f, 0.f);
+                        }
+                        v = v + dt * F;
+                        float3 d = dt * v;
+                        const float l2 = dot(d, d);
+                        if (l2 > A.max_disp * A.max_disp) d = (A.max_disp * __builtin_amdgcn_rsqf(l2)) * d;
+                        x = x + d;
+                        fdt = dt; fal = a;
+                        steps++;
+                    } else {
+                        live = false;
+                    }
+                }
+            }
+
+            if (MODE == MODE_NVE) {
+                if (live && it > 0) v = v + (0.5f * A.dt * me.w) * F;
+                if (A.drift != nullptr && (it % A.drift_every) == 0) {
+                    const double ke = (double)khalf * ((double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z);
+                    s_red64[tid] = make_double2((double)e_atom, ke);
+                    lds_sync();
+                    if (live) {
+                        double ep = 0.0, kk = 0.0;
+                        for (int j = 0; j < n; ++j) {
+                            const double2 r = s_red64[rbase + j];
+                            ep += r.x; kk += r.y;
+                        }
+                        const double et = ep + kk;
+                        if (!__builtin_isfinite(et)) {
+                            st |= GFF_REP_NONFINITE; live = false;
+                        } else {
+                            if (it == 0) { dr0 = et; dr2 = 0; dr3 = 0; dr4 = 0; dr5 = 0; }
+                            const double de = et - dr0;
+                            dr1 = et;
+                            if (fabs(de) > dr2) dr2 = fabs(de);
+                            dr3 += de; dr4 += (double)it * de; dr5 += 1.0;
+                        }
+                    }
+                }
+                if (live && it > 0) steps++;
+            }
+        }
+
+        // ---- outputs: per-atom state, then per-replica sums (FP64) and flags
+        lds_sync();       // the last reduction's LDS reads precede these writes
+        s_red64[tid] = make_double2((double)e_atom, (double)fl);
+        lds_sync();
+        if (active) {
+            if (MODE != MODE_EVAL) {
+                A.pos[g] = x.x; A.pos[g + N] = x.y; A.pos[g + 2 * N] = x.z;
+                A.vel[g] = v.x; A.vel[g + N] = v.y; A.vel[g + 2 * N] = v.z;
+            }
+            if (MODE == MODE_EVAL) {
+                A.F[g] = F.x; A.F[g + N] = F.y; A.F[g + 2 * N] = F.z;
+                if (A.E_atom) A.E_atom[g] = e_grid;
+            }
+            if (at == 0) {
+                double es = 0.0; unsigned fo = 0u;
+                for (int j = 0; j < n; ++j) {
+                    const double2 r = s_red64[rbase + j];
+                    es += r.x;
+                    fo |= (unsigned)r.y;
+                }
+                st |= fo;
+                if (MODE == MODE_FIRE && A.f_conv > 0.f && !(st & (GFF_REP_CONVERGED | GFF_REP_NONFINITE)))
+                    st |= GFF_REP_MAXSTEPS;
+                if (st & GFF_REP_NONFINITE) { es = __builtin_nan(""); fnorm = __builtin_nanf(""); }
+                if (A.E_rep) A.E_rep[rep] = es;
+                if (A.status) A.status[rep] = st;
+                if (MODE != MODE_EVAL) {
+                    if (A.fnorm) A.fnorm[rep] = fnorm;
+                    if (A.steps) A.steps[rep] = steps;
+                }
+                if (MODE == MODE_FIRE) { A.fdt[rep] = fdt; A.falpha[rep] = fal; A.fnpos[rep] = fnp; }
+                if (MODE == MODE_NVE && A.drift) {
+                    double *d = A.drift + 6 * (size_t)rep;
+                    d[0] = dr0; d[1] = dr1; d[2] = dr2; d[3] = dr3; d[4] = dr4; d[5] = dr5;
+                }
+            }
+        }
+        lds_sync();       // LDS is reused by the next pack
+    }
+}
+
+// Atom-parallel interpolation of independent points (no molecules).
+template <int STORE>
+__global__ void __launch_bounds__(256) k_points(GridView g, int n, const float *pos, const float *plq,
+                                                float *F, float *E) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    fetch_scales(g);
+    unsigned fl = 0;
+    float gx, gy, gz;
+    const float e = grid_eval<STORE>(g, pos[p], pos[p + n], pos[p + 2 * n], plq[p], plq[p + n], plq[p + 2 * n],
+                                     gx, gy, gz, fl);
+    F[p] = -gx; F[p + n] = -gy; F[p + 2 * n] = -gz;
+    if (E) E[p] = e;
+}
+
+// ------------------------------------------------------------------ host side
+static gff_status make_view(const gff_grid *gr, GridView &g) {
+    if (!gr || !gr->d_coef) return GFF_EINVAL;
+    if (gr->storage != GFF_STORE_F32 && gr->storage != GFF_STORE_F16) return GFF_EUNSUPPORTED;
+    if (gr->nx < 4 || gr->ny < 4 || gr->nz < 4) return GFF_EINVAL;
+    if (!(gr->dx > 0.f && gr->dy > 0.f && gr->dz > 0.f)) return GFF_EINVAL;
+    if ((double)gr->nx * gr->ny * (gr->nz + 3) >= 2147483647.0) return GFF_EUNSUPPORTED;
+    g.coef = gr->d_coef;
+    g.x0 = gr->x0; g.y0 = gr->y0; g.z0 = gr->z0;
+    g.idx = 1.f / gr->dx; g.idy = 1.f / gr->dy; g.idz = 1.f / gr->dz;
+    g.dx = gr->dx; g.dy = gr->dy; g.dz = gr->dz;
+    g.zmax = (float)(gr->nz - 1);
+    g.nx = gr->nx; g.ny = gr->ny; g.nzp = gr->nz + 3;
+    g.s0 = g.s1 = g.s2 = 1.f;
+    g.scale = nullptr;
+    if (gr->storage == GFF_STORE_F16) {
+        if (!gr->d_scale) return GFF_EINVAL;
+        g.scale = gr->d_scale;
+    }
+    return GFF_OK;
+}
+
+static void fill_common(KArgs &A, const gff_topology *topo, const gff_plan *plan) {
+    A.t = topo->dev;
+    A.alpha = topo->alpha;
+    A.alpha_l2e = topo->alpha * 1.4426950408889634f;
+    A.ke = topo->ke;
+    A.packs = plan->d_packs; A.pack_reps = plan->d_pack_reps; A.atom_off = plan->d_atom_off;
+    A.n_packs = plan->n_packs; A.N = plan->n_atoms;
+}
+
+template <int MODE>
+static gff_status launch_mode(const gff_grid *gr, const gff_plan *plan, KArgs &A, hipStream_t s) {
+    const int BT = plan->block_threads;
+    const size_t lds = (size_t)BT * (16 + 16 + 16) + 16;
+    const int grid = plan->grid_blocks > 0 ? std::min(plan->grid_blocks, plan->n_packs) : plan->n_packs;
+    if (grid <= 0) return GFF_OK;
+    if (gr->storage == GFF_STORE_F32) {
+        hipLaunchKernelGGL((k_replicas<GFF_STORE_F32, MODE>), dim3(grid), dim3(BT), lds, s, A);
+    } else {
+        hipLaunchKernelGGL((k_replicas<GFF_STORE_F16, MODE>), dim3(grid), dim3(BT), lds, s, A);
+    }
+    return hip_status(hipGetLastError());
+}
+
+}  // namespace gff
+
+using namespace gff;
+
+extern "C" gff_status gff_eval_forces(const gff_grid *grid, const gff_topology *topo, const gff_plan *plan,
+                                      int include_intra, const float *d_pos, float *d_F, float *d_E_atom,
+                                      double *d_E_rep, unsigned *d_status, void *stream) {
+    if (!topo || !plan || !d_pos || !d_F) return GFF_EINVAL;
+    KArgs A;
+    std::memset(&A, 0, sizeof(A));
+    gff_status rc = make_view(grid, A.g);
+    if (rc != GFF_OK) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    fill_common(A, topo, plan);
+    A.pos = const_cast<float *>(d_pos);
+    A.F = d_F; A.E_atom = d_E_atom; A.E_rep = d_E_rep; A.status = d_status;
+    A.include_intra = include_intra;
+    return launch_mode<MODE_EVAL>(grid, plan, A, s);
+}
+
+extern "C" gff_status gff_relax_batch(const gff_grid *grid, const gff_topology *topo, const gff_plan *plan,
+                                      const gff_relax_params *p, const gff_state *state,
+                                      double *d_E_rep, float *d_fnorm_rep, int *d_steps_rep,
+                                      double *d_drift_rep, void *stream) {
+    if (!topo || !plan || !p || !state || !state->d_pos || !state->d_vel || !state->d_status) return GFF_EINVAL;
+    if (p->n_steps < 0) return GFF_EINVAL;
+    if (p->mode != GFF_MODE_FIRE && p->mode != GFF_MODE_NVE) return GFF_EINVAL;
+    if (p->mode == GFF_MODE_FIRE && (!state->d_fire_dt || !state->d_fire_alpha || !state->d_fire_npos))
+        return GFF_EINVAL;
+    if (p->mode == GFF_MODE_NVE && d_drift_rep && p->drift_every < 1) return GFF_EINVAL;
+    KArgs A;
+    std::memset(&A, 0, sizeof(A));
+    gff_status rc = make_view(grid, A.g);
+    if (rc != GFF_OK) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    fill_common(A, topo, plan);
+    A.pos = state->d_pos; A.vel = state->d_vel;
+    A.fdt = state->d_fire_dt; A.falpha = state->d_fire_alpha; A.fnpos = state->d_fire_npos;
+    A.status = state->d_status;
+    A.E_rep = d_E_rep; A.fnorm = d_fnorm_rep; A.steps = d_steps_rep;
+    A.drift = p->mode == GFF_MODE_NVE ? d_drift_rep : nullptr;
+    A.n_steps = p->n_steps; A.include_intra = p->include_intra;
+    A.drift_every = p->drift_every < 1 ? 1 : p->drift_every;
+    A.nmin = p->fire_nmin;
+    A.dt = p->dt; A.f_conv = p->f_conv; A.max_disp = p->max_disp;
+    A.finc = p->fire_finc; A.fdec = p->fire_fdec; A.a0 = p->fire_alpha0; A.falpha_f = p->fire_falpha;
+    A.dtmax = p->fire_dtmax;
+    if (p->mode == GFF_MODE_FIRE) return launch_mode<MODE_FIRE>(grid, plan, A, s);
+    return launch_mode<MODE_NVE>(grid, plan, A, s);
+}
+
+extern "C" gff_status gff_interp_points(const gff_grid *grid, int n, const float *d_pos, const float *d_plq,
+                                        float *d_F, float *d_E, void *stream) {
+    if (n < 0 || (n > 0 && (!d_pos || !d_plq || !d_F))) return GFF_EINVAL;
+    GridView g;
+    gff_status rc = make_view(grid, g);
+    if (rc != GFF_OK) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    if (n == 0) return GFF_OK;
+    const int blocks = (n + 255) / 256;
+    if (grid->storage == GFF_STORE_F32)
+        hipLaunchKernelGGL(k_points<GFF_STORE_F32>, dim3(blocks), dim3(256), 0, s, g, n, d_pos, d_plq, d_F, d_E);
+    else
+        hipLaunchKernelGGL(k_points<GFF_STORE_F16>, dim3(blocks), dim3(256), 0, s, g, n, d_pos, d_plq, d_F, d_E);
+    return hip_status(hipGetLastError());
+}

@@ -1,0 +1,251 @@
+"""ctypes binding of libgridff (include/gridff.h): argument marshalling only.
+
+Every step of the path runs in the library's HIP kernels; torch is used for device
+memory and streams.  The functions keep the C names without the ``gff_`` prefix.
+Loading fails loudly if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgridff.so")
+
+STORE_F32, STORE_F16 = 0, 1
+MODE_FIRE, MODE_NVE = 0, 1
+REP_CONVERGED, REP_OUT_OF_DOMAIN, REP_NONFINITE, REP_MAXSTEPS = 1, 2, 4, 8
+
+
+class GffError(RuntimeError):
+    pass
+
+
+class Substrate(C.Structure):
+    _fields_ = [("n_atoms", C.c_int), ("pos_h", C.c_void_p), ("q_h", C.c_void_p), ("eps_h", C.c_void_p),
+                ("R_h", C.c_void_p), ("Lx", C.c_double), ("Ly", C.c_double)]
+
+
+class GridSpec(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("x0", C.c_double), ("y0", C.c_double),
+                ("z0", C.c_double), ("dz", C.c_double), ("alpha", C.c_double), ("rcut", C.c_double),
+                ("k_e", C.c_double)]
+
+
+class Grid(C.Structure):
+    _fields_ = [("storage", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
+                ("x0", C.c_float), ("y0", C.c_float), ("z0", C.c_float),
+                ("dx", C.c_float), ("dy", C.c_float), ("dz", C.c_float),
+                ("d_coef", C.c_void_p), ("d_scale", C.c_void_p)]
+
+
+class MolType(C.Structure):
+    _fields_ = [("n_atoms", C.c_int), ("eps", C.c_void_p), ("R", C.c_void_p), ("q", C.c_void_p),
+                ("mass", C.c_void_p),
+                ("n_bonds", C.c_int), ("bonds", C.c_void_p), ("bond_k", C.c_void_p), ("bond_r0", C.c_void_p),
+                ("n_angles", C.c_int), ("angles", C.c_void_p), ("angle_k", C.c_void_p), ("angle_cos0", C.c_void_p),
+                ("n_tors", C.c_int), ("tors", C.c_void_p), ("tors_V", C.c_void_p), ("tors_n", C.c_void_p),
+                ("tors_phi0", C.c_void_p),
+                ("n_rot", C.c_int), ("rot_quads", C.c_void_p), ("rot_mask", C.c_void_p),
+                ("ref_pos", C.c_void_p)]
+
+
+class Launch(C.Structure):
+    _fields_ = [("block_threads", C.c_int), ("reps_per_block", C.c_int), ("grid_blocks", C.c_int)]
+
+
+class RelaxParams(C.Structure):
+    _fields_ = [("mode", C.c_int), ("n_steps", C.c_int), ("include_intra", C.c_int), ("dt", C.c_float),
+                ("f_conv", C.c_float), ("max_disp", C.c_float), ("fire_finc", C.c_float),
+                ("fire_fdec", C.c_float), ("fire_alpha0", C.c_float), ("fire_falpha", C.c_float),
+                ("fire_dtmax", C.c_float), ("fire_nmin", C.c_int), ("drift_every", C.c_int)]
+
+
+class State(C.Structure):
+    _fields_ = [("d_pos", C.c_void_p), ("d_vel", C.c_void_p), ("d_fire_dt", C.c_void_p),
+                ("d_fire_alpha", C.c_void_p), ("d_fire_npos", C.c_void_p), ("d_status", C.c_void_p)]
+
+
+EXPORTS = [
+    "gff_status_string", "gff_build_grid_workspace_bytes", "gff_build_grid", "gff_fit_workspace_bytes",
+    "gff_fit_bspline", "gff_grid_bytes", "gff_pack_grid", "gff_topology_create", "gff_topology_destroy",
+    "gff_plan_create", "gff_plan_destroy", "gff_plan_n_atoms", "gff_plan_n_packs", "gff_plan_atom_offsets",
+    "gff_eval_forces", "gff_interp_points", "gff_relax_batch",
+]
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise GffError(f"{LIB_PATH} is missing: build it with paper_2508_15522_amd.build.build()")
+        L = C.CDLL(LIB_PATH)
+        L.gff_status_string.restype = C.c_char_p
+        for n in ("gff_build_grid_workspace_bytes", "gff_fit_workspace_bytes", "gff_grid_bytes"):
+            getattr(L, n).restype = C.c_size_t
+        for n in ("gff_build_grid", "gff_fit_bspline", "gff_pack_grid", "gff_topology_create", "gff_plan_create",
+                  "gff_plan_atom_offsets", "gff_eval_forces", "gff_interp_points", "gff_relax_batch",
+                  "gff_plan_n_atoms", "gff_plan_n_packs"):
+            getattr(L, n).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def check(rc):
+    if rc != 0:
+        raise GffError(f"libgridff: {lib().gff_status_string(rc).decode()} ({rc})")
+
+
+def _ptr(t):
+    """Device pointer of a torch tensor (or None)."""
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+# ------------------------------------------------------------------ grid build / fit / pack
+class _Keep:
+    def __init__(self):
+        self.arrays = []
+
+    def np(self, a, dtype):
+        a = np.ascontiguousarray(a, dtype=dtype)
+        self.arrays.append(a)
+        return a.ctypes.data_as(C.c_void_p)
+
+
+def grid_spec(nx, ny, nz, x0, y0, z0, dz, alpha=1.6, rcut=17.0, k_e=0.0):
+    return GridSpec(nx, ny, nz, x0, y0, z0, dz, alpha, rcut, k_e)
+
+
+def substrate(sub, keep):
+    return Substrate(sub.n, keep.np(sub.pos, np.float64), keep.np(sub.q, np.float64),
+                     keep.np(sub.eps, np.float64), keep.np(sub.R, np.float64), sub.Lx, sub.Ly)
+
+
+def build_grid_workspace_bytes(spec, sub):
+    keep = _Keep()
+    s = substrate(sub, keep)
+    return lib().gff_build_grid_workspace_bytes(C.byref(spec), C.byref(s))
+
+
+def build_grid(sub, spec, d_V, d_work, stream=None):
+    keep = _Keep()
+    s = substrate(sub, keep)
+    check(lib().gff_build_grid(C.byref(s), C.byref(spec), _ptr(d_V), _ptr(d_work),
+                               C.c_size_t(d_work.numel() * d_work.element_size()), _stream(stream)))
+
+
+def fit_workspace_bytes(spec):
+    return lib().gff_fit_workspace_bytes(C.byref(spec))
+
+
+def fit_bspline(spec, d_V, d_B, d_work, stream=None):
+    check(lib().gff_fit_bspline(C.byref(spec), _ptr(d_V), _ptr(d_B), _ptr(d_work),
+                                C.c_size_t(d_work.numel() * d_work.element_size()), _stream(stream)))
+
+
+def grid_bytes(spec, storage):
+    return lib().gff_grid_bytes(C.byref(spec), C.c_int(storage))
+
+
+def pack_grid(spec, d_B, storage, d_coef, d_scale, stream=None):
+    check(lib().gff_pack_grid(C.byref(spec), _ptr(d_B), C.c_int(storage), _ptr(d_coef), _ptr(d_scale),
+                              _stream(stream)))
+
+
+def grid(spec, storage, d_coef, d_scale, Lx, Ly):
+    """gff_grid descriptor for a packed grid of `spec` (lateral spacing Lx/nx, Ly/ny)."""
+    return Grid(storage, spec.nx, spec.ny, spec.nz, spec.x0, spec.y0, spec.z0, Lx / spec.nx, Ly / spec.ny,
+                spec.dz, d_coef.data_ptr(), None if d_scale is None else d_scale.data_ptr())
+
+
+# ------------------------------------------------------------------ topology / plan
+class Topology:
+    def __init__(self, mols, alpha=1.6, k_e=0.0):
+        self.keep = _Keep()
+        arr = (MolType * len(mols))()
+        for t, m in enumerate(mols):
+            k = self.keep
+            nrot = len(m.rot_quads)
+            arr[t] = MolType(
+                m.n, k.np(m.eps, np.float32), k.np(m.R, np.float32), k.np(m.q, np.float32), k.np(m.mass, np.float32),
+                len(m.bonds), k.np(m.bonds.reshape(-1, 2), np.int32), k.np(m.bond_k, np.float32),
+                k.np(m.bond_r0, np.float32),
+                len(m.angles), k.np(m.angles.reshape(-1, 3), np.int32), k.np(m.angle_k, np.float32),
+                k.np(m.angle_cos0, np.float32),
+                len(m.tors), k.np(m.tors.reshape(-1, 4), np.int32), k.np(m.tors_V, np.float32),
+                k.np(m.tors_n, np.int32), k.np(m.tors_phi0, np.float32),
+                nrot, k.np(m.rot_quads.reshape(-1, 4) if nrot else np.zeros((1, 4)), np.int32),
+                k.np(m.rot_masks.reshape(nrot, m.n) if nrot else np.zeros((1, m.n)), np.uint8),
+                k.np(m.pos, np.float32))
+        self.handle = C.c_void_p()
+        check(lib().gff_topology_create(arr, C.c_int(len(mols)), C.c_float(alpha), C.c_float(k_e),
+                                        C.byref(self.handle)))
+        self.mols = mols
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.gff_topology_destroy(self.handle)
+            self.handle = None
+
+
+class Plan:
+    def __init__(self, topo: Topology, rep_type, block_threads=256, reps_per_block=0, grid_blocks=0):
+        rt = np.ascontiguousarray(rep_type, dtype=np.int32)
+        self.n_rep = len(rt)
+        self.handle = C.c_void_p()
+        self.launch = Launch(block_threads, reps_per_block, grid_blocks)
+        check(lib().gff_plan_create(topo.handle, C.c_int(self.n_rep), rt.ctypes.data_as(C.c_void_p),
+                                    C.byref(self.launch), C.byref(self.handle)))
+        self.n_atoms = lib().gff_plan_n_atoms(self.handle)
+        self.n_packs = lib().gff_plan_n_packs(self.handle)
+        off = np.zeros(self.n_rep + 1, np.int32)
+        check(lib().gff_plan_atom_offsets(self.handle, off.ctypes.data_as(C.c_void_p)))
+        self.atom_off = off
+        self.rep_type = rt
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.gff_plan_destroy(self.handle)
+            self.handle = None
+
+
+# ------------------------------------------------------------------ evaluation / relaxation
+def eval_forces(grid_desc, topo, plan, include_intra, d_pos, d_F, d_E_atom=None, d_E_rep=None, d_status=None,
+                stream=None):
+    check(lib().gff_eval_forces(C.byref(grid_desc), topo.handle, plan.handle, C.c_int(int(include_intra)),
+                                _ptr(d_pos), _ptr(d_F), _ptr(d_E_atom), _ptr(d_E_rep), _ptr(d_status),
+                                _stream(stream)))
+
+
+def interp_points(grid_desc, d_pos, d_plq, d_F, d_E=None, stream=None):
+    n = d_pos.shape[-1]
+    check(lib().gff_interp_points(C.byref(grid_desc), C.c_int(n), _ptr(d_pos), _ptr(d_plq), _ptr(d_F), _ptr(d_E),
+                                  _stream(stream)))
+
+
+def relax_params(mode=MODE_FIRE, n_steps=1000, include_intra=True, dt=0.5, f_conv=1e-4, max_disp=0.1,
+                 finc=1.1, fdec=0.5, alpha0=0.1, falpha=0.99, dtmax=0.1, nmin=5, drift_every=1):
+    return RelaxParams(mode, n_steps, int(include_intra), dt, f_conv, max_disp, finc, fdec, alpha0, falpha,
+                       dtmax, nmin, drift_every)
+
+
+def relax_batch(grid_desc, topo, plan, params, st, d_E_rep, d_fnorm, d_steps, d_drift=None, stream=None):
+    """st: dict of torch tensors pos, vel, fire_dt, fire_alpha, fire_npos, status."""
+    state = State(st["pos"].data_ptr(), st["vel"].data_ptr(),
+                  st["fire_dt"].data_ptr() if "fire_dt" in st else None,
+                  st["fire_alpha"].data_ptr() if "fire_alpha" in st else None,
+                  st["fire_npos"].data_ptr() if "fire_npos" in st else None,
+                  st["status"].data_ptr())
+    check(lib().gff_relax_batch(C.byref(grid_desc), topo.handle, plan.handle, C.byref(params), C.byref(state),
+                                _ptr(d_E_rep), _ptr(d_fnorm), _ptr(d_steps), _ptr(d_drift), _stream(stream)))

@@ -1,0 +1,193 @@
+"""GPU parity of the evaluation path (a1-a5) against the FP64 oracle.
+
+Tolerances.  The kernels interpolate in FP32 with FP32 accumulation; the oracle
+evaluates the same model in FP64 on the same FP32 inputs.  The required bound on the
+force error is 1e-4 eV/A for FP32 grids and 1e-3 eV/A for FP16 grids (per atom,
+Euclidean norm).  Energies are compared with 2e-5 eV per atom (about 64 terms of
+size |P b| ~ 0.05 eV at 2^-24 relative rounding, plus the FP32 rounding of the
+fractional coordinate).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2508_15522_amd import configs, device as D, gridff as G, synth as S
+from tests.gpu_common import COEF_SCALE, announce, mixing_for
+
+pytestmark = pytest.mark.gpu
+
+NX, NY, NZ = configs.GRID_SMALL.nx, configs.GRID_SMALL.ny, configs.GRID_SMALL.nz
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    D.require_gpu()
+
+
+def _spec(nx=NX, ny=NY, nz=NZ, z0=1.0, dz=0.1):
+    return G.grid_spec(nx, ny, nz, 0.0, 0.0, z0, dz)
+
+
+def _points(n, Lx, Ly, zlo, zhi, seed, span=3.0):
+    return S.random_points(n, Lx, Ly, zlo, zhi, seed, lateral_span=span)
+
+
+def _run_points(grid, pts, plq):
+    dpos = torch.from_numpy(np.ascontiguousarray(pts.T, np.float32)).cuda()
+    dplq = torch.from_numpy(np.ascontiguousarray(plq.T, np.float32)).cuda()
+    F = torch.empty_like(dpos)
+    E = torch.empty(len(pts), dtype=torch.float32, device="cuda")
+    G.interp_points(grid.desc, dpos, dplq, F, E)
+    torch.cuda.synchronize()
+    return E.cpu().numpy().astype(np.float64), F.cpu().numpy().T.astype(np.float64)
+
+
+def _random_plq(n, seed):
+    rng = np.random.default_rng(seed)
+    types = ["C", "O", "H"]
+    el = rng.choice(types, n)
+    eps = np.array([S.MORSE_EPS[e] for e in el]); R = np.array([S.MORSE_R[e] for e in el])
+    q = S.f32(rng.normal(0, 0.3, n))
+    plq = S.f32(O.mixing(eps, R, q))
+    return plq
+
+
+@pytest.mark.parametrize("storage", [G.STORE_F32, G.STORE_F16])
+def test_interp_points_full_grid_random_coefficients(storage):
+    """112 x 112 x 150 grid (the small substrate's size), 200 003 points spread over three
+    lateral periods and the whole height range (ragged tail, wrap in x and y)."""
+    announce(f"interp_points full grid storage={storage}")
+    Lx = Ly = 2 * S.SLAB_A
+    spec = _spec()
+    B = S.random_coefficients(NX, NY, NZ, 11, COEF_SCALE)
+    grid = D.pack_from_coefficients(B, spec, storage, Lx, Ly)
+    geo = grid.geometry
+    n = 200_003
+    pts = _points(n, Lx, Ly, geo["z0"], geo["z0"] + (NZ - 1) * geo["dz"] - 1e-4, 5)
+    plq = _random_plq(n, 6)
+    E, F = _run_points(grid, pts, plq)
+    if storage == G.STORE_F16:
+        Bq, s = O.fp16_quantize(B)
+        # the scales are exact powers of two and match the rule s_c = 2^(ceil(log2 max|b_c|) - 15)
+        assert np.array_equal(grid.scale.cpu().numpy()[:3].astype(np.float64), s)
+        Bref = Bq
+    else:
+        Bref = S.f32(B)
+    Eo, Fo, fl = O.bspline_eval(Bref, geo, pts, plq)
+    assert (fl == 0).all()
+    dF = np.linalg.norm(F - Fo, axis=1)
+    announce(f"  max |dF| = {dF.max():.3e}, max |dE| = {np.abs(E - Eo).max():.3e}, max|F| = {np.abs(Fo).max():.3e}")
+    assert dF.max() < 1e-4
+    assert np.abs(E - Eo).max() < 2e-5
+    if storage == G.STORE_F16:
+        # the FP16 storage error itself against the unquantised model stays within 1e-3 eV/A
+        _, Fu, _ = O.bspline_eval(S.f32(B), geo, pts, plq)
+        assert np.linalg.norm(F - Fu, axis=1).max() < 1e-3
+
+
+def test_pack_layout_f32_and_f16_bitexact():
+    """The storage cast is exact: F32 is the rounded coefficient, F16 the RNE half of
+    b / s_c; plane p holds node p-1 with even-mirror padding (R9)."""
+    announce("pack layout")
+    nx, ny, nz = 9, 7, 11
+    spec = _spec(nx, ny, nz)
+    B = S.random_coefficients(nx, ny, nz, 3, (1.0, 3e-3, 70.0))
+    B[0, 0, 0, 0] = 0.0
+    kk = np.arange(-1, nz + 2)
+    kk = np.where(kk < 0, -kk, kk)
+    kk = np.where(kk > nz - 1, 2 * (nz - 1) - kk, kk)
+    g32 = D.pack_from_coefficients(B, spec, G.STORE_F32, 1.0, 1.0)
+    c32 = g32.coef.cpu().numpy().view(np.float32).reshape(nx, ny, nz + 3, 4)
+    for c in range(3):
+        assert np.array_equal(c32[..., c], B[c][:, :, kk].astype(np.float32))
+    assert (c32[..., 3] == 0).all()
+    g16 = D.pack_from_coefficients(B, spec, G.STORE_F16, 1.0, 1.0)
+    c16 = g16.coef.cpu().numpy().view(np.uint16).reshape(nx, ny, nz + 3, 4)
+    _, s = O.fp16_quantize(B)
+    for c in range(3):
+        ref = (B[c][:, :, kk] / s[c]).astype(np.float16).view(np.uint16)
+        assert np.array_equal(c16[..., c], ref)
+
+
+def test_interp_domain_edges_and_nonfinite():
+    announce("domain edges")
+    Lx = Ly = 2 * S.SLAB_A
+    spec = _spec(28, 28, 20, z0=1.0, dz=0.25)
+    B = S.random_coefficients(28, 28, 20, 4, COEF_SCALE)
+    grid = D.pack_from_coefficients(B, spec, G.STORE_F32, Lx, Ly)
+    geo = grid.geometry
+    ztop = geo["z0"] + 19 * geo["dz"]
+    pts = np.array([[1.0, 2.0, 0.2],            # below z0: evaluated on z0
+                    [1.0, 2.0, geo["z0"]],     # on the first plane
+                    [1.0, 2.0, ztop],          # on the last plane
+                    [1.0, 2.0, ztop + 0.01],   # above: zero
+                    [-1e4, 3e4, 2.0],          # far lateral images (exact remainder keeps t accurate)
+                    [0.0, 0.0, 2.0],           # exactly on a node
+                    [Lx, Ly, 2.0],             # the same node one period away
+                    [np.nan, 1.0, 2.0],
+                    [1.0, np.inf, 2.0]])
+    plq = np.tile([30.0, -3.0, 0.5], (len(pts), 1))
+    E, F = _run_points(grid, pts, plq)
+    Eo, Fo, fl = O.bspline_eval(S.f32(B), geo, pts, plq)
+    for i in range(7):
+        assert abs(E[i] - Eo[i]) < 2e-5 and np.abs(F[i] - Fo[i]).max() < 1e-4, i
+    assert E[3] == 0 and (F[3] == 0).all()
+    # one lateral period away: the model period is nx*dx with the FP32 dx, which differs from
+    # the FP32 value of Lx by rounding, so the two agree to rounding, not bit for bit
+    assert abs(E[5] - E[6]) < 1e-6 and np.abs(F[5] - F[6]).max() < 1e-5
+    assert np.isnan(E[7]) and np.isnan(E[8])
+    # empty launch is a no-op
+    z = torch.empty(3, 0, device="cuda")
+    G.interp_points(grid.desc, z, z, z, None)
+
+
+def _batch(mols, rep_type, seed, h=(2.5, 4.5), Lx=2 * S.SLAB_A):
+    sub = S.rocksalt_slab(2, 3)
+    pos = []
+    for r, t in enumerate(rep_type):
+        pos.append(S.place_replicas(mols[t], 1, sub, seed + r, h)[0])
+    return pos
+
+
+@pytest.mark.parametrize("block", [128, 256, 1024])
+def test_eval_forces_batch_with_intra(block):
+    """Grid + intramolecular energies and forces of a mixed batch (all eight size-series
+    types plus the chain and the planar molecule), compared atom by atom."""
+    announce(f"eval_forces block={block}")
+    mols = S.molecule_types("sizes") + [S.mol_chain24(), S.mol_pah38()]
+    rng = np.random.default_rng(1)
+    rep_type = rng.integers(0, len(mols), 61)
+    Lx = Ly = 2 * S.SLAB_A
+    spec = _spec()
+    B = S.random_coefficients(NX, NY, NZ, 12, COEF_SCALE)
+    grid = D.pack_from_coefficients(B, spec, G.STORE_F32, Lx, Ly)
+    topo = G.Topology(mols)
+    plan = G.Plan(topo, rep_type, block_threads=block)
+    pos = _batch(mols, rep_type, 77)
+    dpos = D.soa(plan, pos)
+    F = torch.empty_like(dpos)
+    Ea = torch.empty(plan.n_atoms, device="cuda")
+    Er = torch.empty(plan.n_rep, dtype=torch.float64, device="cuda")
+    st = torch.empty(plan.n_rep, dtype=torch.int32, device="cuda")
+    G.eval_forces(grid.desc, topo, plan, True, dpos, F, Ea, Er, st)
+    torch.cuda.synchronize()
+    Fo, Ero, Eao, sto = O.eval_batch(S.f32(B), grid.geometry, mols, rep_type, np.concatenate(pos))
+    Fg = F.cpu().numpy().T.astype(np.float64)
+    dF = np.linalg.norm(Fg - Fo, axis=1)
+    announce(f"  max |dF| = {dF.max():.3e} (max |F| {np.abs(Fo).max():.2f}); max |dE_rep| = "
+             f"{np.abs(Er.cpu().numpy() - Ero).max():.3e}")
+    assert dF.max() < 1e-4 * max(1.0, np.abs(Fo).max() / 10)
+    assert np.abs(Ea.cpu().numpy() - Eao).max() < 2e-5
+    nat = np.array([mols[t].n for t in rep_type])
+    assert (np.abs(Er.cpu().numpy() - Ero) < 2e-5 * nat + 1e-5 * np.abs(Ero)).all()
+    assert np.array_equal(st.cpu().numpy(), sto)
+    # grid-only evaluation equals the atom-parallel interpolation bit for bit
+    F0 = torch.empty_like(dpos)
+    G.eval_forces(grid.desc, topo, plan, False, dpos, F0, None, None, None)
+    plq = torch.from_numpy(np.ascontiguousarray(mixing_for(mols, rep_type).T, np.float32)).cuda()
+    F1 = torch.empty_like(dpos)
+    G.interp_points(grid.desc, dpos, plq, F1, None)
+    torch.cuda.synchronize()
+    # same device function; the mixing coefficients differ only by FP32 rounding of alpha
+    assert (F0 - F1).abs().max().item() < 1e-5
