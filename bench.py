@@ -104,9 +104,9 @@ def main():
         return wall, per, states[-1]
 
     if args.copy_probe:
-        src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")     # 1 GiB read, 1 GiB written
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
     log(f"warmup {args.warmup}, timing {args.steps} launches of {args.md_steps} MD steps x {n_rep} replicas")

@@ -21,14 +21,14 @@ constexpr double kTwoPi = 6.283185307179586476925286766559;
 
 // ------------------------------------------------------------------ Morse channels
 struct MorseArgs {
-    const double *sp;      // [n][5]: x, y, z, eps, R
+    const double *sp;      // [n][6]: x, y, z, eps, R, Q
     int nsub, nx, ny, nz, KX, KY;
     double x0, y0, z0, dx, dy, dz, Lx, Ly, alpha, rcut2;
     double *V;             // [3][nx][ny][nz]
 };
 
 __global__ void __launch_bounds__(256) k_morse(MorseArgs a) {
-    __shared__ double s[256 * 5];
+    __shared__ double s[256 * 6];
     const long node = (long)blockIdx.x * blockDim.x + threadIdx.x;
     const long total = (long)a.nx * a.ny * a.nz;
     const bool ok = node < total;
@@ -40,10 +40,10 @@ __global__ void __launch_bounds__(256) k_morse(MorseArgs a) {
     for (int base = 0; base < a.nsub; base += 256) {
         const int cnt = min(256, a.nsub - base);
         __syncthreads();
-        for (int q = threadIdx.x; q < cnt * 5; q += blockDim.x) s[q] = a.sp[(size_t)base * 5 + q];
+        for (int q = threadIdx.x; q < cnt * 6; q += blockDim.x) s[q] = a.sp[(size_t)base * 6 + q];
         __syncthreads();
         for (int q = 0; q < cnt; ++q) {
-            const double *p = s + 5 * q;
+            const double *p = s + 6 * q;
             double ddx = x - p[0], ddy = y - p[1];
             ddx -= a.Lx * rint(ddx / a.Lx);              // minimum image, then neighbours
             ddy -= a.Ly * rint(ddy / a.Ly);
@@ -71,7 +71,7 @@ __global__ void __launch_bounds__(256) k_morse(MorseArgs a) {
 
 // ------------------------------------------------------------------ Coulomb channel
 struct StructArgs {
-    const double *sp;        // [n][5]
+    const double *sp;        // [n][6]: x, y, z, eps, R, Q
     int nsub, MX, MY;
     double Lx, Ly, gmax, ztop, x0, y0;
     double2 *S;              // [(2MX+1)(2MY+1)], index (m+MX)*(2MY+1) + (n+MY)
@@ -87,8 +87,8 @@ __global__ void __launch_bounds__(256) k_structure(StructArgs a) {
     double re = 0.0, im = 0.0;
     if ((m != 0 || n != 0) && G <= a.gmax) {
         for (int j = 0; j < a.nsub; ++j) {
-            const double *p = a.sp + 5 * (size_t)j;
-            const double q = p[3];
+            const double *p = a.sp + 6 * (size_t)j;
+            const double q = p[5];
             if (q == 0.0) continue;
             const double damp = q * exp(-G * (a.ztop - p[2]));
             double sn, cs;
@@ -301,7 +301,7 @@ using namespace gff;
 extern "C" size_t gff_build_grid_workspace_bytes(const gff_grid_spec *spec, const gff_substrate *sub) {
     if (!spec_ok(spec) || !sub || sub->n_atoms < 1 || !sub->pos_h) return 0;
     CoulombPlan p = coulomb_plan(spec, sub);
-    return align256((size_t)sub->n_atoms * 5 * sizeof(double)) + align256(p.S_elems * sizeof(double2)) +
+    return align256((size_t)sub->n_atoms * 6 * sizeof(double)) + align256(p.S_elems * sizeof(double2)) +
            2 * align256(p.C_elems * sizeof(double2)) + align256((size_t)(spec->nx + spec->ny) * sizeof(double2)) +
            align256((size_t)spec->nz * sizeof(double));
 }
@@ -317,17 +317,17 @@ extern "C" gff_status gff_build_grid(const gff_substrate *sub, const gff_grid_sp
     CoulombPlan cp = coulomb_plan(spec, sub);
     if (spec->z0 <= cp.ztop) return GFF_EINVAL;          // grid must lie above the slab
     const int n = sub->n_atoms;
-    std::vector<double> sp(5 * (size_t)n);
+    std::vector<double> sp(6 * (size_t)n);
     double qsum = 0.0, qz = 0.0;
     for (int j = 0; j < n; ++j) {
-        sp[5 * j] = sub->pos_h[3 * j]; sp[5 * j + 1] = sub->pos_h[3 * j + 1]; sp[5 * j + 2] = sub->pos_h[3 * j + 2];
-        sp[5 * j + 3] = sub->eps_h[j]; sp[5 * j + 4] = sub->R_h[j];
+        sp[6 * j] = sub->pos_h[3 * j]; sp[6 * j + 1] = sub->pos_h[3 * j + 1]; sp[6 * j + 2] = sub->pos_h[3 * j + 2];
+        sp[6 * j + 3] = sub->eps_h[j]; sp[6 * j + 4] = sub->R_h[j]; sp[6 * j + 5] = sub->q_h[j];
         qsum += sub->q_h[j]; qz += sub->q_h[j] * sub->pos_h[3 * j + 2];
     }
     const double ke = spec->k_e > 0 ? spec->k_e : kDefaultKe;
     const double dx = sub->Lx / spec->nx, dy = sub->Ly / spec->ny;
     char *w = static_cast<char *>(d_work);
-    double *d_sp = reinterpret_cast<double *>(w); w += align256((size_t)n * 5 * sizeof(double));
+    double *d_sp = reinterpret_cast<double *>(w); w += align256((size_t)n * 6 * sizeof(double));
     double2 *d_S = reinterpret_cast<double2 *>(w); w += align256(cp.S_elems * sizeof(double2));
     double2 *d_C = reinterpret_cast<double2 *>(w); w += align256(cp.C_elems * sizeof(double2));
     double2 *d_T = reinterpret_cast<double2 *>(w); w += align256(cp.C_elems * sizeof(double2));

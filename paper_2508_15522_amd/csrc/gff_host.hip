@@ -76,13 +76,21 @@ extern "C" gff_status gff_topology_create(const gff_mol_type *types, int n_types
     std::vector<int2> incT, rotinfo(n_types);
     std::vector<BondInc> bnd;
     std::vector<AngInc> ang;
-    std::vector<TorInc> tor;
+    std::vector<TorDef> tdef;
+    std::vector<int> tinc;
     std::vector<uint4> rotm;
     for (int t = 0; t < n_types; ++t) {
         const gff_mol_type &m = types[t];
         const int n = m.n_atoms;
-        ti[t] = TypeInfo{n, (int)plqm.size(), 0, 0};
+        ti[t] = TypeInfo{n, (int)plqm.size(), (int)tdef.size(), m.n_tors};
         T->natoms.push_back(n);
+        T->ntors.push_back(m.n_tors);
+        for (int q = 0; q < m.n_tors; ++q) {
+            const int *Q4 = m.tors + 4 * q;
+            const double ph = m.tors_phi0[q];
+            tdef.push_back(TorDef{Q4[0] | (Q4[1] << 8) | (Q4[2] << 16) | (Q4[3] << 24), m.tors_n[q], m.tors_V[q], 0.f,
+                                  (float)std::cos(ph), (float)std::sin(ph), 0.f, 0.f});
+        }
         T->nrot.push_back(m.n_rot);
         // adjacency and exclusions (self, 1-2, 1-3)
         std::vector<std::vector<char>> adj(n, std::vector<char>(n, 0));
@@ -123,18 +131,13 @@ extern "C" gff_status gff_topology_create(const gff_mol_type *types, int n_types
             ia.w = (int)ang.size() - ia.z;
             incA.push_back(ia);
             int2 it;
-            it.x = (int)tor.size();
+            it.x = (int)tinc.size();
             for (int q = 0; q < m.n_tors; ++q) {
                 const int *Q4 = m.tors + 4 * q;
                 for (int s = 0; s < 4; ++s)
-                    if (Q4[s] == a) {
-                        const int packed = Q4[0] | (Q4[1] << 8) | (Q4[2] << 16) | (Q4[3] << 24);
-                        const double ph = m.tors_phi0[q];
-                        tor.push_back(TorInc{packed, s, m.tors_n[q], m.tors_V[q], (float)std::cos(ph), (float)std::sin(ph), 0, 0});
-                        break;
-                    }
+                    if (Q4[s] == a) { tinc.push_back((q << 2) | s); break; }
             }
-            it.y = (int)tor.size() - it.x;
+            it.y = (int)tinc.size() - it.x;
             incT.push_back(it);
         }
         rotinfo[t] = make_int2((int)rotq.size(), m.n_rot);
@@ -151,7 +154,8 @@ extern "C" gff_status gff_topology_create(const gff_mol_type *types, int n_types
     DevTopo &d = T->dev;
     if ((rc = upload(o, ti, &d.types)) || (rc = upload(o, plqm, &d.plqm)) || (rc = upload(o, khalf, &d.khalf)) ||
         (rc = upload(o, excl, &d.excl)) || (rc = upload(o, incA, &d.incA)) || (rc = upload(o, incT, &d.incT)) ||
-        (rc = upload(o, bnd, &d.bnd)) || (rc = upload(o, ang, &d.ang)) || (rc = upload(o, tor, &d.tor)) ||
+        (rc = upload(o, bnd, &d.bnd)) || (rc = upload(o, ang, &d.ang)) || (rc = upload(o, tdef, &d.tordef)) ||
+        (rc = upload(o, tinc, &d.torinc)) ||
         (rc = upload(o, refpos, &d.refpos)) || (rc = upload(o, rotq, &d.rotq)) || (rc = upload(o, rotm, &d.rotm)) ||
         (rc = upload(o, rotinfo, &d.rotinfo))) {
         free_all(o);
@@ -193,13 +197,30 @@ extern "C" gff_status gff_plan_create(const gff_topology *topo, int n_rep, const
     std::vector<int> order(topo->n_types);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return topo->natoms[a] > topo->natoms[b]; });
+    // LDS per block: 84 bytes per lane plus 32 bytes per (replica, torsion term); packs of
+    // torsion-heavy types hold fewer replicas when the block's LDS would overflow
+    int dev = 0, lds_limit = 65536;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
+            lds_limit = v;
+    }
+    const long lane_lds = (long)BT * (5 * 16 + 4) + 16;
+    if (lane_lds >= lds_limit) return GFF_EUNSUPPORTED;
     std::vector<int4> packs;
     std::vector<int> reps;
+    int tres_max = 0;
     for (int t : order) {
         const int n = topo->natoms[t];
         int rpb = BT / n;
         if (rpb_cap > 0) rpb = std::min(rpb, rpb_cap);
+        if (topo->ntors[t] > 0 && !by_type[t].empty()) {
+            const long fit = (lds_limit - lane_lds) / (32L * topo->ntors[t]);
+            if (fit < 1) return GFF_EUNSUPPORTED;
+            rpb = (int)std::min<long>(rpb, fit);
+        }
         const auto &L = by_type[t];
+        if (!L.empty()) tres_max = std::max(tres_max, (int)std::min<size_t>(rpb, L.size()) * topo->ntors[t]);
         for (size_t s = 0; s < L.size(); s += rpb) {
             const int cnt = (int)std::min<size_t>(rpb, L.size() - s);
             packs.push_back(make_int4(t, cnt, (int)reps.size(), 0));
@@ -208,7 +229,7 @@ extern "C" gff_status gff_plan_create(const gff_topology *topo, int n_rep, const
     }
     auto *P = new gff_plan_s();
     P->n_rep = n_rep; P->n_atoms = atom_off[n_rep]; P->n_packs = (int)packs.size();
-    P->block_threads = BT; P->grid_blocks = grid; P->max_n = max_n;
+    P->block_threads = BT; P->grid_blocks = grid; P->max_n = max_n; P->tres_max = tres_max;
     P->atom_off_h = atom_off;
     P->rep_type_h.assign(rep_type_h, rep_type_h + n_rep);
     std::vector<void *> owned;

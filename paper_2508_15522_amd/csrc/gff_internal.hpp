@@ -16,14 +16,18 @@ constexpr double kDefaultKe = 14.3996454784;
 struct TypeInfo {              // per molecule type
     int n;                     // atoms
     int abase;                 // first entry in the per-type-atom arrays
-    int pad0, pad1;
+    int tbase;                 // first torsion of the type in the torsion-term table
+    int nt;                    // torsion terms of the type
 };
+
+// Torsion term: atoms (i,j,k,l) packed one byte each, multiplicity, barrier V and
+// (cos phi0, sin phi0).
+struct TorDef { int ijkl; int n; float V; float pad; float c0, s0, pad1, pad2; };
 
 // One entry per (atom, incident term).  `slot` is the atom's position in the term; the
 // slot-0 entry carries the term's energy so every term is counted once.
 struct BondInc { int other; int slot; float k; float r0; };
 struct AngInc  { int a, b, c, slot; float k, cos0, pad0, pad1; };        // b = vertex
-struct TorInc  { int ijkl; int slot; int n; float V; float c0, s0, pad0, pad1; }; // ijkl: 4 bytes
 
 struct DevTopo {
     const TypeInfo *types;
@@ -31,10 +35,11 @@ struct DevTopo {
     const float *khalf;        // [type atoms] m * 103.6427 / 2
     const uint4 *excl;         // [type atoms] bit j: pair excluded (self, 1-2, 1-3)
     const int4 *incA;          // [type atoms] bond start, bond count, angle start, angle count
-    const int2 *incT;          // [type atoms] torsion start, torsion count
+    const int2 *incT;          // [type atoms] torsion-incidence start, count
+    const int *torinc;         // torsion incidences: (term within type) << 2 | slot
+    const TorDef *tordef;      // torsion terms
     const BondInc *bnd;
     const AngInc *ang;
-    const TorInc *tor;
     const float4 *refpos;      // [type atoms] reference geometry (pose construction)
     const int4 *rotq;          // [rotatable torsions of all types] quad
     const uint4 *rotm;         // [same] 128-bit moving mask
@@ -45,6 +50,7 @@ struct DevTopo {
 
 struct gff_topology_s {
     int n_types;
+    std::vector<int> ntors;
     float alpha, ke;
     std::vector<int> natoms;
     std::vector<int> nrot;
@@ -55,6 +61,7 @@ struct gff_topology_s {
 struct gff_plan_s {
     int n_rep, n_atoms, n_packs;
     int block_threads, grid_blocks, max_n;
+    int tres_max;              // largest (replicas per pack) x (torsion terms) of the batch
     int4 *d_packs;             // type, replicas in pack, first entry in d_pack_reps, pad
     int *d_pack_reps;          // replica ids in pack order
     int *d_atom_off;           // [n_rep+1]

@@ -36,7 +36,7 @@ struct KArgs {
     DevTopo t;
     float alpha_l2e, alpha, ke;
     const int4 *packs; const int *pack_reps; const int *atom_off;
-    int n_packs, N;
+    int n_packs, N, tres_max;
     float *pos, *vel;
     float *fdt, *falpha; int *fnpos; unsigned *status;
     float *F; float *E_atom; double *E_rep; float *fnorm; int *steps; double *drift;
@@ -159,17 +159,93 @@ __device__ __forceinline__ float3 cross(float3 a, float3 b) {
     return make_float3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
 }
 
-// Intramolecular force on this lane's atom and its energy share: pairs more than two
-// bonds apart (Morse with depth eps_i eps_j at R_i + R_j, factorised as
-// P_i P_j e^{-2 alpha r} - L_i L_j e^{-alpha r}/2, plus k_e Q_i Q_j / r; half the pair
-// energy to each atom), then the bonded terms incident to the atom (each term evaluated
-// by every participant for its own slot; the slot-0 participant carries the energy).
-__device__ __forceinline__ float intra_atom(const KArgs &A, const float4 *sp, int rbase, int n,
-                                            int abase, int at, float3 xi, float4 me, uint4 ex,
-                                            float3 &F) {
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
+// Sum over the four lanes of a quad (lanes 4q..4q+3) with DPP quad permutations; every
+// lane of the quad receives the same value ((v0+v1)+(v2+v3) in either order).
+__device__ __forceinline__ float quad_sum(float v) {
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));  // [1,0,3,2]
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false));  // [2,3,0,1]
+    return v;
+}
+
+// Hand-off of one atom's grid lookup: owner lane -> the quad that gathers for it.
+struct GridKey { int i, j, k, valid; };
+
+// Owner side: cell indices and in-cell offsets (same rules as grid_eval).
+__device__ __forceinline__ GridKey grid_key(const GridView &g, float x, float y, float z, float4 &t, unsigned &fl) {
+    GridKey key{0, 0, 0, 0};
+    t = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (!(__builtin_isfinite(x) && __builtin_isfinite(y) && __builtin_isfinite(z))) {
+        fl |= GFF_REP_NONFINITE;
+        return key;
+    }
+    float tx, ty, tz;
+    const float qx = cell_split(x - g.x0, g.dx, g.idx, tx);
+    const float qy = cell_split(y - g.y0, g.dy, g.idy, ty);
+    float qz = cell_split(z - g.z0, g.dz, g.idz, tz);
+    if (qz < 0.f) { qz = 0.f; tz = 0.f; fl |= GFF_REP_OUT_OF_DOMAIN; }
+    if (qz > g.zmax || (qz == g.zmax && tz > 0.f)) return key;         // above the grid: zero
+    key.i = wrap_index(qx, g.nx); key.j = wrap_index(qy, g.ny); key.k = (int)qz; key.valid = 1;
+    t = make_float4(tx, ty, tz, 0.f);
+    return key;
+}
+
+// Quad side: lane s of the quad loads node k-1+s of each of the 16 columns (so the quad
+// reads each column as one contiguous 64-byte (F32) / 32-byte (F16) segment), mixes the
+// channels and accumulates its share of the tensor-product contraction; the quad sum is
+// the atom's energy and gradient (in grid units).
+template <int STORE>
+__device__ __forceinline__ float4 quad_gather(const GridView &g, GridKey key, float4 t, float P, float L, float Q,
+                                              int s) {
+    float E = 0.f, Ex = 0.f, Ey = 0.f, Ez = 0.f;
+    if (key.valid) {
+        float wx[4], dx[4], wy[4], dy[4], wz[4], dz[4];
+        bspline_weights(t.x, wx, dx);
+        bspline_weights(t.y, wy, dy);
+        bspline_weights(t.z, wz, dz);
+        const float wzs = s == 0 ? wz[0] : (s == 1 ? wz[1] : (s == 2 ? wz[2] : wz[3]));
+        const float dzs = s == 0 ? dz[0] : (s == 1 ? dz[1] : (s == 2 ? dz[2] : dz[3]));
+        const int i = key.i, j = key.j;
+        int ix[4], jy[4];
+        ix[0] = (i == 0 ? g.nx : i) - 1; ix[1] = i;
+        ix[2] = (i + 1 == g.nx) ? 0 : i + 1; ix[3] = (i + 2 >= g.nx) ? i + 2 - g.nx : i + 2;
+        jy[0] = (j == 0 ? g.ny : j) - 1; jy[1] = j;
+        jy[2] = (j + 1 == g.ny) ? 0 : j + 1; jy[3] = (j + 2 >= g.ny) ? j + 2 - g.ny : j + 2;
+        const float Ps = P * g.s0, Ls = L * g.s1, Qs = Q * g.s2;
+        const int kk = key.k + s;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const int row = ix[a] * g.ny;
+            float4 c[4];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) c[b] = load_node<STORE>(g.coef, (row + jy[b]) * g.nzp + kk);
+            float yv = 0.f, yy = 0.f;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const float m = Ps * c[b].x + Ls * c[b].y + Qs * c[b].z;
+                yv += wy[b] * m; yy += dy[b] * m;
+            }
+            E += wx[a] * yv; Ex += dx[a] * yv; Ey += wx[a] * yy;
+        }
+        // z weights enter once per lane: E = sum_s wz[s] (...), dE/dz = sum_s dz[s] (...)
+        Ez = E * dzs;
+        E *= wzs; Ex *= wzs; Ey *= wzs;
+    }
+    return make_float4(quad_sum(E), quad_sum(Ex), quad_sum(Ey), quad_sum(Ez));
+}
+
+// Non-bonded pairs of this lane's atom (more than two bonds apart): Morse with depth
+// eps_i eps_j at R_i + R_j factorised as P_i P_j e^{-2 alpha r} - L_i L_j e^{-alpha r}/2,
+// plus k_e Q_i Q_j / r.  Returns the sum of full pair energies (the caller halves it).
+__device__ __forceinline__ float pair_terms(const KArgs &A, const float4 *sp, const float4 *splq, int rbase, int n,
+                                            float3 xi, float4 me, uint4 ex, float &fx, float &fy, float &fz) {
     float e = 0.f;
-    float fx = 0.f, fy = 0.f, fz = 0.f;
-    const float4 *prm = A.t.plqm + abase;
+    const float keQ = A.ke * me.z;
 #pragma unroll
     for (int w = 0; w < 4; ++w) {
         const int jb = w * 32;
@@ -178,22 +254,28 @@ __device__ __forceinline__ float intra_atom(const KArgs &A, const float4 *sp, in
         const int je = min(n, jb + 32);
         for (int j = jb; j < je; ++j) {
             const float4 pj = sp[rbase + j];
-            const float4 qj = prm[j];
+            const float4 qj = splq[rbase + j];
             const float ddx = xi.x - pj.x, ddy = xi.y - pj.y, ddz = xi.z - pj.z;
             const float r2 = ddx * ddx + ddy * ddy + ddz * ddz;
             const bool skip = (m >> (j - jb)) & 1u;
             const float rinv = __builtin_amdgcn_rsqf(skip ? 1.f : r2);
             const float r = r2 * rinv;
             const float u = __builtin_amdgcn_exp2f(-A.alpha_l2e * r);
-            const float PP = me.x * qj.x, LL = me.y * qj.y, QQ = A.ke * me.z * qj.z;
-            const float eu = PP * u * u, el = 0.5f * LL * u, ec = QQ * rinv;
-            const float epair = eu - el + ec;
-            const float dEdr = A.alpha * (el - 2.f * eu) - ec * rinv;
-            const float s = skip ? 0.f : -dEdr * rinv;
-            fx += s * ddx; fy += s * ddy; fz += s * ddz;
-            e += skip ? 0.f : 0.5f * epair;
+            const float eu = me.x * qj.x * u * u, el = 0.5f * me.y * qj.y * u, ec = keQ * qj.z * rinv;
+            const float g = A.alpha * (2.f * eu - el) + ec * rinv;      // -dE/dr
+            const float sc = skip ? 0.f : g * rinv;
+            fx += sc * ddx; fy += sc * ddy; fz += sc * ddz;
+            e += skip ? 0.f : (eu - el + ec);
         }
     }
+    return e;
+}
+
+// Bonds and angles incident to this lane's atom (each term evaluated by every
+// participant for its own slot; the slot-0 participant carries the energy).
+__device__ __forceinline__ float bond_angle_terms(const KArgs &A, const float4 *sp, int rbase, int abase, int at,
+                                                  float3 xi, float &fx, float &fy, float &fz) {
+    float e = 0.f;
     const int4 ia = A.t.incA[abase + at];
     for (int b = ia.x; b < ia.x + ia.y; ++b) {
         const BondInc bi = A.t.bnd[b];
@@ -218,58 +300,72 @@ __device__ __forceinline__ float intra_atom(const KArgs &A, const float4 *sp, in
         fx -= de * gs.x; fy -= de * gs.y; fz -= de * gs.z;
         if (ai.slot == 0) e += 0.5f * ai.k * (cs - ai.cos0) * (cs - ai.cos0);
     }
-    const int2 it = A.t.incT[abase + at];
-    for (int q = it.x; q < it.x + it.y; ++q) {
-        const TorInc ti = A.t.tor[q];
-        const int i0 = ti.ijkl & 0xff, i1 = (ti.ijkl >> 8) & 0xff, i2 = (ti.ijkl >> 16) & 0xff, i3 = (ti.ijkl >> 24) & 0xff;
-        const float3 p0 = f3(sp[rbase + i0]), p1 = f3(sp[rbase + i1]), p2 = f3(sp[rbase + i2]), p3 = f3(sp[rbase + i3]);
-        const float3 b1 = p1 - p0, b2 = p2 - p1, b3 = p3 - p2;
-        const float3 mm = cross(b1, b2), nn = cross(b2, b3);
-        const float m2 = dot(mm, mm), n2 = dot(nn, nn), bb = dot(b2, b2);
-        if (m2 < 1e-12f || n2 < 1e-12f) continue;        // collinear: dihedral undefined
-        const float lb = sqrtf(bb);
-        const float inv = __builtin_amdgcn_rsqf(m2 * n2);
-        const float c1 = dot(mm, nn) * inv, s1 = lb * dot(b1, nn) * inv;  // cos phi, sin phi
-        float cn = c1, sn = s1;
-        for (int r = 1; r < ti.n; ++r) {                  // (cos n phi, sin n phi)
-            const float c2 = cn * c1 - sn * s1;
-            sn = sn * c1 + cn * s1; cn = c2;
-        }
-        const float carg = cn * ti.c0 + sn * ti.s0, sarg = sn * ti.c0 - cn * ti.s0;
-        const float dEdphi = 0.5f * ti.V * (float)ti.n * sarg;
-        const float3 gi = (-lb / m2) * mm, gl = (lb / n2) * nn;
-        const float p = dot(b1, b2) / bb, qq = dot(b3, b2) / bb;
-        float3 gs;
-        if (ti.slot == 0) gs = gi;
-        else if (ti.slot == 3) gs = gl;
-        else if (ti.slot == 1) gs = (-(1.f + p)) * gi + qq * gl;
-        else gs = p * gi + (-(1.f + qq)) * gl;
-        fx -= dEdphi * gs.x; fy -= dEdphi * gs.y; fz -= dEdphi * gs.z;
-        if (ti.slot == 0) e += 0.5f * ti.V * (1.f - carg);
-    }
-    F = make_float3(fx, fy, fz);
     return e;
+}
+
+// One torsion term 1/2 V (1 - cos(n phi - phi0)) evaluated once: its energy, and the
+// per-term data from which each participant's force follows,
+//   F_i = A, F_l = B, F_j = -(1+p) A + q B, F_k = p A - (1+q) B,
+// with A = -dE/dphi dphi/dr_i, B = -dE/dphi dphi/dr_l, p = b1.b2/|b2|^2, q = b3.b2/|b2|^2.
+__device__ __forceinline__ float torsion_term(const TorDef td, const float4 *sp, int rbase, float4 &oA, float4 &oB) {
+    const int i0 = td.ijkl & 0xff, i1 = (td.ijkl >> 8) & 0xff, i2 = (td.ijkl >> 16) & 0xff, i3 = (td.ijkl >> 24) & 0xff;
+    const float3 p0 = f3(sp[rbase + i0]), p1 = f3(sp[rbase + i1]), p2 = f3(sp[rbase + i2]), p3 = f3(sp[rbase + i3]);
+    const float3 b1 = p1 - p0, b2 = p2 - p1, b3 = p3 - p2;
+    const float3 mm = cross(b1, b2), nn = cross(b2, b3);
+    const float m2 = dot(mm, mm), n2 = dot(nn, nn), bb = dot(b2, b2);
+    if (m2 < 1e-12f || n2 < 1e-12f) {             // collinear: dihedral undefined, term dropped
+        oA = make_float4(0.f, 0.f, 0.f, 0.f); oB = oA;
+        return 0.f;
+    }
+    const float lb = sqrtf(bb);
+    const float inv = __builtin_amdgcn_rsqf(m2 * n2);
+    const float c1 = dot(mm, nn) * inv, s1 = lb * dot(b1, nn) * inv;    // cos phi, sin phi
+    float cn = c1, sn = s1;
+    for (int r = 1; r < td.n; ++r) {                                    // (cos n phi, sin n phi)
+        const float c2 = cn * c1 - sn * s1;
+        sn = sn * c1 + cn * s1; cn = c2;
+    }
+    const float carg = cn * td.c0 + sn * td.s0, sarg = sn * td.c0 - cn * td.s0;
+    const float dEdphi = 0.5f * td.V * (float)td.n * sarg;
+    const float fa = dEdphi * lb / m2, fb = -dEdphi * lb / n2;           // A = fa mm, B = fb nn
+    oA = make_float4(fa * mm.x, fa * mm.y, fa * mm.z, dot(b1, b2) / bb);
+    oB = make_float4(fb * nn.x, fb * nn.y, fb * nn.z, dot(b3, b2) / bb);
+    return 0.5f * td.V * (1.f - carg);
 }
 
 template <int STORE, int MODE>
 __global__ void __launch_bounds__(1024) k_replicas(KArgs A) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int BT = blockDim.x, tid = threadIdx.x;
-    // LDS: two position buffers, one reduction buffer used as float4 (FIRE sums) or double2
-    // (FP64 energy sums; flags at the end) -- never both between two barriers -- and a flag pair
+    // LDS, one float4 slot per lane in each array:
+    //   s_pos0/s_pos1  positions (double-buffered by step parity); the buffer of the other
+    //                  parity carries the gather results during a step
+    //   s_red          per-atom partial sums (float4 FIRE, double2 NVE) and, earlier in the
+    //                  step, the gather offsets
+    //   s_sum          per-replica sums (index = replica in pack) and, earlier, gather indices
+    //   s_plq          per-lane P, L, Q, 1/(m 103.6427)
+    //   s_nf           per-replica non-finite flags (NVE)
+    //   s_tres         torsion-term results, 2 float4 per term and replica
     float4 *s_pos0 = reinterpret_cast<float4 *>(smem);
     float4 *s_pos1 = s_pos0 + BT;
     float4 *s_red = s_pos1 + BT;
+    float4 *s_sum = s_red + BT;
+    float4 *s_plq = s_sum + BT;
+    float4 *s_tres = s_plq + BT;
+    int *s_nf = reinterpret_cast<int *>(s_tres + 2 * A.tres_max);
+    int *s_any = s_nf + BT;
     double2 *s_red64 = reinterpret_cast<double2 *>(s_red);
-    int *s_any = reinterpret_cast<int *>(s_red + BT);
+    float4 *s_gt = s_red;
+    int4 *s_gi = reinterpret_cast<int4 *>(s_sum);
     const int N = A.N;
+    const int wl = tid & 63, wb = tid - wl, quad_s = wl & 3;
     GridView gv = A.g;
     fetch_scales(gv);
 
     for (int pk = blockIdx.x; pk < A.n_packs; pk += gridDim.x) {
         const int4 pinfo = A.packs[pk];
         const TypeInfo ti = A.t.types[pinfo.x];
-        const int n = ti.n, nrep = pinfo.y, abase = ti.abase;
+        const int n = ti.n, nrep = pinfo.y, abase = ti.abase, nt = ti.nt;
         const int lr = tid / n, at = tid - lr * n;
         const bool active = lr < nrep;
         const int rbase = active ? lr * n : 0;
@@ -290,34 +386,24 @@ __global__ void __launch_bounds__(1024) k_replicas(KArgs A) {
             st = MODE == MODE_EVAL ? 0u : A.status[rep];
             if (MODE == MODE_FIRE) { fdt = A.fdt[rep]; fal = A.falpha[rep]; fnp = A.fnpos[rep]; }
         }
+        s_plq[tid] = me;
+        s_nf[tid] = 0;
         if (tid == 0) { s_any[0] = 0; s_any[1] = 0; }
         lds_sync();
 
-        unsigned fl = 0;                 // per-lane sticky flags (out of domain)
+        unsigned fl = 0;                 // per-lane sticky flags (out of domain, non-finite position)
         float3 F = make_float3(0.f, 0.f, 0.f);
         float e_atom = 0.f, e_grid = 0.f, fnorm = 0.f;
         int steps = 0;
         const bool entered_conv = (st & GFF_REP_CONVERGED) != 0;
         bool live = active && !(st & GFF_REP_NONFINITE);
-        double dr0 = 0, dr1 = 0, dr2 = 0, dr3 = 0, dr4 = 0, dr5 = 0;
-
-        // evaluation of the current positions: F, e_atom, e_grid
-        auto evaluate = [&](const float4 *sp) {
-            float gx, gy, gz;
-            e_grid = grid_eval<STORE>(gv, x.x, x.y, x.z, me.x, me.y, me.z, gx, gy, gz, fl);
-            F = make_float3(-gx, -gy, -gz);
-            e_atom = e_grid;
-            if (A.include_intra) {
-                float3 Fi;
-                e_atom += intra_atom(A, sp, rbase, n, abase, at, x, me, ex, Fi);
-                F = F + Fi;
-            }
-        };
+        double dr0 = 0, dr1 = 0, dr2 = 0, dr3 = 0, dr4 = 0, dr5 = 0;   // reducer lane: drift record
 
         const int total = (MODE == MODE_EVAL) ? 0 : A.n_steps;
         for (int it = 0; it <= total; ++it) {
             const int par = it & 1;
             float4 *sp = par ? s_pos1 : s_pos0;
+            float4 *s_gres = par ? s_pos0 : s_pos1;
             if (MODE == MODE_NVE && it > 0 && live) {       // velocity Verlet: half kick, drift
                 v = v + (0.5f * A.dt * me.w) * F;
                 x = x + A.dt * v;
@@ -325,21 +411,90 @@ __global__ void __launch_bounds__(1024) k_replicas(KArgs A) {
             if (live) s_any[par] = 1;
             if (tid == 0) s_any[par ^ 1] = 0;
             sp[tid] = make_float4(x.x, x.y, x.z, 0.f);
-            lds_sync();
-            if (s_any[par] == 0) break;                 // every replica of the pack is done
-            if (live) evaluate(sp);
+            lds_sync();                                          // A: positions visible
+            if (s_any[par] == 0) break;                          // every replica of the pack is done
+            if (MODE == MODE_NVE && live && s_nf[lr]) { st |= GFF_REP_NONFINITE; live = false; }
+
+            // --- grid: owner hand-off, then four quad-gather rounds within the wave
+            {
+                float4 t;
+                unsigned fk = 0;
+                GridKey key = grid_key(gv, x.x, x.y, x.z, t, fk);
+                if (!live) key.valid = 0;
+                else fl |= fk;
+                s_gi[tid] = make_int4(key.i, key.j, key.k, key.valid);
+                s_gt[tid] = t;
+                wave_sync();
+#pragma unroll 1
+                for (int rnd = 0; rnd < 4; ++rnd) {
+                    const int o = wb + 16 * rnd + (wl >> 2);
+                    const int4 ki = s_gi[o];
+                    const float4 ko = s_gt[o];
+                    const float4 po = s_plq[o];
+                    const float4 r = quad_gather<STORE>(gv, GridKey{ki.x, ki.y, ki.z, ki.w}, ko, po.x, po.y, po.z, quad_s);
+                    if (quad_s == 0) s_gres[o] = r;
+                }
+                wave_sync();
+                const float4 r = s_gres[tid];
+                e_grid = r.x;
+                F = make_float3(-r.y * gv.idx, -r.z * gv.idy, -r.w * gv.idz);
+                if (fk & GFF_REP_NONFINITE) {
+                    e_grid = __builtin_nanf("");
+                    F = make_float3(e_grid, e_grid, e_grid);
+                }
+            }
+            // --- intramolecular: torsion terms once per term, pairs/bonds/angles per atom
+            float e_intra = 0.f;
+            if (A.include_intra) {
+                if (live) {
+                    for (int q = at; q < nt; q += n) {
+                        float4 oA, oB;
+                        e_intra += torsion_term(A.t.tordef[ti.tbase + q], sp, rbase, oA, oB);
+                        s_tres[2 * (lr * nt + q)] = oA;
+                        s_tres[2 * (lr * nt + q) + 1] = oB;
+                    }
+                    float fx = 0.f, fy = 0.f, fz = 0.f;
+                    e_intra += 0.5f * pair_terms(A, sp, s_plq, rbase, n, x, me, ex, fx, fy, fz);
+                    e_intra += bond_angle_terms(A, sp, rbase, abase, at, x, fx, fy, fz);
+                    F = F + make_float3(fx, fy, fz);
+                }
+                lds_sync();                                      // B: torsion results visible
+                if (live) {
+                    const int2 itc = A.t.incT[abase + at];
+                    float fx = 0.f, fy = 0.f, fz = 0.f;
+                    for (int c = itc.x; c < itc.x + itc.y; ++c) {
+                        const int code = A.t.torinc[c];
+                        const int q = code >> 2, slot = code & 3;
+                        const float4 ra = s_tres[2 * (lr * nt + q)], rb = s_tres[2 * (lr * nt + q) + 1];
+                        float ca, cb;
+                        if (slot == 0) { ca = 1.f; cb = 0.f; }
+                        else if (slot == 3) { ca = 0.f; cb = 1.f; }
+                        else if (slot == 1) { ca = -(1.f + ra.w); cb = rb.w; }
+                        else { ca = ra.w; cb = -(1.f + rb.w); }
+                        fx += ca * ra.x + cb * rb.x; fy += ca * ra.y + cb * rb.y; fz += ca * ra.z + cb * rb.z;
+                    }
+                    F = F + make_float3(fx, fy, fz);
+                }
+            }
+            if (live) e_atom = e_grid + e_intra;
 
             if (MODE == MODE_EVAL) break;
 
             if (MODE == MODE_FIRE) {
                 s_red[tid] = make_float4(dot(F, F), dot(F, v), dot(v, v), 0.f);
-                lds_sync();
-                if (live) {
+                lds_sync();                                      // C: partials visible
+                if (tid < nrep) {                                // reducer lane of replica tid
                     float ff = 0.f, fv = 0.f, vv = 0.f;
                     for (int j = 0; j < n; ++j) {
-                        const float4 r = s_red[rbase + j];
+                        const float4 r = s_red[tid * n + j];
                         ff += r.x; fv += r.y; vv += r.z;
                     }
+                    s_sum[tid] = make_float4(ff, fv, vv, 0.f);
+                }
+                lds_sync();                                      // D: sums visible
+                if (live) {
+                    const float4 sm = s_sum[lr];
+                    const float ff = sm.x, fv = sm.y, vv = sm.z;
                     fnorm = sqrtf(ff);
                     if (!__builtin_isfinite(ff) || !__builtin_isfinite(fv) || !__builtin_isfinite(vv)) {
                         st |= GFF_REP_NONFINITE; live = false;
@@ -376,17 +531,17 @@ __global__ void __launch_bounds__(1024) k_replicas(KArgs A) {
                 if (live && it > 0) v = v + (0.5f * A.dt * me.w) * F;
                 if (A.drift != nullptr && (it % A.drift_every) == 0) {
                     const double ke = (double)khalf * ((double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z);
-                    s_red64[tid] = make_double2((double)e_atom, ke);
-                    lds_sync();
-                    if (live) {
+                    s_red64[tid] = live ? make_double2((double)e_atom, ke) : make_double2(0.0, 0.0);
+                    lds_sync();                                  // C: partials visible
+                    if (tid < nrep && !s_nf[tid]) {              // reducer lane of replica tid
                         double ep = 0.0, kk = 0.0;
                         for (int j = 0; j < n; ++j) {
-                            const double2 r = s_red64[rbase + j];
+                            const double2 r = s_red64[tid * n + j];
                             ep += r.x; kk += r.y;
                         }
                         const double et = ep + kk;
                         if (!__builtin_isfinite(et)) {
-                            st |= GFF_REP_NONFINITE; live = false;
+                            s_nf[tid] = 1;
                         } else {
                             if (it == 0) { dr0 = et; dr2 = 0; dr3 = 0; dr4 = 0; dr5 = 0; }
                             const double de = et - dr0;
@@ -401,7 +556,8 @@ __global__ void __launch_bounds__(1024) k_replicas(KArgs A) {
         }
 
         // ---- outputs: per-atom state, then per-replica sums (FP64) and flags
-        lds_sync();       // the last reduction's LDS reads precede these writes
+        lds_sync();       // the last reductions' LDS reads precede these writes
+        if (MODE == MODE_NVE && live && s_nf[lr]) { st |= GFF_REP_NONFINITE; live = false; }
         s_red64[tid] = make_double2((double)e_atom, (double)fl);
         lds_sync();
         if (active) {
@@ -431,11 +587,11 @@ __global__ void __launch_bounds__(1024) k_replicas(KArgs A) {
                     if (A.steps) A.steps[rep] = steps;
                 }
                 if (MODE == MODE_FIRE) { A.fdt[rep] = fdt; A.falpha[rep] = fal; A.fnpos[rep] = fnp; }
-                if (MODE == MODE_NVE && A.drift) {
-                    double *d = A.drift + 6 * (size_t)rep;
-                    d[0] = dr0; d[1] = dr1; d[2] = dr2; d[3] = dr3; d[4] = dr4; d[5] = dr5;
-                }
             }
+        }
+        if (MODE == MODE_NVE && A.drift && tid < nrep) {
+            double *d = A.drift + 6 * (size_t)A.pack_reps[pinfo.z + tid];
+            d[0] = dr0; d[1] = dr1; d[2] = dr2; d[3] = dr3; d[4] = dr4; d[5] = dr5;
         }
         lds_sync();       // LDS is reused by the next pack
     }
@@ -484,18 +640,24 @@ static void fill_common(KArgs &A, const gff_topology *topo, const gff_plan *plan
     A.alpha_l2e = topo->alpha * 1.4426950408889634f;
     A.ke = topo->ke;
     A.packs = plan->d_packs; A.pack_reps = plan->d_pack_reps; A.atom_off = plan->d_atom_off;
-    A.n_packs = plan->n_packs; A.N = plan->n_atoms;
+    A.n_packs = plan->n_packs; A.N = plan->n_atoms; A.tres_max = plan->tres_max;
 }
 
 template <int MODE>
 static gff_status launch_mode(const gff_grid *gr, const gff_plan *plan, KArgs &A, hipStream_t s) {
     const int BT = plan->block_threads;
-    const size_t lds = (size_t)BT * (16 + 16 + 16) + 16;
+    const size_t lds = (size_t)BT * (5 * 16 + 4) + (size_t)plan->tres_max * 32 + 16;
     const int grid = plan->grid_blocks > 0 ? std::min(plan->grid_blocks, plan->n_packs) : plan->n_packs;
     if (grid <= 0) return GFF_OK;
     if (gr->storage == GFF_STORE_F32) {
+        if (lds > 65536)
+            (void)hipFuncSetAttribute((const void *)k_replicas<GFF_STORE_F32, MODE>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         hipLaunchKernelGGL((k_replicas<GFF_STORE_F32, MODE>), dim3(grid), dim3(BT), lds, s, A);
     } else {
+        if (lds > 65536)
+            (void)hipFuncSetAttribute((const void *)k_replicas<GFF_STORE_F16, MODE>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         hipLaunchKernelGGL((k_replicas<GFF_STORE_F16, MODE>), dim3(grid), dim3(BT), lds, s, A);
     }
     return hip_status(hipGetLastError());

@@ -163,7 +163,12 @@ def test_eval_forces_batch_with_intra(block):
     B = S.random_coefficients(NX, NY, NZ, 12, COEF_SCALE)
     grid = D.pack_from_coefficients(B, spec, G.STORE_F32, Lx, Ly)
     topo = G.Topology(mols)
-    plan = G.Plan(topo, rep_type, block_threads=block)
+    try:
+        plan = G.Plan(topo, rep_type, block_threads=block)
+    except G.GffError as e:
+        if "unsupported" in str(e):
+            pytest.skip(f"{block}-thread blocks exceed this device's LDS per block")
+        raise
     pos = _batch(mols, rep_type, 77)
     dpos = D.soa(plan, pos)
     F = torch.empty_like(dpos)

@@ -116,7 +116,7 @@ def test_batch_composition_and_launch_shape_do_not_change_results(world):
     rep_type = rng.integers(0, len(w["mols"]), 50)
     pos = _positions(w, rep_type, 1200)
     ref = None
-    for bt in (128, 512, 1024):
+    for bt in (128, 320, 512):
         plan = G.Plan(w["topo"], rep_type, block_threads=bt)
         st, out = _fire(w, plan, pos, 40)
         x = D.unsoa(plan, st["pos"])
