@@ -243,6 +243,91 @@ gff_status gff_relax_batch(const gff_grid *grid, const gff_topology *topo, const
                            double *d_E_rep, float *d_fnorm_rep, int *d_steps_rep,
                            double *d_drift_rep, void *stream);
 
+/* ------------------------------------------------------------------ proposals and minima */
+
+/* Degrees of freedom per replica, float [n][7 + T]: u, v (lateral centroid as fractions of the
+ * cell), h (height of the lowest atom above z_top), unit quaternion (w, x, y, z) of the rigid
+ * rotation about the centroid, and T target dihedrals (IUPAC) of the rotatable torsions.
+ * The sampling loop perturbs poses and relaxes them to nearby minima (Section
+ * "Configuration sampling on GPU"); here proposals are drawn directly. */
+
+/* Uniform proposals from Philox4x32-10 (Salmon et al. 2011) with counter (replica, block,
+ * round, 0) and key (seed low, seed high): block 0 gives (u, v, h, s1), block 1 (s2, s3, t0,
+ * t1), block b >= 2 the torsions t_{4b-6 ..}; uniforms are (x >> 8) 2^-24; h = h_lo +
+ * (h_hi - h_lo) U; the quaternion follows Shoemake's method from (s1, s2, s3); phi_k = 2 pi t_k.
+ * n_tors <= 16.  d_raw (nullable) receives the raw 32-bit outputs [n][blocks][4]. */
+gff_status gff_propose_uniform(int n_rep, int n_tors, uint64_t seed, uint32_t round, float h_lo, float h_hi,
+                               float *d_dof, uint32_t *d_raw, void *stream);
+
+/* Pose construction from DOF (rows of dof_stride floats) for every replica of `plan`:
+ * reference geometry of the type; each rotatable torsion k in order set to phi_k by rotating
+ * its moving atoms about the j->k bond; rotation about the centroid by the quaternion;
+ * translation of the centroid to (u Lx, v Ly) and of the lowest atom to z_top + h.
+ * Writes d_pos [3][N]. */
+gff_status gff_pose_from_dof(const gff_topology *topo, const gff_plan *plan, const float *d_dof, int dof_stride,
+                             float Lx, float Ly, float z_top, float *d_pos, void *stream);
+
+/* Inverse map for training the proposer: pose -> encoding [n][41] = (cos 2 pi u, sin 2 pi u,
+ * cos 2 pi v, sin 2 pi v, h, quaternion with w >= 0, (cos phi_k, sin phi_k) for k < 16, zero past
+ * the type's torsions).  The orientation is the rigid rotation that best maps the reference
+ * geometry (with the measured torsions) onto the pose (Horn's quaternion method).
+ * d_work: 3N floats of scratch. */
+gff_status gff_encode_pose(const gff_topology *topo, const gff_plan *plan, const float *d_pos, float Lx, float Ly,
+                           float z_top, float *d_work, float *d_enc, void *stream);
+
+/* Encoding [n][41] -> DOF [n][7 + n_tors]: angles from the (cos, sin) pairs, quaternion
+ * normalised, height clamped to [h_lo, h_hi]. */
+gff_status gff_decode_dof(int n, const float *d_enc, int n_tors, float h_lo, float h_hi, float *d_dof, void *stream);
+
+/* Distinct minima in discovery order (energy criterion): candidate c (skipped if d_ok[c] == 0;
+ * d_ok nullable) is new when its energy differs by more than tol from every archived minimum
+ * of the same type, including candidates accepted earlier in the batch.  New minima are
+ * appended to the archive (d_arch_E, d_arch_type, count *d_arch_n, at most `capacity`);
+ * d_is_new[c] = 1 for them.  Sequential in c by definition; one workgroup. */
+gff_status gff_dedupe_energy(int n_new, const double *d_E, const int *d_type, const int *d_ok, double tol,
+                             int capacity, double *d_arch_E, int *d_arch_type, int *d_arch_n, int *d_is_new,
+                             void *stream);
+
+/* ------------------------------------------------------------------ learned proposer */
+
+/* A 4-layer MLP (widths 96 -> 256 -> 256 -> 256 -> 41, SiLU between layers) maps
+ * [64 standard-normal noise values | 32-d embedding of the molecule type] to the pose
+ * encoding of gff_encode_pose.  Weights are FP32 masters with BF16 copies; every GEMM runs
+ * on BF16 MFMA with FP32 accumulation.  Parameter layout (FP32): W1 [256][96], b1 [256],
+ * W2 [256][256], b2, W3 [256][256], b3, W4 [41][256], b4 [41], embedding [n_types][32].
+ * The proposer is trained on the distinct minima the relaxation finds (IMLE, Li & Malik 2018):
+ * for every minimum K noise draws are decoded, the nearest output is kept, and a step on the
+ * masked squared error (quaternion compared up to sign) follows. */
+typedef struct gff_mlp_s gff_mlp;
+size_t gff_mlp_n_params(int n_types);
+/* copies params_h (FP32, gff_mlp_n_params floats) to the device; Adam moments start at 0 */
+gff_status gff_mlp_create(int n_types, const float *params_h, gff_mlp **out);
+void gff_mlp_destroy(gff_mlp *mlp);
+/* synchronous copies of the FP32 parameters and/or the last gradient (either may be NULL) */
+gff_status gff_mlp_get_params(const gff_mlp *mlp, float *params_h, float *grads_h);
+size_t gff_mlp_workspace_bytes(int batch);
+/* d_noise [batch][64], d_type [batch] -> d_out [batch][41] */
+gff_status gff_mlp_forward(gff_mlp *mlp, int batch, const float *d_noise, const int *d_type, float *d_out,
+                           void *d_work, size_t work_bytes, void *stream);
+/* one training step on (noise, type, target encoding, torsion count) rows: outputs, per-sample
+ * loss (nullable), gradient of the batch mean into the model, then Adam with step lr (lr <= 0:
+ * gradient only) */
+gff_status gff_mlp_train_step(gff_mlp *mlp, int batch, const float *d_noise, const int *d_type,
+                              const float *d_target, const int *d_ntors, float lr, float *d_out, float *d_loss,
+                              void *d_work, size_t work_bytes, void *stream);
+/* IMLE selection: d_cand_out [n][K][41] against d_target [n][41]: index of the nearest
+ * candidate per row (ties: lowest index) and its distance (nullable) */
+gff_status gff_imle_select(int n, int K, const float *d_cand_out, const float *d_target, const int *d_ntors,
+                           int *d_best, float *d_best_dist, void *stream);
+/* n standard normals by Box-Muller from Philox4x32-10: counter (q, round, 1, q >> 32) with
+ * q = i/4 gives outputs 4q..4q+3; uniforms ((x >> 8) + 0.5) 2^-24; pairs (u0,u1), (u2,u3) */
+gff_status gff_normal_philox(long n, uint64_t seed, uint32_t round, float *d_out, void *stream);
+/* dst[r][:] = src[r K + idx[r]][:] for rows of `len` floats (idx clamped to [0, K)): picks the
+ * IMLE-selected noise rows */
+gff_status gff_gather_rows(int n, int len, const float *d_src, int K, const int *d_idx, float *d_dst, void *stream);
+/* C [M][N] (FP32) = A [M][K] B [K][N] (BF16, row-major) on the MFMA tile used by the MLP */
+gff_status gff_gemm_bf16(int M, int N, int K, const void *d_A, const void *d_B, float *d_C, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

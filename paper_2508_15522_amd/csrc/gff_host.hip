@@ -233,9 +233,10 @@ extern "C" gff_status gff_plan_create(const gff_topology *topo, int n_rep, const
     P->atom_off_h = atom_off;
     P->rep_type_h.assign(rep_type_h, rep_type_h + n_rep);
     std::vector<void *> owned;
-    const int4 *dp; const int *dr, *da;
+    const int4 *dp; const int *dr, *da, *dt;
     gff_status rc;
-    if ((rc = upload(owned, packs, &dp)) || (rc = upload(owned, reps, &dr)) || (rc = upload(owned, atom_off, &da))) {
+    if ((rc = upload(owned, packs, &dp)) || (rc = upload(owned, reps, &dr)) || (rc = upload(owned, atom_off, &da)) ||
+        (rc = upload(owned, P->rep_type_h, &dt))) {
         free_all(owned);
         delete P;
         return rc;
@@ -243,6 +244,7 @@ extern "C" gff_status gff_plan_create(const gff_topology *topo, int n_rep, const
     P->d_packs = const_cast<int4 *>(dp);
     P->d_pack_reps = const_cast<int *>(dr);
     P->d_atom_off = const_cast<int *>(da);
+    P->d_rep_type = const_cast<int *>(dt);
     *out = P;
     return GFF_OK;
 }
@@ -252,6 +254,7 @@ extern "C" void gff_plan_destroy(gff_plan *P) {
     (void)hipFree(P->d_packs);
     (void)hipFree(P->d_pack_reps);
     (void)hipFree(P->d_atom_off);
+    (void)hipFree(P->d_rep_type);
     delete P;
 }
 

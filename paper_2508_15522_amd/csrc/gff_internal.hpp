@@ -65,6 +65,7 @@ struct gff_plan_s {
     int4 *d_packs;             // type, replicas in pack, first entry in d_pack_reps, pad
     int *d_pack_reps;          // replica ids in pack order
     int *d_atom_off;           // [n_rep+1]
+    int *d_rep_type;           // [n_rep]
     std::vector<int> atom_off_h;
     std::vector<int> rep_type_h;
 };

@@ -1,0 +1,355 @@
+// Pose proposals for the sampling loop: uniform random degrees of freedom from a
+// counter-based Philox4x32-10 stream (Salmon et al., SC'11), decoding of the learned
+// proposer's output encoding, pose construction (torsions, then rigid rotation and
+// placement), minimum deduplication and the inverse map from relaxed poses to the
+// encoding used to train the proposer.
+//
+// DOF layout per replica (float): [u, v, h, qw, qx, qy, qz, phi_0 .. phi_{T-1}]
+//   u, v   lateral position of the centroid as fractions of the cell
+//   h      height of the lowest atom above the top substrate plane
+//   q      unit quaternion of the rigid rotation about the centroid
+//   phi_k  target dihedral of rotatable torsion k (IUPAC convention)
+#include "gff_internal.hpp"
+#include <algorithm>
+#include <cmath>
+
+namespace gff {
+
+constexpr float kTwoPiF = 6.28318530717958647692f;
+
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c[0]), lo0 = 0xD2511F53u * c[0];
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c[2]), lo1 = 0xCD9E8D57u * c[2];
+        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+    }
+}
+
+__device__ __forceinline__ float u01(uint32_t x) { return (float)(x >> 8) * (1.f / 16777216.f); }
+
+__global__ void __launch_bounds__(256) k_propose_uniform(int n_rep, int T, uint32_t key0, uint32_t key1, uint32_t round,
+                                                         float hlo, float hhi, float *dof, uint32_t *raw) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n_rep) return;
+    const int nb = 2 + (T > 2 ? (T - 2 + 3) / 4 : 0);
+    float u[24];
+#pragma unroll 1
+    for (int b = 0; b < nb; ++b) {
+        uint32_t c[4] = {(uint32_t)r, (uint32_t)b, round, 0u};
+        philox4x32_10(c, key0, key1);
+        for (int k = 0; k < 4; ++k) {
+            u[4 * b + k] = u01(c[k]);
+            if (raw) raw[((size_t)r * nb + b) * 4 + k] = c[k];
+        }
+    }
+    float *d = dof + (size_t)r * (7 + T);
+    d[0] = u[0]; d[1] = u[1]; d[2] = hlo + (hhi - hlo) * u[2];
+    const float a = sqrtf(1.f - u[3]), bq = sqrtf(u[3]);
+    float s2, c2, s3, c3;
+    sincosf(kTwoPiF * u[4], &s2, &c2);
+    sincosf(kTwoPiF * u[5], &s3, &c3);
+    d[3] = bq * c3; d[4] = a * s2; d[5] = a * c2; d[6] = bq * s3;       // Shoemake
+    for (int k = 0; k < T; ++k) d[7 + k] = kTwoPiF * u[6 + k];
+}
+
+__device__ __forceinline__ float3 ld3(const float *p, int i, int N) { return make_float3(p[i], p[i + N], p[i + 2 * N]); }
+__device__ __forceinline__ void st3(float *p, int i, int N, float3 v) { p[i] = v.x; p[i + N] = v.y; p[i + 2 * N] = v.z; }
+__device__ __forceinline__ float3 sub3(float3 a, float3 b) { return make_float3(a.x - b.x, a.y - b.y, a.z - b.z); }
+__device__ __forceinline__ float dot3(float3 a, float3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ float3 cross3(float3 a, float3 b) {
+    return make_float3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ float dihedral(float3 p0, float3 p1, float3 p2, float3 p3) {
+    const float3 b1 = sub3(p1, p0), b2 = sub3(p2, p1), b3 = sub3(p3, p2);
+    const float3 m = cross3(b1, b2), n = cross3(b2, b3);
+    return atan2f(sqrtf(dot3(b2, b2)) * dot3(b1, n), dot3(m, n));
+}
+
+// One thread per replica, working in the caller's position array (SoA [3][N]).
+__global__ void __launch_bounds__(128) k_pose(DevTopo t, const int *rep_type, const int *atom_off, int n_rep, int N,
+                                              const float *dof, int stride, float Lx, float Ly, float ztop, float *pos) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n_rep) return;
+    const int ty = rep_type[r];
+    const TypeInfo ti = t.types[ty];
+    const int n = ti.n, a0 = atom_off[r];
+    const float *d = dof + (size_t)r * stride;
+    for (int a = 0; a < n; ++a) {
+        const float4 p = t.refpos[ti.abase + a];
+        st3(pos, a0 + a, N, make_float3(p.x, p.y, p.z));
+    }
+    const int2 ri = t.rotinfo[ty];
+    for (int k = 0; k < ri.y; ++k) {
+        const int4 q = t.rotq[ri.x + k];
+        const uint4 mk = t.rotm[ri.x + k];
+        const float3 pi = ld3(pos, a0 + q.x, N), pj = ld3(pos, a0 + q.y, N), pk = ld3(pos, a0 + q.z, N),
+                     pl = ld3(pos, a0 + q.w, N);
+        const float ang = d[7 + k] - dihedral(pi, pj, pk, pl);
+        float3 ax = sub3(pk, pj);
+        const float il = rsqrtf(dot3(ax, ax));
+        ax = make_float3(ax.x * il, ax.y * il, ax.z * il);
+        float sn, cs;
+        sincosf(ang, &sn, &cs);
+        for (int a = 0; a < n; ++a) {
+            const unsigned w = a < 32 ? mk.x : (a < 64 ? mk.y : (a < 96 ? mk.z : mk.w));
+            if (!((w >> (a & 31)) & 1u)) continue;
+            const float3 v = sub3(ld3(pos, a0 + a, N), pj);
+            const float3 kv = cross3(ax, v);
+            const float kd = dot3(ax, v) * (1.f - cs);
+            st3(pos, a0 + a, N, make_float3(pj.x + v.x * cs + kv.x * sn + ax.x * kd,
+                                            pj.y + v.y * cs + kv.y * sn + ax.y * kd,
+                                            pj.z + v.z * cs + kv.z * sn + ax.z * kd));
+        }
+    }
+    float3 c = make_float3(0.f, 0.f, 0.f);
+    for (int a = 0; a < n; ++a) { const float3 p = ld3(pos, a0 + a, N); c.x += p.x; c.y += p.y; c.z += p.z; }
+    c = make_float3(c.x / n, c.y / n, c.z / n);
+    const float w = d[3], x = d[4], y = d[5], z = d[6];
+    const float R00 = 1.f - 2.f * (y * y + z * z), R01 = 2.f * (x * y - z * w), R02 = 2.f * (x * z + y * w);
+    const float R10 = 2.f * (x * y + z * w), R11 = 1.f - 2.f * (x * x + z * z), R12 = 2.f * (y * z - x * w);
+    const float R20 = 2.f * (x * z - y * w), R21 = 2.f * (y * z + x * w), R22 = 1.f - 2.f * (x * x + y * y);
+    float zmin = 3.4e38f;
+    for (int a = 0; a < n; ++a) {
+        const float3 p = sub3(ld3(pos, a0 + a, N), c);
+        const float3 q = make_float3(R00 * p.x + R01 * p.y + R02 * p.z, R10 * p.x + R11 * p.y + R12 * p.z,
+                                     R20 * p.x + R21 * p.y + R22 * p.z);
+        st3(pos, a0 + a, N, q);
+        zmin = fminf(zmin, q.z);
+    }
+    const float3 sh = make_float3(d[0] * Lx, d[1] * Ly, ztop + d[2] - zmin);
+    for (int a = 0; a < n; ++a) {
+        const float3 p = ld3(pos, a0 + a, N);
+        st3(pos, a0 + a, N, make_float3(p.x + sh.x, p.y + sh.y, p.z + sh.z));
+    }
+}
+
+// ---------------------------------------------------------------- deduplication
+// Distinct minima in discovery order (energy criterion): candidate c of type t (with
+// ok[c] != 0) is new if |E_c - E_k| > tol for every archived minimum k of type t,
+// including those accepted earlier in the same batch.  One workgroup walks the candidates
+// in order; its threads scan the archive in parallel.  Appends to the archive.
+__global__ void __launch_bounds__(1024) k_dedupe(int n_new, const double *E, const int *type, const int *ok,
+                                                 double tol, int capacity, double *arch_E, int *arch_type,
+                                                 int *arch_n, int *is_new) {
+    __shared__ int s_match;
+    __shared__ int s_n;
+    if (threadIdx.x == 0) s_n = *arch_n;
+    __syncthreads();
+    for (int c = 0; c < n_new; ++c) {
+        const bool cand = ok == nullptr || ok[c] != 0;
+        if (!cand) {
+            if (threadIdx.x == 0) is_new[c] = 0;
+            continue;                                   // uniform across the block
+        }
+        const double e = E[c];
+        const int t = type[c];
+        if (threadIdx.x == 0) s_match = !(fabs(e) < 1e300);   // non-finite energies never count
+        __syncthreads();
+        const int na = s_n;
+        bool m = false;
+        for (int k = threadIdx.x; k < na; k += blockDim.x)
+            if (arch_type[k] == t && fabs(arch_E[k] - e) <= tol) m = true;
+        if (m) s_match = 1;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const int fresh = !s_match && na < capacity;
+            is_new[c] = fresh;
+            if (fresh) { arch_E[na] = e; arch_type[na] = t; s_n = na + 1; }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *arch_n = s_n;
+}
+
+// ---------------------------------------------------------------- pose -> encoding
+// Symmetric 4x4 eigenvector of the largest eigenvalue by cyclic Jacobi rotations.
+__device__ void top_eigvec4(float A[4][4], float v[4]) {
+    float V[4][4] = {{1, 0, 0, 0}, {0, 1, 0, 0}, {0, 0, 1, 0}, {0, 0, 0, 1}};
+    for (int sweep = 0; sweep < 12; ++sweep) {
+        for (int p = 0; p < 3; ++p)
+            for (int q = p + 1; q < 4; ++q) {
+                const float apq = A[p][q];
+                if (fabsf(apq) < 1e-30f) continue;
+                const float th = 0.5f * (A[q][q] - A[p][p]) / apq;
+                const float tt = (th >= 0.f ? 1.f : -1.f) / (fabsf(th) + sqrtf(th * th + 1.f));
+                const float c = rsqrtf(tt * tt + 1.f), sn = tt * c;
+                for (int k = 0; k < 4; ++k) {          // A <- J^T A J
+                    const float akp = A[k][p], akq = A[k][q];
+                    A[k][p] = c * akp - sn * akq; A[k][q] = sn * akp + c * akq;
+                }
+                for (int k = 0; k < 4; ++k) {
+                    const float apk = A[p][k], aqk = A[q][k];
+                    A[p][k] = c * apk - sn * aqk; A[q][k] = sn * apk + c * aqk;
+                }
+                for (int k = 0; k < 4; ++k) {
+                    const float vkp = V[k][p], vkq = V[k][q];
+                    V[k][p] = c * vkp - sn * vkq; V[k][q] = sn * vkp + c * vkq;
+                }
+            }
+    }
+    int b = 0;
+    for (int k = 1; k < 4; ++k) if (A[k][k] > A[b][b]) b = k;
+    for (int k = 0; k < 4; ++k) v[k] = V[k][b];
+}
+
+// Encoding of a pose (inverse of k_pose): torsions measured on the pose, the reference
+// geometry re-posed with those torsions, and the rigid rotation that best maps it onto the
+// pose (Horn's quaternion method).  enc[41] = [cos 2pi u, sin 2pi u, cos 2pi v, sin 2pi v,
+// h, qw, qx, qy, qz (qw >= 0), (cos phi_k, sin phi_k) for k < 16 (zero past the type's T)].
+__global__ void __launch_bounds__(128) k_encode(DevTopo t, const int *rep_type, const int *atom_off, int n_rep, int N,
+                                                const float *pos, float Lx, float Ly, float ztop, float *work,
+                                                float *enc) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n_rep) return;
+    const int ty = rep_type[r];
+    const TypeInfo ti = t.types[ty];
+    const int n = ti.n, a0 = atom_off[r];
+    const int2 ri = t.rotinfo[ty];
+    float *e = enc + (size_t)r * 41;
+    float dof[7 + 16];
+    // measured torsions
+    for (int k = 0; k < ri.y; ++k) {
+        const int4 q = t.rotq[ri.x + k];
+        dof[7 + k] = dihedral(ld3(pos, a0 + q.x, N), ld3(pos, a0 + q.y, N), ld3(pos, a0 + q.z, N), ld3(pos, a0 + q.w, N));
+    }
+    // reference with those torsions, in the work array (same layout as pos)
+    for (int a = 0; a < n; ++a) {
+        const float4 p = t.refpos[ti.abase + a];
+        st3(work, a0 + a, N, make_float3(p.x, p.y, p.z));
+    }
+    for (int k = 0; k < ri.y; ++k) {
+        const int4 q = t.rotq[ri.x + k];
+        const uint4 mk = t.rotm[ri.x + k];
+        const float3 pj = ld3(work, a0 + q.y, N), pk = ld3(work, a0 + q.z, N);
+        const float ang = dof[7 + k] - dihedral(ld3(work, a0 + q.x, N), pj, pk, ld3(work, a0 + q.w, N));
+        float3 ax = sub3(pk, pj);
+        const float il = rsqrtf(dot3(ax, ax));
+        ax = make_float3(ax.x * il, ax.y * il, ax.z * il);
+        float sn, cs;
+        sincosf(ang, &sn, &cs);
+        for (int a = 0; a < n; ++a) {
+            const unsigned w = a < 32 ? mk.x : (a < 64 ? mk.y : (a < 96 ? mk.z : mk.w));
+            if (!((w >> (a & 31)) & 1u)) continue;
+            const float3 v = sub3(ld3(work, a0 + a, N), pj);
+            const float3 kv = cross3(ax, v);
+            const float kd = dot3(ax, v) * (1.f - cs);
+            st3(work, a0 + a, N, make_float3(pj.x + v.x * cs + kv.x * sn + ax.x * kd,
+                                             pj.y + v.y * cs + kv.y * sn + ax.y * kd,
+                                             pj.z + v.z * cs + kv.z * sn + ax.z * kd));
+        }
+    }
+    float3 cr = make_float3(0.f, 0.f, 0.f), cp = cr;
+    float zmin = 3.4e38f;
+    for (int a = 0; a < n; ++a) {
+        const float3 p = ld3(pos, a0 + a, N), q = ld3(work, a0 + a, N);
+        cp.x += p.x; cp.y += p.y; cp.z += p.z; cr.x += q.x; cr.y += q.y; cr.z += q.z;
+        zmin = fminf(zmin, p.z);
+    }
+    cp = make_float3(cp.x / n, cp.y / n, cp.z / n);
+    cr = make_float3(cr.x / n, cr.y / n, cr.z / n);
+    float S[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    for (int a = 0; a < n; ++a) {
+        const float3 x = sub3(ld3(work, a0 + a, N), cr), y = sub3(ld3(pos, a0 + a, N), cp);
+        const float xs[3] = {x.x, x.y, x.z}, ys[3] = {y.x, y.y, y.z};
+        for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) S[i][j] += xs[i] * ys[j];
+    }
+    float M[4][4] = {
+        {S[0][0] + S[1][1] + S[2][2], S[1][2] - S[2][1], S[2][0] - S[0][2], S[0][1] - S[1][0]},
+        {S[1][2] - S[2][1], S[0][0] - S[1][1] - S[2][2], S[0][1] + S[1][0], S[2][0] + S[0][2]},
+        {S[2][0] - S[0][2], S[0][1] + S[1][0], -S[0][0] + S[1][1] - S[2][2], S[1][2] + S[2][1]},
+        {S[0][1] - S[1][0], S[2][0] + S[0][2], S[1][2] + S[2][1], -S[0][0] - S[1][1] + S[2][2]}};
+    float q[4];
+    top_eigvec4(M, q);
+    const float qn = rsqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    const float sg = q[0] < 0.f ? -qn : qn;
+    float u = cp.x / Lx, v = cp.y / Ly;
+    u -= floorf(u); v -= floorf(v);
+    float su, cu, sv, cv;
+    sincosf(kTwoPiF * u, &su, &cu);
+    sincosf(kTwoPiF * v, &sv, &cv);
+    e[0] = cu; e[1] = su; e[2] = cv; e[3] = sv; e[4] = zmin - ztop;
+    for (int k = 0; k < 4; ++k) e[5 + k] = q[k] * sg;
+    for (int k = 0; k < 16; ++k) {
+        float sn = 0.f, cs = 0.f;
+        if (k < ri.y) sincosf(dof[7 + k], &sn, &cs);
+        e[9 + 2 * k] = cs; e[10 + 2 * k] = sn;
+    }
+}
+
+// Encoding (e.g. the proposer's output) -> DOF: angles from (cos, sin) pairs, the
+// quaternion normalised, the height clamped to [h_lo, h_hi].
+__global__ void __launch_bounds__(256) k_decode(int n, const float *enc, int T, float hlo, float hhi, float *dof) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const float *e = enc + (size_t)r * 41;
+    float *d = dof + (size_t)r * (7 + T);
+    float u = atan2f(e[1], e[0]) / kTwoPiF, v = atan2f(e[3], e[2]) / kTwoPiF;
+    d[0] = u - floorf(u); d[1] = v - floorf(v);
+    d[2] = fminf(fmaxf(e[4], hlo), hhi);
+    float qw = e[5], qx = e[6], qy = e[7], qz = e[8];
+    float nq = qw * qw + qx * qx + qy * qy + qz * qz;
+    if (!(nq > 1e-12f)) { qw = 1.f; qx = qy = qz = 0.f; nq = 1.f; }
+    const float inq = rsqrtf(nq);
+    d[3] = qw * inq; d[4] = qx * inq; d[5] = qy * inq; d[6] = qz * inq;
+    for (int k = 0; k < T; ++k) d[7 + k] = atan2f(e[10 + 2 * k], e[9 + 2 * k]);
+}
+
+}  // namespace gff
+
+using namespace gff;
+
+extern "C" gff_status gff_dedupe_energy(int n_new, const double *d_E, const int *d_type, const int *d_ok, double tol,
+                                        int capacity, double *d_arch_E, int *d_arch_type, int *d_arch_n,
+                                        int *d_is_new, void *stream) {
+    if (n_new < 0 || capacity < 0 || !(tol >= 0.0)) return GFF_EINVAL;
+    if (n_new > 0 && (!d_E || !d_type || !d_is_new)) return GFF_EINVAL;
+    if (!d_arch_E || !d_arch_type || !d_arch_n) return GFF_EINVAL;
+    hipLaunchKernelGGL(k_dedupe, dim3(1), dim3(1024), 0, (hipStream_t)stream, n_new, d_E, d_type, d_ok, tol, capacity,
+                       d_arch_E, d_arch_type, d_arch_n, d_is_new);
+    return hip_status(hipGetLastError());
+}
+
+extern "C" gff_status gff_encode_pose(const gff_topology *topo, const gff_plan *plan, const float *d_pos, float Lx,
+                                      float Ly, float z_top, float *d_work, float *d_enc, void *stream) {
+    if (!topo || !plan || (plan->n_rep > 0 && (!d_pos || !d_work || !d_enc))) return GFF_EINVAL;
+    for (int t : plan->rep_type_h) if (topo->nrot[t] > 16) return GFF_EUNSUPPORTED;
+    if (plan->n_rep == 0) return GFF_OK;
+    hipLaunchKernelGGL(k_encode, dim3((plan->n_rep + 127) / 128), dim3(128), 0, (hipStream_t)stream, topo->dev,
+                       plan->d_rep_type, plan->d_atom_off, plan->n_rep, plan->n_atoms, d_pos, Lx, Ly, z_top, d_work,
+                       d_enc);
+    return hip_status(hipGetLastError());
+}
+
+extern "C" gff_status gff_decode_dof(int n, const float *d_enc, int n_tors, float h_lo, float h_hi, float *d_dof,
+                                     void *stream) {
+    if (n < 0 || n_tors < 0 || n_tors > 16 || (n > 0 && (!d_enc || !d_dof))) return GFF_EINVAL;
+    if (n == 0) return GFF_OK;
+    hipLaunchKernelGGL(k_decode, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, n, d_enc, n_tors, h_lo, h_hi,
+                       d_dof);
+    return hip_status(hipGetLastError());
+}
+
+extern "C" gff_status gff_propose_uniform(int n_rep, int n_tors, uint64_t seed, uint32_t round, float h_lo, float h_hi,
+                                          float *d_dof, uint32_t *d_raw, void *stream) {
+    if (n_rep < 0 || n_tors < 0 || n_tors > 16 || (n_rep > 0 && !d_dof) || !(h_hi >= h_lo)) return GFF_EINVAL;
+    if (n_rep == 0) return GFF_OK;
+    hipLaunchKernelGGL(k_propose_uniform, dim3((n_rep + 255) / 256), dim3(256), 0, (hipStream_t)stream, n_rep, n_tors,
+                       (uint32_t)seed, (uint32_t)(seed >> 32), round, h_lo, h_hi, d_dof, d_raw);
+    return hip_status(hipGetLastError());
+}
+
+extern "C" gff_status gff_pose_from_dof(const gff_topology *topo, const gff_plan *plan, const float *d_dof,
+                                        int dof_stride, float Lx, float Ly, float z_top, float *d_pos, void *stream) {
+    if (!topo || !plan || !d_pos || (plan->n_rep > 0 && !d_dof)) return GFF_EINVAL;
+    int tmax = 0;
+    for (int t : plan->rep_type_h) tmax = std::max(tmax, topo->nrot[t]);
+    if (dof_stride < 7 + tmax) return GFF_EINVAL;
+    if (plan->n_rep == 0) return GFF_OK;
+    hipLaunchKernelGGL(k_pose, dim3((plan->n_rep + 127) / 128), dim3(128), 0, (hipStream_t)stream, topo->dev,
+                       plan->d_rep_type, plan->d_atom_off, plan->n_rep, plan->n_atoms, d_dof, dof_stride, Lx, Ly, z_top,
+                       d_pos);
+    return hip_status(hipGetLastError());
+}

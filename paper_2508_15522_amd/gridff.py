@@ -249,3 +249,110 @@ def relax_batch(grid_desc, topo, plan, params, st, d_E_rep, d_fnorm, d_steps, d_
                   st["status"].data_ptr())
     check(lib().gff_relax_batch(C.byref(grid_desc), topo.handle, plan.handle, C.byref(params), C.byref(state),
                                 _ptr(d_E_rep), _ptr(d_fnorm), _ptr(d_steps), _ptr(d_drift), _stream(stream)))
+
+
+# ------------------------------------------------------------------ proposals / minima
+EXPORTS += ["gff_propose_uniform", "gff_pose_from_dof", "gff_encode_pose", "gff_decode_dof", "gff_dedupe_energy",
+            "gff_mlp_n_params", "gff_mlp_create", "gff_mlp_destroy", "gff_mlp_get_params", "gff_mlp_workspace_bytes",
+            "gff_mlp_forward", "gff_mlp_train_step", "gff_imle_select", "gff_normal_philox", "gff_gemm_bf16",
+            "gff_gather_rows"]
+N_ENC = 41
+
+
+def _rt(name, restype):
+    getattr(lib(), name).restype = restype
+
+
+def propose_uniform(n_rep, n_tors, seed, rnd, h_lo, h_hi, d_dof, d_raw=None, stream=None):
+    check(lib().gff_propose_uniform(C.c_int(n_rep), C.c_int(n_tors), C.c_uint64(seed), C.c_uint32(rnd),
+                                    C.c_float(h_lo), C.c_float(h_hi), _ptr(d_dof), _ptr(d_raw), _stream(stream)))
+
+
+def pose_from_dof(topo, plan, d_dof, dof_stride, Lx, Ly, z_top, d_pos, stream=None):
+    check(lib().gff_pose_from_dof(topo.handle, plan.handle, _ptr(d_dof), C.c_int(dof_stride), C.c_float(Lx),
+                                  C.c_float(Ly), C.c_float(z_top), _ptr(d_pos), _stream(stream)))
+
+
+def encode_pose(topo, plan, d_pos, Lx, Ly, z_top, d_work, d_enc, stream=None):
+    check(lib().gff_encode_pose(topo.handle, plan.handle, _ptr(d_pos), C.c_float(Lx), C.c_float(Ly), C.c_float(z_top),
+                                _ptr(d_work), _ptr(d_enc), _stream(stream)))
+
+
+def decode_dof(d_enc, n_tors, h_lo, h_hi, d_dof, stream=None):
+    check(lib().gff_decode_dof(C.c_int(d_enc.shape[0]), _ptr(d_enc), C.c_int(n_tors), C.c_float(h_lo),
+                               C.c_float(h_hi), _ptr(d_dof), _stream(stream)))
+
+
+def dedupe_energy(d_E, d_type, d_ok, tol, capacity, d_arch_E, d_arch_type, d_arch_n, d_is_new, stream=None):
+    check(lib().gff_dedupe_energy(C.c_int(d_E.numel()), _ptr(d_E), _ptr(d_type), _ptr(d_ok), C.c_double(tol),
+                                  C.c_int(capacity), _ptr(d_arch_E), _ptr(d_arch_type), _ptr(d_arch_n),
+                                  _ptr(d_is_new), _stream(stream)))
+
+
+def normal_philox(n, seed, rnd, d_out, stream=None):
+    check(lib().gff_normal_philox(C.c_long(n), C.c_uint64(seed), C.c_uint32(rnd), _ptr(d_out), _stream(stream)))
+
+
+def gemm_bf16(d_A, d_B, d_C, stream=None):
+    M, K = d_A.shape
+    N = d_B.shape[1]
+    check(lib().gff_gemm_bf16(C.c_int(M), C.c_int(N), C.c_int(K), _ptr(d_A), _ptr(d_B), _ptr(d_C), _stream(stream)))
+
+
+def imle_select(d_cand, d_target, d_ntors, d_best, d_bestd=None, stream=None):
+    n, K = d_cand.shape[0], d_cand.shape[1]
+    check(lib().gff_imle_select(C.c_int(n), C.c_int(K), _ptr(d_cand), _ptr(d_target), _ptr(d_ntors), _ptr(d_best),
+                                _ptr(d_bestd), _stream(stream)))
+
+
+class MLP:
+    """The learned proposer (device-resident FP32 masters, BF16 copies, Adam moments)."""
+
+    def __init__(self, n_types, params):
+        L = lib()
+        L.gff_mlp_n_params.restype = C.c_size_t
+        L.gff_mlp_workspace_bytes.restype = C.c_size_t
+        self.n_types = n_types
+        self.n_params = L.gff_mlp_n_params(C.c_int(n_types))
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        assert p.size == self.n_params, (p.size, self.n_params)
+        self.handle = C.c_void_p()
+        check(L.gff_mlp_create(C.c_int(n_types), p.ctypes.data_as(C.c_void_p), C.byref(self.handle)))
+        self._work = None
+
+    def workspace(self, batch):
+        import torch
+        need = lib().gff_mlp_workspace_bytes(C.c_int(batch))
+        if self._work is None or self._work.numel() < need:
+            self._work = torch.empty(need, dtype=torch.uint8, device="cuda")
+        return self._work
+
+    def params(self):
+        p = np.zeros(self.n_params, np.float32)
+        g = np.zeros(self.n_params, np.float32)
+        check(lib().gff_mlp_get_params(self.handle, p.ctypes.data_as(C.c_void_p), g.ctypes.data_as(C.c_void_p)))
+        return p, g
+
+    def forward(self, d_noise, d_type, d_out, stream=None):
+        B = d_noise.shape[0]
+        w = self.workspace(B)
+        check(lib().gff_mlp_forward(self.handle, C.c_int(B), _ptr(d_noise), _ptr(d_type), _ptr(d_out), _ptr(w),
+                                    C.c_size_t(w.numel()), _stream(stream)))
+
+    def train_step(self, d_noise, d_type, d_target, d_ntors, lr, d_out, d_loss=None, stream=None):
+        B = d_noise.shape[0]
+        w = self.workspace(B)
+        check(lib().gff_mlp_train_step(self.handle, C.c_int(B), _ptr(d_noise), _ptr(d_type), _ptr(d_target),
+                                       _ptr(d_ntors), C.c_float(lr), _ptr(d_out), _ptr(d_loss), _ptr(w),
+                                       C.c_size_t(w.numel()), _stream(stream)))
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.gff_mlp_destroy(self.handle)
+            self.handle = None
+
+
+def gather_rows(d_src, K, d_idx, d_dst, stream=None):
+    n, ln = d_dst.shape[0], d_dst.shape[-1]
+    check(lib().gff_gather_rows(C.c_int(n), C.c_int(ln), _ptr(d_src), C.c_int(K), _ptr(d_idx), _ptr(d_dst),
+                                _stream(stream)))

@@ -1,0 +1,142 @@
+"""Configuration sampling with uniform or learned proposals (host orchestration only).
+
+Each round: proposals (uniform Philox DOF, or the MLP's output from Philox noise,
+decoded) -> poses -> FIRE relaxation to |F| < f_conv in one persistent launch -> energy
+dedupe of the converged minima against the method's archive.  The sampling loop of the
+paper perturbs replicas with Langevin dynamics before relaxing (Section "Configuration
+sampling on GPU"); here proposals are drawn directly and the relaxation is the judge.
+Training (IMLE): the distinct minima are encoded; for each training minimum K noise rows
+are decoded by the network, the nearest output is kept and a step on it follows.
+Every numerical step is a libgridff call; this module only sequences them.
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import device as D, gridff as G, synth as S
+
+H_LO, H_HI = 3.0, 5.0
+
+
+@dataclass
+class Archive:
+    capacity: int = 200000
+    E: torch.Tensor = None
+    types: torch.Tensor = None
+    n: torch.Tensor = None
+
+    def __post_init__(self):
+        self.E = torch.zeros(self.capacity, dtype=torch.float64, device="cuda")
+        self.types = torch.zeros(self.capacity, dtype=torch.int32, device="cuda")
+        self.n = torch.zeros(1, dtype=torch.int32, device="cuda")
+
+    def count(self):
+        return int(self.n.item())
+
+
+@dataclass
+class RoundStats:
+    proposals: int
+    converged: int
+    new_minima: int
+    fire_steps_converged: float
+    seconds: float
+    new_pos: list = field(default_factory=list)
+
+
+class Sampler:
+    def __init__(self, grid, mol, n_rep, f_conv=1e-4, max_steps=5000, seed=S.SEED_PHILOX, block=256):
+        self.grid, self.mol, self.n_rep = grid, mol, n_rep
+        self.topo = G.Topology([mol])
+        self.plan = G.Plan(self.topo, np.zeros(n_rep, np.int32), block_threads=block)
+        self.T = len(mol.rot_quads)
+        self.f_conv, self.max_steps, self.seed = f_conv, max_steps, seed
+        self.Lx, self.Ly = grid.Lx, grid.Ly
+        self.dof = torch.empty(n_rep, 7 + self.T, device="cuda")
+        self.types = torch.zeros(n_rep, dtype=torch.int32, device="cuda")
+        self.ntors = torch.full((n_rep,), self.T, dtype=torch.int32, device="cuda")
+        self.is_new = torch.empty(n_rep, dtype=torch.int32, device="cuda")
+        self.out = D.outputs(self.plan)
+
+    def _relax_and_dedupe(self, archive, keep_new):
+        st = {"pos": torch.empty(3, self.plan.n_atoms, device="cuda"),
+              "vel": torch.zeros(3, self.plan.n_atoms, device="cuda"),
+              "fire_dt": torch.full((self.n_rep,), 0.05, device="cuda"),
+              "fire_alpha": torch.full((self.n_rep,), 0.1, device="cuda"),
+              "fire_npos": torch.zeros(self.n_rep, dtype=torch.int32, device="cuda"),
+              "status": torch.zeros(self.n_rep, dtype=torch.int32, device="cuda")}
+        G.pose_from_dof(self.topo, self.plan, self.dof, 7 + self.T, self.Lx, self.Ly, 0.0, st["pos"])
+        prm = G.relax_params(G.MODE_FIRE, self.max_steps, True, f_conv=self.f_conv)
+        G.relax_batch(self.grid.desc, self.topo, self.plan, prm, st, self.out["E"], self.out["fnorm"],
+                      self.out["steps"])
+        ok = ((st["status"] & G.REP_CONVERGED) != 0).to(torch.int32)
+        G.dedupe_energy(self.out["E"], self.types, ok, 0.01, archive.capacity, archive.E, archive.types, archive.n,
+                        self.is_new)
+        torch.cuda.synchronize()
+        okh = ok.cpu().numpy().astype(bool)
+        steps = self.out["steps"].cpu().numpy()
+        newh = self.is_new.cpu().numpy().astype(bool)
+        kept = [st["pos"].clone()] if keep_new else []
+        return okh, steps, newh, kept
+
+    def round_uniform(self, archive, rnd, keep_new=False):
+        t0 = time.time()
+        G.propose_uniform(self.n_rep, self.T, self.seed, rnd, H_LO, H_HI, self.dof)
+        okh, steps, newh, kept = self._relax_and_dedupe(archive, keep_new)
+        rs = RoundStats(self.n_rep, int(okh.sum()), int(newh.sum()),
+                        float(steps[okh].mean()) if okh.any() else float("nan"), time.time() - t0)
+        rs.new_pos = [(kept[0], newh)] if keep_new else []
+        return rs
+
+    def round_learned(self, archive, mlp, rnd):
+        t0 = time.time()
+        noise = torch.empty(self.n_rep, 64, device="cuda")
+        G.normal_philox(self.n_rep * 64, self.seed + 1, rnd, noise)
+        enc = torch.empty(self.n_rep, 41, device="cuda")
+        mlp.forward(noise, self.types, enc)
+        G.decode_dof(enc, self.T, H_LO, H_HI, self.dof)
+        okh, steps, newh, _ = self._relax_and_dedupe(archive, False)
+        return RoundStats(self.n_rep, int(okh.sum()), int(newh.sum()),
+                          float(steps[okh].mean()) if okh.any() else float("nan"), time.time() - t0)
+
+    def encode_minima(self, pos, mask):
+        """Encodings [m][41] of the replicas selected by mask (host bool array)."""
+        work = torch.empty_like(pos)
+        enc = torch.empty(self.n_rep, 41, device="cuda")
+        G.encode_pose(self.topo, self.plan, pos, self.Lx, self.Ly, 0.0, work, enc)
+        idx = torch.from_numpy(np.where(mask)[0]).cuda()
+        return enc.index_select(0, idx)
+
+
+def train_imle(mlp, targets, ntors, types, steps, batch=1024, K=16, lr=1e-3, seed=S.SEED_MLP, log=None):
+    """IMLE training on encoded minima (device tensors targets [m][41], ntors [m], types [m])."""
+    m = targets.shape[0]
+    rng = np.random.default_rng(seed)
+    cand_noise = torch.empty(batch * K, 64, device="cuda")
+    cand_out = torch.empty(batch * K, 41, device="cuda")
+    best = torch.empty(batch, dtype=torch.int32, device="cuda")
+    sel_noise = torch.empty(batch, 64, device="cuda")
+    out = torch.empty(batch, 41, device="cuda")
+    loss = torch.empty(batch, device="cuda")
+    hist = []
+    for s in range(steps):
+        idx = torch.from_numpy(rng.integers(0, m, batch)).cuda()
+        tg = targets.index_select(0, idx).contiguous()
+        nt = ntors.index_select(0, idx).contiguous()
+        ty = types.index_select(0, idx).contiguous()
+        G.normal_philox(batch * K * 64, seed, s, cand_noise)
+        ty_rep = ty.repeat_interleave(K).contiguous()
+        mlp.forward(cand_noise, ty_rep, cand_out)
+        G.imle_select(cand_out.view(batch, K, 41), tg, nt, best)
+        G.gather_rows(cand_noise.view(batch * K, 64), K, best, sel_noise)
+        mlp.train_step(sel_noise, ty, tg, nt, lr, out, loss)
+        if s % 50 == 0 or s == steps - 1:
+            torch.cuda.synchronize()
+            hist.append((s, float(loss.mean().item())))
+            if log:
+                log(f"imle step {s}: loss {hist[-1][1]:.4f}")
+    return hist

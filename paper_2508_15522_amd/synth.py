@@ -459,3 +459,22 @@ def random_coefficients(nx: int, ny: int, nz: int, seed: int, scale=(1.0, 1.0, 1
     rng = np.random.default_rng(seed)
     b = rng.standard_normal((3, nx, ny, nz)) * np.asarray(scale)[:, None, None, None]
     return f32(b)
+
+
+def mlp_init_params(n_types: int, seed: int = SEED_MLP) -> np.ndarray:
+    """Initial proposer parameters (flat FP32, layout of the library's MLP): weights
+    U(-1/sqrt(fan_in), 1/sqrt(fan_in)), zero biases, N(0, 1) type embeddings."""
+    rng = np.random.default_rng(seed)
+    dims = [96, 256, 256, 256, 41]
+    parts = []
+    for l in range(4):
+        a = 1.0 / np.sqrt(dims[l])
+        parts.append(rng.uniform(-a, a, (dims[l + 1], dims[l])).ravel())
+        parts.append(np.zeros(dims[l + 1]))
+    parts.append(rng.normal(size=(n_types, 32)).ravel())
+    return np.concatenate(parts).astype(np.float32)
+
+
+def mlp_noise(n: int, seed: int) -> np.ndarray:
+    """Standard-normal noise rows [n][64] (FP32-representable)."""
+    return f32(np.random.default_rng(seed).normal(size=(n, 64)))

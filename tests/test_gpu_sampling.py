@@ -1,0 +1,211 @@
+"""GPU parity of the sampling rows: uniform proposals (Philox), pose construction, pose
+encoding/decoding, energy dedupe (a11, a13) and the proposer MLP (a11, a12).
+
+Tolerances: Philox words are compared bit for bit; FP32 DOF/poses against the FP64 oracle
+within 1e-5 (angles, fractions) and 1e-4 A (poses); the MLP runs BF16 GEMMs with FP32
+accumulation against an FP64 oracle that rounds only the weights to BF16, so outputs and
+gradients agree to the BF16 bound (2e-2 relative to the largest magnitude).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from oracle import sampling as OS
+from paper_2508_15522_amd import device as D, gridff as G, synth as S
+from tests.gpu_common import announce
+
+pytestmark = pytest.mark.gpu
+
+L_CELL = 2 * S.SLAB_A
+
+
+@pytest.fixture(scope="module")
+def mols():
+    D.require_gpu()
+    return [S.mol_chain24(), S.mol_pah38(), S.mol_size(52, 6), S.mol_size(18, 3)]
+
+
+def test_propose_uniform_bitexact_stream(mols):
+    announce("propose uniform")
+    T = 16
+    n = 5003
+    dof = torch.empty(n, 7 + T, device="cuda")
+    nb = 2 + (T - 2 + 3) // 4
+    raw = torch.empty(n, nb, 4, dtype=torch.int32, device="cuda")
+    G.propose_uniform(n, T, S.SEED_PHILOX, 7, 3.0, 5.0, dof, raw)
+    torch.cuda.synchronize()
+    rg = raw.cpu().numpy().view(np.uint32)
+    key = [S.SEED_PHILOX & 0xFFFFFFFF, S.SEED_PHILOX >> 32]
+    for r in (0, 1, 17, 4096, n - 1):
+        for b in range(nb):
+            assert list(rg[r, b]) == O.philox4x32_10([r, b, 7, 0], key)
+    ref = O.propose_uniform(n, T, S.SEED_PHILOX, 7)
+    assert np.abs(dof.cpu().numpy() - ref).max() < 2e-5
+
+
+def _plan_and_pos(mols, rep_type, dof):
+    topo = G.Topology(mols)
+    plan = G.Plan(topo, rep_type)
+    Tmax = max(len(mols[t].rot_quads) for t in rep_type)
+    d = torch.from_numpy(np.ascontiguousarray(dof, np.float32)).cuda()
+    pos = torch.empty(3, plan.n_atoms, device="cuda")
+    G.pose_from_dof(topo, plan, d, dof.shape[1], L_CELL, L_CELL, 0.0, pos)
+    return topo, plan, pos
+
+
+def test_pose_and_encoding_parity(mols):
+    announce("pose + encode")
+    rng = np.random.default_rng(2)
+    rep_type = rng.integers(0, len(mols), 301)
+    Tm = 16
+    dof = S.f32(O.propose_uniform(len(rep_type), Tm, 99, 1))
+    topo, plan, pos = _plan_and_pos(mols, rep_type, dof)
+    work = torch.empty_like(pos)
+    enc = torch.empty(len(rep_type), 41, device="cuda")
+    G.encode_pose(topo, plan, pos, L_CELL, L_CELL, 0.0, work, enc)
+    torch.cuda.synchronize()
+    xs = D.unsoa(plan, pos)
+    eg = enc.cpu().numpy()
+    for r, t in enumerate(rep_type):
+        ref = O.pose(mols[t], dof[r, :7 + len(mols[t].rot_quads)], L_CELL, L_CELL, 0.0)[0]
+        assert np.abs(xs[r] - ref).max() < 1e-4, r
+        eo = OS.encode_pose(mols[t], ref, L_CELL, L_CELL, 0.0)
+        assert np.abs(eg[r] - eo).max() < 2e-4, (r, np.abs(eg[r] - eo).max())
+    # decode inverts encode (up to FP32)
+    dd = torch.empty(len(rep_type), 7 + Tm, device="cuda")
+    G.decode_dof(enc, Tm, 0.0, 10.0, dd)
+    torch.cuda.synchronize()
+    dg = dd.cpu().numpy()
+    q = dof[:, 3:7] * np.where(dof[:, 3:4] < 0, -1, 1)
+    assert np.abs(dg[:, :3] - dof[:, :3]).max() < 1e-4
+    assert np.abs(dg[:, 3:7] - q).max() < 1e-4
+    for r, t in enumerate(rep_type):
+        T = len(mols[t].rot_quads)
+        if T:
+            ang = (dg[r, 7:7 + T] - dof[r, 7:7 + T] + np.pi) % (2 * np.pi) - np.pi
+            assert np.abs(ang).max() < 1e-4
+
+
+def test_dedupe_matches_oracle():
+    announce("dedupe")
+    rng = np.random.default_rng(5)
+    n = 3000
+    E = np.round(rng.normal(-1.0, 0.3, n), 3) + rng.uniform(-0.004, 0.004, n)
+    E[17] = np.nan
+    types = rng.integers(0, 3, n)
+    ok = (rng.random(n) < 0.9).astype(np.int32)
+    cap = 100000
+    dE = torch.from_numpy(E).cuda()
+    dt = torch.from_numpy(types.astype(np.int32)).cuda()
+    dok = torch.from_numpy(ok).cuda()
+    aE = torch.zeros(cap, dtype=torch.float64, device="cuda")
+    at = torch.zeros(cap, dtype=torch.int32, device="cuda")
+    an = torch.zeros(1, dtype=torch.int32, device="cuda")
+    isn = torch.empty(n, dtype=torch.int32, device="cuda")
+    half = n // 2
+    G.dedupe_energy(dE[:half], dt[:half], dok[:half], 0.01, cap, aE, at, an, isn[:half])
+    G.dedupe_energy(dE[half:], dt[half:], dok[half:], 0.01, cap, aE, at, an, isn[half:])
+    torch.cuda.synchronize()
+    ref_new, arch = OS.dedupe_energy(E, types, ok, 0.01)
+    assert np.array_equal(isn.cpu().numpy(), ref_new)
+    assert an.item() == len(arch)
+    assert np.array_equal(aE[:len(arch)].cpu().numpy(), np.array([a[0] for a in arch]))
+
+
+def _bf16_bits(a):
+    a = np.asarray(a, np.float32)
+    return (OS.bf16(a).astype(np.float32).view(np.uint32) >> 16).astype(np.uint16)
+
+
+@pytest.mark.parametrize("shape", [(64, 64, 32), (130, 41, 256), (37, 256, 96), (256, 96, 1000)])
+def test_gemm_bf16_mfma_layout(shape):
+    """The MFMA tile against an exact FP64 product of the same BF16 inputs."""
+    M, N, K = shape
+    announce(f"gemm {shape}")
+    rng = np.random.default_rng(M + N + K)
+    A = rng.normal(size=(M, K)); B = rng.normal(size=(K, N))
+    Ab, Bb = _bf16_bits(A), _bf16_bits(B)
+    dA = torch.from_numpy(Ab.view(np.int16)).cuda()
+    dB = torch.from_numpy(Bb.view(np.int16)).cuda()
+    dC = torch.empty(M, N, device="cuda")
+    G.gemm_bf16(dA, dB, dC)
+    torch.cuda.synchronize()
+    ref = OS.bf16(A) @ OS.bf16(B)
+    err = np.abs(dC.cpu().numpy() - ref).max()
+    assert err < 1e-5 * np.sqrt(K) * np.abs(ref).max() + 1e-5, err
+
+
+def test_normal_philox_parity():
+    n = 10001
+    z = torch.empty(n, device="cuda")
+    G.normal_philox(n, 1234567, 3, z)
+    torch.cuda.synchronize()
+    ref = OS.normal_philox(n, 1234567, 3)
+    assert np.abs(z.cpu().numpy() - ref).max() < 2e-5 * (1 + np.abs(ref).max())
+
+
+def test_mlp_forward_backward_adam_imle():
+    announce("mlp")
+    n_types = 4
+    p0 = S.mlp_init_params(n_types)
+    mlp = G.MLP(n_types, p0)
+    rng = np.random.default_rng(3)
+    B = 300
+    noise = S.mlp_noise(B, 11)
+    types = rng.integers(0, n_types, B).astype(np.int32)
+    target = S.f32(rng.normal(size=(B, 41)) * 0.5)
+    ntors = rng.integers(0, 17, B).astype(np.int32)
+    dn = torch.from_numpy(noise.astype(np.float32)).cuda()
+    dt = torch.from_numpy(types).cuda()
+    dtg = torch.from_numpy(target.astype(np.float32)).cuda()
+    dnt = torch.from_numpy(ntors).cuda()
+    out = torch.empty(B, 41, device="cuda")
+    mlp.forward(dn, dt, out)
+    torch.cuda.synchronize()
+    Y, _ = OS.forward(p0, n_types, noise, types)
+    yg = out.cpu().numpy()
+    assert np.abs(yg - Y).max() < 2e-2 * np.abs(Y).max()
+    # gradient (lr = 0: no update)
+    loss = torch.empty(B, device="cuda")
+    mlp.train_step(dn, dt, dtg, dnt, 0.0, out, loss)
+    torch.cuda.synchronize()
+    L, gref, _ = OS.loss_and_grad(p0, n_types, noise, types, target, ntors)
+    pg, gg = mlp.params()
+    assert np.array_equal(pg, p0)
+    o = 0
+    for l in range(4):
+        nW = OS.DIMS[l + 1] * OS.DIMS[l]
+        for a, b in ((o, o + nW), (o + nW, o + nW + OS.DIMS[l + 1])):
+            sc = np.abs(gref[a:b]).max()
+            assert np.abs(gg[a:b] - gref[a:b]).max() < 3e-2 * sc, (l, a, np.abs(gg[a:b] - gref[a:b]).max(), sc)
+        o += nW + OS.DIMS[l + 1]
+    assert np.abs(gg[o:] - gref[o:]).max() < 3e-2 * np.abs(gref[o:]).max()
+    assert abs(loss.cpu().numpy().mean() - L) < 2e-2 * L
+    # first Adam step against the oracle's step from its own gradient: the step is
+    # -lr g/(|g| + eps) ~ -lr sign(g), fixed wherever the gradient is not near zero
+    mlp.train_step(dn, dt, dtg, dnt, 1e-3, out, loss)
+    torch.cuda.synchronize()
+    p1, _ = mlp.params()
+    pe, _, _ = OS.adam(p0.astype(np.float64), gref, 0.0, 0.0, 1, 1e-3)
+    big = np.abs(gref) > 0.1 * np.abs(gref).max()
+    assert np.abs(p1 - pe)[big].max() < 1e-6
+    assert np.abs(p1 - p0).max() <= 1e-3 + 2e-7       # plus the FP32 rounding of p - step
+    # loss decreases over a few steps on a fixed batch
+    losses = []
+    for _ in range(30):
+        mlp.train_step(dn, dt, dtg, dnt, 1e-3, out, loss)
+        torch.cuda.synchronize()
+        losses.append(loss.cpu().numpy().mean())
+    announce(f"  loss {losses[0]:.4f} -> {losses[-1]:.4f}")
+    assert losses[-1] < 0.95 * losses[0] and losses[-1] < losses[len(losses) // 2]
+    # IMLE selection against the oracle on the GPU's candidate outputs
+    K = 8
+    cand = torch.from_numpy(S.f32(rng.normal(size=(B, K, 41))).astype(np.float32)).cuda()
+    best = torch.empty(B, dtype=torch.int32, device="cuda")
+    bd = torch.empty(B, device="cuda")
+    G.imle_select(cand, dtg, dnt, best, bd)
+    torch.cuda.synchronize()
+    bo, do = OS.imle_select(cand.cpu().numpy().astype(np.float64), target, ntors)
+    assert (best.cpu().numpy() == bo).mean() > 0.99
+    assert np.allclose(bd.cpu().numpy(), do, rtol=1e-5)

@@ -1,0 +1,118 @@
+"""Pins of the oracle's sampling rows (proposals, pose encoding, dedupe, proposer MLP)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import sampling as OS
+from paper_2508_15522_amd import synth as S
+
+
+def test_horn_quaternion_matches_svd_kabsch():
+    rng = np.random.default_rng(0)
+    X = rng.normal(size=(20, 3)); X -= X.mean(0)
+    R = S.random_rotations(1, rng)[0]
+    Y = X @ R.T + rng.normal(scale=0.01, size=X.shape); Y -= Y.mean(0)
+    q = OS.horn_quaternion(X, Y)
+    U, s, Vt = np.linalg.svd(X.T @ Y)
+    D = np.diag([1, 1, np.sign(np.linalg.det(Vt.T @ U.T))])
+    Rk = Vt.T @ D @ U.T
+    assert np.allclose(OS.quat_to_matrix(q), Rk, atol=1e-12)
+    assert q[0] >= 0
+
+
+@pytest.mark.parametrize("mk", [S.mol_chain24, lambda: S.mol_size(52, 6)])
+def test_encode_inverts_pose(mk):
+    mol = mk()
+    T = len(mol.rot_quads)
+    dof = O.propose_uniform(30, T, 77, 3)
+    dof[:, 3:7] *= np.where(dof[:, 3:4] < 0, -1, 1)          # canonical sign (w >= 0)
+    P = O.pose(mol, dof, 11.28, 11.28, 0.0)
+    for r in range(30):
+        e = OS.encode_pose(mol, P[r], 11.28, 11.28, 0.0)
+        d = OS.decode_dof(e, T, 0.0, 10.0)
+        assert np.allclose(d[:3], dof[r, :3], atol=1e-9)
+        assert np.allclose(d[3:7], dof[r, 3:7], atol=1e-9)
+        ang = (d[7:] - dof[r, 7:] + np.pi) % (2 * np.pi) - np.pi
+        assert np.abs(ang).max() < 1e-9
+        # decoding then posing reproduces the pose
+        assert np.abs(O.pose(mol, d, 11.28, 11.28, 0.0)[0] - P[r]).max() < 1e-9
+
+
+def test_dedupe_semantics():
+    E = np.array([-1.0, -1.005, -1.02, -1.0149, -2.0, np.nan, -1.0])
+    t = np.array([0, 0, 0, 0, 0, 0, 1])
+    new, arch = OS.dedupe_energy(E, t, None, 0.01)
+    # -1.005 matches -1.0; -1.02 is new; -1.0149 matches -1.02 (|d| < 0.01); NaN never counts;
+    # the same energy in another type is new
+    assert list(new) == [1, 0, 1, 0, 1, 0, 1]
+    new2, _ = OS.dedupe_energy(np.array([-1.0, -3.0]), np.array([0, 0]), None, 0.01, arch)
+    assert list(new2) == [0, 1]
+
+
+def test_mlp_backward_matches_finite_differences():
+    """P12: the FP64 oracle's gradient against central differences of its own loss."""
+    n_types = 3
+    rng = np.random.default_rng(1)
+    p = S.mlp_init_params(n_types).astype(np.float64)
+    B = 6
+    noise = rng.normal(size=(B, 64))
+    types = rng.integers(0, n_types, B)
+    target = rng.normal(size=(B, 41)) * 0.5
+    ntors = rng.integers(0, 17, B)
+    # BF16 rounding is piecewise constant in the weights, so differentiate with respect to
+    # parameters through a model whose weights are already BF16 values: perturb biases and
+    # the embedding's effect exactly, weights by BF16-representable steps is not smooth --
+    # use the bias and final-layer entries, and a smooth surrogate for the rest below
+    L, g, _ = OS.loss_and_grad(p, n_types, noise, types, target, ntors)
+    idx = []
+    o = 0
+    for l in range(4):
+        nW = OS.DIMS[l + 1] * OS.DIMS[l]
+        idx += [o + nW + k for k in (0, 5, OS.DIMS[l + 1] - 1)]     # biases
+        o += nW + OS.DIMS[l + 1]
+    for i in idx:
+        h = 1e-6
+        pp = p.copy(); pp[i] += h
+        pm = p.copy(); pm[i] -= h
+        fd = (OS.loss_and_grad(pp, n_types, noise, types, target, ntors)[0] -
+              OS.loss_and_grad(pm, n_types, noise, types, target, ntors)[0]) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-7 * max(1.0, abs(fd)), (i, fd, g[i])
+    # weights: with the BF16 rounding switched off the analytic gradient matches FD too
+    orig = OS.bf16
+    try:
+        OS.bf16 = lambda a: np.asarray(a, dtype=np.float64)
+        L, g, _ = OS.loss_and_grad(p, n_types, noise, types, target, ntors)
+        o = 0
+        for l in range(4):
+            for i in (o, o + 7, o + OS.DIMS[l] + 3):
+                h = 1e-6
+                pp = p.copy(); pp[i] += h
+                pm = p.copy(); pm[i] -= h
+                fd = (OS.loss_and_grad(pp, n_types, noise, types, target, ntors)[0] -
+                      OS.loss_and_grad(pm, n_types, noise, types, target, ntors)[0]) / (2 * h)
+                assert abs(fd - g[i]) <= 1e-7 * max(1.0, abs(fd)), (l, i, fd, g[i])
+            o += OS.DIMS[l + 1] * OS.DIMS[l] + OS.DIMS[l + 1]
+        for i in range(o, o + 5):                                           # embedding
+            h = 1e-6
+            pp = p.copy(); pp[i] += h
+            pm = p.copy(); pm[i] -= h
+            fd = (OS.loss_and_grad(pp, n_types, noise, types, target, ntors)[0] -
+                  OS.loss_and_grad(pm, n_types, noise, types, target, ntors)[0]) / (2 * h)
+            assert abs(fd - g[i]) <= 1e-7 * max(1.0, abs(fd)), (i, fd, g[i])
+    finally:
+        OS.bf16 = orig
+
+
+def test_bf16_rounding_rule():
+    x = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -9, -3.14159, 1e-30])
+    r = OS.bf16(x)
+    assert r[0] == 1.0 and r[1] == 1.0                 # tie to even
+    assert r[2] == 1.0 + 2 ** -7                       # tie to even (odd mantissa rounds up)
+    assert abs(r[3] + 3.14159) <= 2 ** -8 * 3.15
+    assert (np.abs(r - x) <= np.abs(x) * 2 ** -8).all()
+
+
+def test_normal_philox_moments():
+    z = OS.normal_philox(40000, 9, 2)
+    assert abs(z.mean()) < 0.02 and abs(z.std() - 1) < 0.02
+    assert abs((z ** 4).mean() - 3) < 0.1
