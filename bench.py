@@ -42,6 +42,9 @@ def main():
     ap.add_argument("--compare-f16", action="store_true", help="also time the FP16-grid variant")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--minima", action="store_true", help="learned vs uniform proposals: minima found per second")
+    ap.add_argument("--extra", nargs="*", default=[], choices=["c1", "c3", "c5"],
+                    help="also time the chain (c1), uneven-size (c3) or large-substrate (c5) workloads")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a 1 GiB device copy first (reference for HBM counter scaling)")
     args = ap.parse_args()
@@ -157,9 +160,75 @@ def main():
         res["f16_value"] = rs * args.steps / w16
         res["f16_kernel_avg_s"] = float(np.mean(p16))
         res["f16_vs_f32"] = res["f16_value"] / value
+    if args.minima:
+        from paper_2508_15522_amd import sampling as SM
+        log("learned vs uniform proposals (minima found per second)")
+        g32 = grid if args.storage == "f32" else setup(G.STORE_F32)
+        cmp = SM.compare_learned_vs_uniform(g32, S.mol_chain24(), collect_rounds=4, collect_rep=4096,
+                                            train_steps=300, eval_rounds=4, eval_rep=2048, log=log)
+        res["minima_per_s"] = {"learned": cmp["learned"]["minima_per_s"], "uniform": cmp["uniform"]["minima_per_s"],
+                               "gain": cmp["gain_minima_per_s"], "detail": cmp,
+                               "workload": "chain24 FIRE to 1e-4 eV/A (max 5000 steps), distinct within 0.01 eV"}
+    for extra in args.extra:
+        res.setdefault("other_workloads", {})[extra] = run_workload(extra, log)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(mol, cfg, args.cpu_seconds)
     print(json.dumps(res), flush=True)
+
+
+def run_workload(name, log):
+    """The other configurations, timed with HIP events around one relaxation launch."""
+    import torch
+    from paper_2508_15522_amd import autotune as AT, configs, device as D, gridff as G, synth as S
+    wl = {"c1": configs.C1_CHAIN_FIRE, "c3": configs.C3_SIZES_FIRE, "c5": configs.C5_PAH_FIRE_LARGE}[name]
+    cfg = wl.grid
+    sub = cfg.substrate()
+    spec = D.spec_for(cfg)
+    t0 = time.time()
+    grid = D.build_physical_grid(sub, spec, G.STORE_F32)
+    torch.cuda.synchronize()
+    build_s = time.time() - t0
+    mols = S.molecule_types(wl.molecules)
+    rep_type = np.arange(wl.n_rep) % len(mols)
+    pos = []
+    for t, m in enumerate(mols):
+        k = int((rep_type == t).sum())
+        pos.append(S.place_replicas(m, k, sub, S.SEED_PLACE * (3 if name == "c3" else 1) + t))
+    it = [iter(p) for p in pos]
+    per_rep = [next(it[t]) for t in rep_type]
+    topo = G.Topology(mols)
+    prm = G.relax_params(G.MODE_FIRE, wl.n_steps, True, f_conv=1e-4)
+    launch = (256, 0, 0)
+    tuned = None
+    if name == "c3":
+        plan0 = G.Plan(topo, rep_type)
+        st = D.fire_state(plan0, per_rep)
+        tune_prm = G.relax_params(G.MODE_FIRE, 50, True, f_conv=1e-4)
+        launch, tuned = AT.launch_for(grid, topo, rep_type, tune_prm, st, use_cache=False)
+        log(f"c3 autotuned launch {launch} ({tuned:.3e} replica-steps/s on 50 steps)")
+    plan = G.Plan(topo, rep_type, *launch)
+    st = D.fire_state(plan, per_rep)
+    out = D.outputs(plan)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    e0.record(stream)
+    G.relax_batch(grid.desc, topo, plan, prm, st, out["E"], out["fnorm"], out["steps"], None, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    secs = e0.elapsed_time(e1) / 1e3
+    steps = out["steps"].cpu().numpy()
+    status = st["status"].cpu().numpy()
+    moves = int(steps.sum())
+    r = {"workload": wl.name, "replicas": wl.n_rep, "types": [m.n for m in mols], "max_steps": wl.n_steps,
+         "seconds": secs, "replica_steps_per_s_moves": moves / secs,
+         "replica_steps_per_s_launch": wl.n_rep * wl.n_steps / secs,
+         "converged": int(((status & G.REP_CONVERGED) != 0).sum()), "grid_build_fit_s": build_s,
+         "grid": f"{cfg.nx}x{cfg.ny}x{cfg.nz}x3 f32", "substrate_atoms": sub.n, "launch": list(launch)}
+    if tuned is not None:
+        r["autotune_rate"] = tuned
+    log(f"{name}: {r}")
+    return r
 
 
 def cpu_baseline(mol, cfg, budget_s):

@@ -243,6 +243,26 @@ gff_status gff_relax_batch(const gff_grid *grid, const gff_topology *topo, const
                            double *d_E_rep, float *d_fnorm_rep, int *d_steps_rep,
                            double *d_drift_rep, void *stream);
 
+/* ------------------------------------------------------------------ graphs and autotuning */
+
+/* One relaxation launch captured as a HIP graph (arguments and buffers fixed at capture);
+ * every gff_graph_launch re-runs it on the same buffers, continuing from their current
+ * contents.  The graph holds no memset nodes. */
+typedef struct gff_graph_s gff_graph;
+gff_status gff_relax_graph_create(const gff_grid *grid, const gff_topology *topo, const gff_plan *plan,
+                                  const gff_relax_params *params, const gff_state *state, double *d_E_rep,
+                                  float *d_fnorm_rep, int *d_steps_rep, double *d_drift_rep, gff_graph **out);
+gff_status gff_graph_launch(gff_graph *graph, void *stream);
+void gff_graph_destroy(gff_graph *graph);
+
+/* Measured launch shape for a batch (setup step: allocates scratch and synchronises): runs
+ * `params` for every block size 64..1024 (multiple of 64, >= the largest molecule) with the
+ * default grid and with persistent grids of 1-4 blocks per compute unit, on copies of
+ * `state`; returns the fastest shape and its replica-steps/s (nullable). */
+gff_status gff_autotune(const gff_grid *grid, const gff_topology *topo, int n_rep, const int *rep_type_h,
+                        const gff_relax_params *params, const gff_state *state, gff_launch *best,
+                        float *best_rate, void *stream);
+
 /* ------------------------------------------------------------------ proposals and minima */
 
 /* Degrees of freedom per replica, float [n][7 + T]: u, v (lateral centroid as fractions of the

@@ -24,11 +24,14 @@ struct GridView {
     int nx, ny, nzp;                     // nzp = nz + 3 padded planes
     float s0, s1, s2;                    // per-channel decode scales (filled on the device)
     const float *scale;                  // F16: device scales [4]; NULL for F32
+    unsigned bytes;                      // size of the coefficient array
+    __amdgpu_buffer_rsrc_t rsrc;         // buffer resource over the coefficients (device side)
 };
 
 // Decode scales of an F16 grid are read on the device (no host round trip).
 __device__ __forceinline__ void fetch_scales(GridView &g) {
     if (g.scale) { g.s0 = g.scale[0]; g.s1 = g.scale[1]; g.s2 = g.scale[2]; }
+    g.rsrc = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(g.coef), (short)0, (int)g.bytes, 0x00020000);
 }
 
 struct KArgs {
@@ -93,6 +96,20 @@ __device__ __forceinline__ int wrap_index(float q, int n) {
     int i = (int)fminf(fmaxf(q, -1073741824.f), 1073741824.f);
     if (i < 0 || i >= n) { i %= n; if (i < 0) i += n; }
     return i;
+}
+
+template <int STORE>
+__device__ __forceinline__ float4 load_node_buf(__amdgpu_buffer_rsrc_t r, int off) {
+    if constexpr (STORE == GFF_STORE_F32) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b96(r, off, 0, 0);
+        return make_float4(__uint_as_float(v[0]), __uint_as_float(v[1]), __uint_as_float(v[2]), 0.f);
+    } else {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+        const unsigned lo = v[0], hi = v[1];
+        __half2 a = *reinterpret_cast<const __half2 *>(&lo), b = *reinterpret_cast<const __half2 *>(&hi);
+        const float2 fa = __half22float2(a), fb = __half22float2(b);
+        return make_float4(fa.x, fa.y, fb.x, 0.f);
+    }
 }
 
 // Grid energy E = P V^P + L V^L + Q V^C at (x,y,z) and its gradient.  Channels are
@@ -217,13 +234,18 @@ __device__ __forceinline__ float4 quad_gather(const GridView &g, GridKey key, fl
         jy[0] = (j == 0 ? g.ny : j) - 1; jy[1] = j;
         jy[2] = (j + 1 == g.ny) ? 0 : j + 1; jy[3] = (j + 2 >= g.ny) ? j + 2 - g.ny : j + 2;
         const float Ps = P * g.s0, Ls = L * g.s1, Qs = Q * g.s2;
-        const int kk = key.k + s;
+        // 32-bit byte offsets into a buffer resource (out-of-range offsets would read 0)
+        constexpr int NB = STORE == GFF_STORE_F32 ? 16 : 8;
+        const int col_stride = g.nzp * NB;
+        int yoff[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) yoff[b] = jy[b] * col_stride + (key.k + s) * NB;
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
-            const int row = ix[a] * g.ny;
+            const int xoff = ix[a] * g.ny * col_stride;
             float4 c[4];
 #pragma unroll
-            for (int b = 0; b < 4; ++b) c[b] = load_node<STORE>(g.coef, (row + jy[b]) * g.nzp + kk);
+            for (int b = 0; b < 4; ++b) c[b] = load_node_buf<STORE>(g.rsrc, xoff + yoff[b]);
             float yv = 0.f, yy = 0.f;
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
@@ -618,13 +640,15 @@ static gff_status make_view(const gff_grid *gr, GridView &g) {
     if (gr->storage != GFF_STORE_F32 && gr->storage != GFF_STORE_F16) return GFF_EUNSUPPORTED;
     if (gr->nx < 4 || gr->ny < 4 || gr->nz < 4) return GFF_EINVAL;
     if (!(gr->dx > 0.f && gr->dy > 0.f && gr->dz > 0.f)) return GFF_EINVAL;
-    if ((double)gr->nx * gr->ny * (gr->nz + 3) >= 2147483647.0) return GFF_EUNSUPPORTED;
     g.coef = gr->d_coef;
     g.x0 = gr->x0; g.y0 = gr->y0; g.z0 = gr->z0;
     g.idx = 1.f / gr->dx; g.idy = 1.f / gr->dy; g.idz = 1.f / gr->dz;
     g.dx = gr->dx; g.dy = gr->dy; g.dz = gr->dz;
     g.zmax = (float)(gr->nz - 1);
     g.nx = gr->nx; g.ny = gr->ny; g.nzp = gr->nz + 3;
+    const double bytes = (double)gr->nx * gr->ny * (gr->nz + 3) * (gr->storage == GFF_STORE_F32 ? 16 : 8);
+    if (bytes >= 2147483647.0) return GFF_EUNSUPPORTED;    // 32-bit buffer offsets
+    g.bytes = (unsigned)bytes;
     g.s0 = g.s1 = g.s2 = 1.f;
     g.scale = nullptr;
     if (gr->storage == GFF_STORE_F16) {

@@ -255,7 +255,7 @@ def relax_batch(grid_desc, topo, plan, params, st, d_E_rep, d_fnorm, d_steps, d_
 EXPORTS += ["gff_propose_uniform", "gff_pose_from_dof", "gff_encode_pose", "gff_decode_dof", "gff_dedupe_energy",
             "gff_mlp_n_params", "gff_mlp_create", "gff_mlp_destroy", "gff_mlp_get_params", "gff_mlp_workspace_bytes",
             "gff_mlp_forward", "gff_mlp_train_step", "gff_imle_select", "gff_normal_philox", "gff_gemm_bf16",
-            "gff_gather_rows"]
+            "gff_gather_rows", "gff_relax_graph_create", "gff_graph_launch", "gff_graph_destroy", "gff_autotune"]
 N_ENC = 41
 
 
@@ -356,3 +356,40 @@ def gather_rows(d_src, K, d_idx, d_dst, stream=None):
     n, ln = d_dst.shape[0], d_dst.shape[-1]
     check(lib().gff_gather_rows(C.c_int(n), C.c_int(ln), _ptr(d_src), C.c_int(K), _ptr(d_idx), _ptr(d_dst),
                                 _stream(stream)))
+
+
+class RelaxGraph:
+    """A captured relaxation launch (fixed buffers); launch() re-runs it."""
+
+    def __init__(self, grid_desc, topo, plan, params, st, d_E_rep, d_fnorm, d_steps, d_drift=None):
+        self.state = State(st["pos"].data_ptr(), st["vel"].data_ptr(),
+                           st["fire_dt"].data_ptr() if "fire_dt" in st else None,
+                           st["fire_alpha"].data_ptr() if "fire_alpha" in st else None,
+                           st["fire_npos"].data_ptr() if "fire_npos" in st else None, st["status"].data_ptr())
+        self.keep = (grid_desc, topo, plan, params, st, d_E_rep, d_fnorm, d_steps, d_drift)
+        self.handle = C.c_void_p()
+        check(lib().gff_relax_graph_create(C.byref(grid_desc), topo.handle, plan.handle, C.byref(params),
+                                           C.byref(self.state), _ptr(d_E_rep), _ptr(d_fnorm), _ptr(d_steps),
+                                           _ptr(d_drift), C.byref(self.handle)))
+
+    def launch(self, stream=None):
+        check(lib().gff_graph_launch(self.handle, _stream(stream)))
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.gff_graph_destroy(self.handle)
+            self.handle = None
+
+
+def autotune(grid_desc, topo, rep_type, params, st, stream=None):
+    """Measured launch shape -> (Launch, replica-steps/s)."""
+    rt = np.ascontiguousarray(rep_type, dtype=np.int32)
+    state = State(st["pos"].data_ptr(), st["vel"].data_ptr(),
+                  st["fire_dt"].data_ptr() if "fire_dt" in st else None,
+                  st["fire_alpha"].data_ptr() if "fire_alpha" in st else None,
+                  st["fire_npos"].data_ptr() if "fire_npos" in st else None, st["status"].data_ptr())
+    best = Launch()
+    rate = C.c_float()
+    check(lib().gff_autotune(C.byref(grid_desc), topo.handle, C.c_int(len(rt)), rt.ctypes.data_as(C.c_void_p),
+                             C.byref(params), C.byref(state), C.byref(best), C.byref(rate), _stream(stream)))
+    return best, rate.value

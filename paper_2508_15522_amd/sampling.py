@@ -140,3 +140,50 @@ def train_imle(mlp, targets, ntors, types, steps, batch=1024, K=16, lr=1e-3, see
             if log:
                 log(f"imle step {s}: loss {hist[-1][1]:.4f}")
     return hist
+
+
+def compare_learned_vs_uniform(grid, mol, collect_rounds=6, collect_rep=4096, train_steps=400, eval_rounds=6,
+                               eval_rep=1024, seed=S.SEED_PHILOX, log=None):
+    """Collect minima with uniform proposals, train the proposer on the distinct ones, then
+    run equal numbers of proposals with each method against fresh archives.  Returns a
+    dict of counts, wall times, minima/s and mean FIRE steps per converged minimum."""
+    say = log or (lambda m: None)
+    col = Sampler(grid, mol, collect_rep, seed=seed)
+    arch = Archive()
+    targets = []
+    t0 = time.time()
+    for r in range(collect_rounds):
+        rs = col.round_uniform(arch, r, keep_new=True)
+        pos, newh = rs.new_pos[0]
+        if newh.any():
+            targets.append(col.encode_minima(pos, newh))
+        say(f"collect round {r}: converged {rs.converged}/{rs.proposals}, new {rs.new_minima}, "
+            f"mean steps {rs.fire_steps_converged:.0f}, {rs.seconds:.2f} s")
+    collect_s = time.time() - t0
+    tg = torch.cat(targets, 0).contiguous()
+    m = tg.shape[0]
+    ntors = torch.full((m,), len(mol.rot_quads), dtype=torch.int32, device="cuda")
+    types = torch.zeros(m, dtype=torch.int32, device="cuda")
+    mlp = G.MLP(1, S.mlp_init_params(1))
+    t0 = time.time()
+    hist = train_imle(mlp, tg, ntors, types, train_steps, batch=min(1024, max(64, m)), log=say)
+    torch.cuda.synchronize()
+    train_s = time.time() - t0
+    ev = Sampler(grid, mol, eval_rep, seed=seed + 17)
+    res = {}
+    for name in ("uniform", "learned"):
+        a = Archive()
+        secs, conv, props, steps = 0.0, 0, 0, []
+        for r in range(eval_rounds):
+            rs = ev.round_uniform(a, 1000 + r) if name == "uniform" else ev.round_learned(a, mlp, 1000 + r)
+            secs += rs.seconds; conv += rs.converged; props += rs.proposals
+            steps.append(rs.fire_steps_converged)
+        n_min = a.count()
+        res[name] = dict(distinct_minima=n_min, proposals=props, converged=conv, seconds=secs,
+                         minima_per_s=n_min / secs, mean_fire_steps=float(np.nanmean(steps)))
+        say(f"{name}: {n_min} distinct minima from {props} proposals ({conv} converged) in {secs:.2f} s, "
+            f"mean FIRE steps {res[name]['mean_fire_steps']:.0f}")
+    res["training"] = dict(minima=m, steps=train_steps, loss_first=hist[0][1], loss_last=hist[-1][1],
+                           collect_s=collect_s, train_s=train_s)
+    res["gain_minima_per_s"] = res["learned"]["minima_per_s"] / max(res["uniform"]["minima_per_s"], 1e-12)
+    return res
