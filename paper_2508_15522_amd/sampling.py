@@ -4,7 +4,8 @@ Each round: proposals (uniform Philox DOF, or the MLP's output from Philox noise
 decoded) -> poses -> FIRE relaxation to |F| < f_conv in one persistent launch -> energy
 dedupe of the converged minima against the method's archive.  The sampling loop of the
 paper perturbs replicas with Langevin dynamics before relaxing (Section "Configuration
-sampling on GPU"); here proposals are drawn directly and the relaxation is the judge.
+sampling on GPU"); here proposals are drawn directly and relaxed, and the relaxation
+decides which of them end in minima.
 Training (IMLE): the distinct minima are encoded; for each training minimum K noise rows
 are decoded by the network, the nearest output is kept and a step on it follows.
 Every numerical step is a libgridff call; this module only sequences them.
