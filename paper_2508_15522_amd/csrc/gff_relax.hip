@@ -212,53 +212,66 @@ __device__ __forceinline__ GridKey grid_key(const GridView &g, float x, float y,
     return key;
 }
 
-// Quad side: lane s of the quad loads node k-1+s of each of the 16 columns (so the quad
-// reads each column as one contiguous 64-byte (F32) / 32-byte (F16) segment), mixes the
-// channels and accumulates its share of the tensor-product contraction; the quad sum is
-// the atom's energy and gradient (in grid units).
+// Quad side, fetch: lane s of the quad loads node k-1+s of each of the 16 columns (so the
+// quad reads each column as one contiguous 64-byte (F32) / 32-byte (F16) segment) and
+// mixes the channels with the atom's (P, L, Q): m[4a+b] is the mixed coefficient of
+// column (i-1+a, j-1+b) on the lane's plane.
 template <int STORE>
-__device__ __forceinline__ float4 quad_gather(const GridView &g, GridKey key, float4 t, float P, float L, float Q,
-                                              int s) {
+__device__ __forceinline__ void quad_fetch(const GridView &g, GridKey key, float P, float L, float Q, int s,
+                                           float m[16]) {
+    const int i = key.i, j = key.j;
+    int ix[4], jy[4];
+    ix[0] = (i == 0 ? g.nx : i) - 1; ix[1] = i;
+    ix[2] = (i + 1 == g.nx) ? 0 : i + 1; ix[3] = (i + 2 >= g.nx) ? i + 2 - g.nx : i + 2;
+    jy[0] = (j == 0 ? g.ny : j) - 1; jy[1] = j;
+    jy[2] = (j + 1 == g.ny) ? 0 : j + 1; jy[3] = (j + 2 >= g.ny) ? j + 2 - g.ny : j + 2;
+    const float Ps = P * g.s0, Ls = L * g.s1, Qs = Q * g.s2;
+    // 32-bit byte offsets into a buffer resource (out-of-range offsets would read 0)
+    constexpr int NB = STORE == GFF_STORE_F32 ? 16 : 8;
+    const int col_stride = g.nzp * NB;
+    int yoff[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) yoff[b] = jy[b] * col_stride + (key.k + s) * NB;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        const int xoff = ix[a] * g.ny * col_stride;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const float4 c = load_node_buf<STORE>(g.rsrc, xoff + yoff[b]);
+            m[4 * a + b] = Ps * c.x + Ls * c.y + Qs * c.z;
+        }
+    }
+}
+
+// Quad side, contraction: the lane's share of the tensor-product sum over its plane; the
+// quad sum is the atom's energy and gradient (in grid units).  The z weights enter once
+// per lane: E = sum_s wz[s] (...), dE/dz = sum_s dz[s] (...).
+__device__ __forceinline__ float4 quad_contract(const float m[16], float4 t, int s, bool valid) {
     float E = 0.f, Ex = 0.f, Ey = 0.f, Ez = 0.f;
-    if (key.valid) {
+    if (valid) {
         float wx[4], dx[4], wy[4], dy[4], wz[4], dz[4];
         bspline_weights(t.x, wx, dx);
         bspline_weights(t.y, wy, dy);
         bspline_weights(t.z, wz, dz);
         const float wzs = s == 0 ? wz[0] : (s == 1 ? wz[1] : (s == 2 ? wz[2] : wz[3]));
         const float dzs = s == 0 ? dz[0] : (s == 1 ? dz[1] : (s == 2 ? dz[2] : dz[3]));
-        const int i = key.i, j = key.j;
-        int ix[4], jy[4];
-        ix[0] = (i == 0 ? g.nx : i) - 1; ix[1] = i;
-        ix[2] = (i + 1 == g.nx) ? 0 : i + 1; ix[3] = (i + 2 >= g.nx) ? i + 2 - g.nx : i + 2;
-        jy[0] = (j == 0 ? g.ny : j) - 1; jy[1] = j;
-        jy[2] = (j + 1 == g.ny) ? 0 : j + 1; jy[3] = (j + 2 >= g.ny) ? j + 2 - g.ny : j + 2;
-        const float Ps = P * g.s0, Ls = L * g.s1, Qs = Q * g.s2;
-        // 32-bit byte offsets into a buffer resource (out-of-range offsets would read 0)
-        constexpr int NB = STORE == GFF_STORE_F32 ? 16 : 8;
-        const int col_stride = g.nzp * NB;
-        int yoff[4];
-#pragma unroll
-        for (int b = 0; b < 4; ++b) yoff[b] = jy[b] * col_stride + (key.k + s) * NB;
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
-            const int xoff = ix[a] * g.ny * col_stride;
-            float4 c[4];
-#pragma unroll
-            for (int b = 0; b < 4; ++b) c[b] = load_node_buf<STORE>(g.rsrc, xoff + yoff[b]);
             float yv = 0.f, yy = 0.f;
 #pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const float m = Ps * c[b].x + Ls * c[b].y + Qs * c[b].z;
-                yv += wy[b] * m; yy += dy[b] * m;
-            }
+            for (int b = 0; b < 4; ++b) { yv += wy[b] * m[4 * a + b]; yy += dy[b] * m[4 * a + b]; }
             E += wx[a] * yv; Ex += dx[a] * yv; Ey += wx[a] * yy;
         }
-        // z weights enter once per lane: E = sum_s wz[s] (...), dE/dz = sum_s dz[s] (...)
         Ez = E * dzs;
         E *= wzs; Ex *= wzs; Ey *= wzs;
     }
     return make_float4(quad_sum(E), quad_sum(Ex), quad_sum(Ey), quad_sum(Ez));
+}
+
+// Linear index of the stencil's base node, the key of a cached stencil (-1: no stencil).
+// It fits in an int: the coefficient array is addressed with 32-bit byte offsets.
+__device__ __forceinline__ int stencil_id(const GridView &g, int4 ki) {
+    return ki.w ? (ki.x * g.ny + ki.y) * g.nzp + ki.z : -1;
 }
 
 // Non-bonded pairs of this lane's atom (more than two bonds apart): Morse with depth
@@ -355,8 +368,11 @@ __device__ __forceinline__ float torsion_term(const TorDef td, const float4 *sp,
     return 0.5f * td.V * (1.f - carg);
 }
 
-template <int STORE, int MODE>
-__global__ void __launch_bounds__(1024) k_replicas(KArgs A) {
+// CACHE: keep each lane's four pre-mixed stencil planes (64 values) in registers from step
+// to step; this needs blocks of at most 512 threads (up to 256 registers per lane).
+template <int STORE, int MODE, bool CACHE>
+__global__ void __launch_bounds__(CACHE ? 512 : 1024) __attribute__((amdgpu_waves_per_eu(CACHE ? 3 : 1)))
+k_replicas(KArgs A) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int BT = blockDim.x, tid = threadIdx.x;
     // LDS, one float4 slot per lane in each array:
@@ -420,6 +436,8 @@ __global__ void __launch_bounds__(1024) k_replicas(KArgs A) {
         const bool entered_conv = (st & GFF_REP_CONVERGED) != 0;
         bool live = active && !(st & GFF_REP_NONFINITE);
         double dr0 = 0, dr1 = 0, dr2 = 0, dr3 = 0, dr4 = 0, dr5 = 0;   // reducer lane: drift record
+        float cm[4][16];                        // cached pre-mixed stencil planes (CACHE)
+        int cid[4] = {-1, -1, -1, -1};          // their stencil ids (-1: none)
 
         const int total = (MODE == MODE_EVAL) ? 0 : A.n_steps;
         for (int it = 0; it <= total; ++it) {
@@ -447,14 +465,38 @@ __global__ void __launch_bounds__(1024) k_replicas(KArgs A) {
                 s_gi[tid] = make_int4(key.i, key.j, key.k, key.valid);
                 s_gt[tid] = t;
                 wave_sync();
+                if constexpr (CACHE) {
+                    // stencils stay in registers across steps; a quad reloads its plane
+                    // only when its atom has moved to another cell
+#pragma unroll
+                    for (int rnd = 0; rnd < 4; ++rnd) {
+                        const int o = wb + 16 * rnd + (wl >> 2);
+                        const int4 ki = s_gi[o];
+                        const float4 ko = s_gt[o];
+                        const int id = stencil_id(gv, ki);
+                        if (id != cid[rnd]) {
+                            if (id >= 0) {
+                                const float4 po = s_plq[o];
+                                quad_fetch<STORE>(gv, GridKey{ki.x, ki.y, ki.z, ki.w}, po.x, po.y, po.z, quad_s,
+                                                  cm[rnd]);
+                            }
+                            cid[rnd] = id;
+                        }
+                        const float4 r = quad_contract(cm[rnd], ko, quad_s, id >= 0);
+                        if (quad_s == 0) s_gres[o] = r;
+                    }
+                } else {
 #pragma unroll 1
-                for (int rnd = 0; rnd < 4; ++rnd) {
-                    const int o = wb + 16 * rnd + (wl >> 2);
-                    const int4 ki = s_gi[o];
-                    const float4 ko = s_gt[o];
-                    const float4 po = s_plq[o];
-                    const float4 r = quad_gather<STORE>(gv, GridKey{ki.x, ki.y, ki.z, ki.w}, ko, po.x, po.y, po.z, quad_s);
-                    if (quad_s == 0) s_gres[o] = r;
+                    for (int rnd = 0; rnd < 4; ++rnd) {
+                        const int o = wb + 16 * rnd + (wl >> 2);
+                        const int4 ki = s_gi[o];
+                        const float4 ko = s_gt[o];
+                        const float4 po = s_plq[o];
+                        float m[16];
+                        if (ki.w) quad_fetch<STORE>(gv, GridKey{ki.x, ki.y, ki.z, ki.w}, po.x, po.y, po.z, quad_s, m);
+                        const float4 r = quad_contract(m, ko, quad_s, ki.w != 0);
+                        if (quad_s == 0) s_gres[o] = r;
+                    }
                 }
                 wave_sync();
                 const float4 r = s_gres[tid];
@@ -667,22 +709,30 @@ static void fill_common(KArgs &A, const gff_topology *topo, const gff_plan *plan
     A.n_packs = plan->n_packs; A.N = plan->n_atoms; A.tres_max = plan->tres_max;
 }
 
+template <int STORE, int MODE, bool CACHE>
+static void launch_one(int grid, int BT, size_t lds, const KArgs &A, hipStream_t s) {
+    if (lds > 65536)
+        (void)hipFuncSetAttribute((const void *)k_replicas<STORE, MODE, CACHE>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((k_replicas<STORE, MODE, CACHE>), dim3(grid), dim3(BT), lds, s, A);
+}
+
+// Relaxation and MD launches keep stencils in registers when the block fits the cached
+// variant's register budget (<= 512 threads); single evaluations never reuse a stencil.
 template <int MODE>
 static gff_status launch_mode(const gff_grid *gr, const gff_plan *plan, KArgs &A, hipStream_t s) {
     const int BT = plan->block_threads;
     const size_t lds = (size_t)BT * (5 * 16 + 4) + (size_t)plan->tres_max * 32 + 16;
     const int grid = plan->grid_blocks > 0 ? std::min(plan->grid_blocks, plan->n_packs) : plan->n_packs;
     if (grid <= 0) return GFF_OK;
+    constexpr bool can_cache = MODE != MODE_EVAL;
+    const bool cache = can_cache && BT <= 512;
     if (gr->storage == GFF_STORE_F32) {
-        if (lds > 65536)
-            (void)hipFuncSetAttribute((const void *)k_replicas<GFF_STORE_F32, MODE>,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL((k_replicas<GFF_STORE_F32, MODE>), dim3(grid), dim3(BT), lds, s, A);
+        if (cache) launch_one<GFF_STORE_F32, MODE, can_cache>(grid, BT, lds, A, s);
+        else launch_one<GFF_STORE_F32, MODE, false>(grid, BT, lds, A, s);
     } else {
-        if (lds > 65536)
-            (void)hipFuncSetAttribute((const void *)k_replicas<GFF_STORE_F16, MODE>,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL((k_replicas<GFF_STORE_F16, MODE>), dim3(grid), dim3(BT), lds, s, A);
+        if (cache) launch_one<GFF_STORE_F16, MODE, can_cache>(grid, BT, lds, A, s);
+        else launch_one<GFF_STORE_F16, MODE, false>(grid, BT, lds, A, s);
     }
     return hip_status(hipGetLastError());
 }
