@@ -209,13 +209,13 @@ extern "C" gff_status gff_plan_create(const gff_topology *topo, int n_rep, const
     if (lane_lds >= lds_limit) return GFF_EUNSUPPORTED;
     std::vector<int4> packs;
     std::vector<int> reps;
-    int tres_max = 0;
+    int tres_max = 0, max_pack_reps = 0;
     for (int t : order) {
         const int n = topo->natoms[t];
         int rpb = BT / n;
         if (rpb_cap > 0) rpb = std::min(rpb, rpb_cap);
         if (topo->ntors[t] > 0 && !by_type[t].empty()) {
-            const long fit = (lds_limit - lane_lds) / (32L * topo->ntors[t]);
+            const long fit = (lds_limit - lane_lds - 48L * rpb) / (32L * topo->ntors[t]);
             if (fit < 1) return GFF_EUNSUPPORTED;
             rpb = (int)std::min<long>(rpb, fit);
         }
@@ -224,12 +224,15 @@ extern "C" gff_status gff_plan_create(const gff_topology *topo, int n_rep, const
         for (size_t s = 0; s < L.size(); s += rpb) {
             const int cnt = (int)std::min<size_t>(rpb, L.size() - s);
             packs.push_back(make_int4(t, cnt, (int)reps.size(), 0));
+            max_pack_reps = std::max(max_pack_reps, cnt);
             for (int k = 0; k < cnt; ++k) reps.push_back(L[s + k]);
         }
     }
     auto *P = new gff_plan_s();
     P->n_rep = n_rep; P->n_atoms = atom_off[n_rep]; P->n_packs = (int)packs.size();
     P->block_threads = BT; P->grid_blocks = grid; P->max_n = max_n; P->tres_max = tres_max;
+    P->max_pack_reps = max_pack_reps;
+    if ((long)replica_lds_bytes(BT, tres_max, max_pack_reps) > lds_limit) { delete P; return GFF_EUNSUPPORTED; }
     P->atom_off_h = atom_off;
     P->rep_type_h.assign(rep_type_h, rep_type_h + n_rep);
     std::vector<void *> owned;

@@ -62,6 +62,7 @@ struct gff_plan_s {
     int n_rep, n_atoms, n_packs;
     int block_threads, grid_blocks, max_n;
     int tres_max;              // largest (replicas per pack) x (torsion terms) of the batch
+    int max_pack_reps;         // largest number of replicas in one pack
     int4 *d_packs;             // type, replicas in pack, first entry in d_pack_reps, pad
     int *d_pack_reps;          // replica ids in pack order
     int *d_atom_off;           // [n_rep+1]
@@ -72,4 +73,10 @@ struct gff_plan_s {
 
 namespace gff {
 inline gff_status hip_status(hipError_t e) { return e == hipSuccess ? GFF_OK : GFF_EHIP; }
+}
+
+// Dynamic LDS of the replica kernel: five float4 slots and one int per lane, two float4 per
+// (replica, torsion term), six doubles of NVE drift record per replica, two flag words.
+inline size_t replica_lds_bytes(int block_threads, int tres_max, int max_pack_reps) {
+    return (size_t)block_threads * (5 * 16 + 4) + (size_t)tres_max * 32 + (size_t)max_pack_reps * 48 + 16;
 }

@@ -39,7 +39,7 @@ struct KArgs {
     DevTopo t;
     float alpha_l2e, alpha, ke;
     const int4 *packs; const int *pack_reps; const int *atom_off;
-    int n_packs, N, tres_max;
+    int n_packs, N, tres_max, max_pack_reps;
     float *pos, *vel;
     float *fdt, *falpha; int *fnpos; unsigned *status;
     float *F; float *E_atom; double *E_rep; float *fnorm; int *steps; double *drift;
@@ -190,6 +190,18 @@ __device__ __forceinline__ float quad_sum(float v) {
     return v;
 }
 
+__device__ __forceinline__ double quad_sum(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    int lo = (int)(unsigned)b, hi = (int)(unsigned)(b >> 32);
+    v += __longlong_as_double((long long)(((unsigned long long)(unsigned)__builtin_amdgcn_update_dpp(0, hi, 0xB1, 0xF, 0xF, false) << 32) |
+                                          (unsigned)__builtin_amdgcn_update_dpp(0, lo, 0xB1, 0xF, 0xF, false)));
+    const unsigned long long c = (unsigned long long)__double_as_longlong(v);
+    lo = (int)(unsigned)c; hi = (int)(unsigned)(c >> 32);
+    v += __longlong_as_double((long long)(((unsigned long long)(unsigned)__builtin_amdgcn_update_dpp(0, hi, 0x4E, 0xF, 0xF, false) << 32) |
+                                          (unsigned)__builtin_amdgcn_update_dpp(0, lo, 0x4E, 0xF, 0xF, false)));
+    return v;
+}
+
 // Hand-off of one atom's grid lookup: owner lane -> the quad that gathers for it.
 struct GridKey { int i, j, k, valid; };
 
@@ -315,9 +327,9 @@ __device__ __forceinline__ float bond_angle_terms(const KArgs &A, const float4 *
     for (int b = ia.x; b < ia.x + ia.y; ++b) {
         const BondInc bi = A.t.bnd[b];
         const float3 d = xi - f3(sp[rbase + bi.other]);
-        const float r = sqrtf(dot(d, d));
-        const float dr = r - bi.r0;
-        const float g = bi.k * dr / r;
+        const float d2 = dot(d, d), rinv = __builtin_amdgcn_rsqf(d2);
+        const float dr = d2 * rinv - bi.r0;
+        const float g = bi.k * dr * rinv;
         fx -= g * d.x; fy -= g * d.y; fz -= g * d.z;
         if (bi.slot == 0) e += 0.5f * bi.k * dr * dr;
     }
@@ -329,8 +341,8 @@ __device__ __forceinline__ float bond_angle_terms(const KArgs &A, const float4 *
         const float inv = __builtin_amdgcn_rsqf(uu * vv);
         const float cs = dot(u, v) * inv;
         const float de = ai.k * (cs - ai.cos0);
-        const float3 ga = inv * v - (cs / uu) * u;
-        const float3 gc = inv * u - (cs / vv) * v;
+        const float3 ga = inv * v - (cs * __builtin_amdgcn_rcpf(uu)) * u;
+        const float3 gc = inv * u - (cs * __builtin_amdgcn_rcpf(vv)) * v;
         float3 gs = ai.slot == 0 ? ga : (ai.slot == 2 ? gc : make_float3(-ga.x - gc.x, -ga.y - gc.y, -ga.z - gc.z));
         fx -= de * gs.x; fy -= de * gs.y; fz -= de * gs.z;
         if (ai.slot == 0) e += 0.5f * ai.k * (cs - ai.cos0) * (cs - ai.cos0);
@@ -352,7 +364,7 @@ __device__ __forceinline__ float torsion_term(const TorDef td, const float4 *sp,
         oA = make_float4(0.f, 0.f, 0.f, 0.f); oB = oA;
         return 0.f;
     }
-    const float lb = sqrtf(bb);
+    const float ibb = __builtin_amdgcn_rcpf(bb), lb = bb * __builtin_amdgcn_rsqf(bb);
     const float inv = __builtin_amdgcn_rsqf(m2 * n2);
     const float c1 = dot(mm, nn) * inv, s1 = lb * dot(b1, nn) * inv;    // cos phi, sin phi
     float cn = c1, sn = s1;
@@ -362,9 +374,9 @@ __device__ __forceinline__ float torsion_term(const TorDef td, const float4 *sp,
     }
     const float carg = cn * td.c0 + sn * td.s0, sarg = sn * td.c0 - cn * td.s0;
     const float dEdphi = 0.5f * td.V * (float)td.n * sarg;
-    const float fa = dEdphi * lb / m2, fb = -dEdphi * lb / n2;           // A = fa mm, B = fb nn
-    oA = make_float4(fa * mm.x, fa * mm.y, fa * mm.z, dot(b1, b2) / bb);
-    oB = make_float4(fb * nn.x, fb * nn.y, fb * nn.z, dot(b3, b2) / bb);
+    const float fa = dEdphi * lb * __builtin_amdgcn_rcpf(m2), fb = -dEdphi * lb * __builtin_amdgcn_rcpf(n2);
+    oA = make_float4(fa * mm.x, fa * mm.y, fa * mm.z, dot(b1, b2) * ibb);   // A = fa mm, B = fb nn
+    oB = make_float4(fb * nn.x, fb * nn.y, fb * nn.z, dot(b3, b2) * ibb);
     return 0.5f * td.V * (1.f - carg);
 }
 
@@ -382,15 +394,17 @@ k_replicas(KArgs A) {
     //                  step, the gather offsets
     //   s_sum          per-replica sums (index = replica in pack) and, earlier, gather indices
     //   s_plq          per-lane P, L, Q, 1/(m 103.6427)
-    //   s_nf           per-replica non-finite flags (NVE)
     //   s_tres         torsion-term results, 2 float4 per term and replica
+    //   s_drift        per-replica NVE drift record (6 doubles)
+    //   s_nf           per-replica non-finite flags (NVE)
     float4 *s_pos0 = reinterpret_cast<float4 *>(smem);
     float4 *s_pos1 = s_pos0 + BT;
     float4 *s_red = s_pos1 + BT;
     float4 *s_sum = s_red + BT;
     float4 *s_plq = s_sum + BT;
     float4 *s_tres = s_plq + BT;
-    int *s_nf = reinterpret_cast<int *>(s_tres + 2 * A.tres_max);
+    double *s_drift = reinterpret_cast<double *>(s_tres + 2 * A.tres_max);
+    int *s_nf = reinterpret_cast<int *>(s_drift + 6 * A.max_pack_reps);
     int *s_any = s_nf + BT;
     double2 *s_red64 = reinterpret_cast<double2 *>(s_red);
     float4 *s_gt = s_red;
@@ -426,6 +440,8 @@ k_replicas(KArgs A) {
         }
         s_plq[tid] = me;
         s_nf[tid] = 0;
+        if (MODE == MODE_NVE)
+            for (int k = tid; k < 6 * nrep; k += BT) s_drift[k] = 0.0;
         if (tid == 0) { s_any[0] = 0; s_any[1] = 0; }
         lds_sync();
 
@@ -435,7 +451,11 @@ k_replicas(KArgs A) {
         int steps = 0;
         const bool entered_conv = (st & GFF_REP_CONVERGED) != 0;
         bool live = active && !(st & GFF_REP_NONFINITE);
-        double dr0 = 0, dr1 = 0, dr2 = 0, dr3 = 0, dr4 = 0, dr5 = 0;   // reducer lane: drift record
+        // per-replica sums: a quad of reducer lanes per replica (lane q adds atoms q, q+4, ...,
+        // then a quad sum), one lane for molecules of fewer than four atoms
+        const int RL = n >= 4 ? 4 : 1;
+        const int rr = RL == 4 ? (tid >> 2) : tid, rq = tid - rr * RL;
+        const bool reducer = rr < nrep;
         float cm[4][16];                        // cached pre-mixed stencil planes (CACHE)
         int cid[4] = {-1, -1, -1, -1};          // their stencil ids (-1: none)
 
@@ -547,13 +567,15 @@ k_replicas(KArgs A) {
             if (MODE == MODE_FIRE) {
                 s_red[tid] = make_float4(dot(F, F), dot(F, v), dot(v, v), 0.f);
                 lds_sync();                                      // C: partials visible
-                if (tid < nrep) {                                // reducer lane of replica tid
+                if (reducer) {                                   // reducer lanes of replica rr
                     float ff = 0.f, fv = 0.f, vv = 0.f;
-                    for (int j = 0; j < n; ++j) {
-                        const float4 r = s_red[tid * n + j];
+#pragma unroll 4
+                    for (int j = rq; j < n; j += RL) {
+                        const float4 r = s_red[rr * n + j];
                         ff += r.x; fv += r.y; vv += r.z;
                     }
-                    s_sum[tid] = make_float4(ff, fv, vv, 0.f);
+                    if (RL == 4) { ff = quad_sum(ff); fv = quad_sum(fv); vv = quad_sum(vv); }
+                    if (rq == 0) s_sum[rr] = make_float4(ff, fv, vv, 0.f);
                 }
                 lds_sync();                                      // D: sums visible
                 if (live) {
@@ -597,21 +619,28 @@ k_replicas(KArgs A) {
                     const double ke = (double)khalf * ((double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z);
                     s_red64[tid] = live ? make_double2((double)e_atom, ke) : make_double2(0.0, 0.0);
                     lds_sync();                                  // C: partials visible
-                    if (tid < nrep && !s_nf[tid]) {              // reducer lane of replica tid
+                    if (reducer && !s_nf[rr]) {                  // reducer lanes of replica rr
                         double ep = 0.0, kk = 0.0;
-                        for (int j = 0; j < n; ++j) {
-                            const double2 r = s_red64[tid * n + j];
+#pragma unroll 4
+                        for (int j = rq; j < n; j += RL) {
+                            const double2 r = s_red64[rr * n + j];
                             ep += r.x; kk += r.y;
                         }
-                        const double et = ep + kk;
-                        if (!__builtin_isfinite(et)) {
-                            s_nf[tid] = 1;
-                        } else {
-                            if (it == 0) { dr0 = et; dr2 = 0; dr3 = 0; dr4 = 0; dr5 = 0; }
-                            const double de = et - dr0;
-                            dr1 = et;
-                            if (fabs(de) > dr2) dr2 = fabs(de);
-                            dr3 += de; dr4 += (double)it * de; dr5 += 1.0;
+                        if (RL == 4) { ep = quad_sum(ep); kk = quad_sum(kk); }
+                        const double et = ep + kk;       // identical on the quad's lanes
+                        if (rq == 0) {
+                            // drift record {E(0), E(last), max |dE|, sum dE, sum step*dE, samples}
+                            double *dr = s_drift + 6 * rr;
+                            if (!__builtin_isfinite(et)) {
+                                s_nf[rr] = 1;
+                            } else if (it == 0) {
+                                dr[0] = et; dr[1] = et; dr[2] = 0.0; dr[3] = 0.0; dr[4] = 0.0; dr[5] = 1.0;
+                            } else {
+                                const double de = et - dr[0];
+                                dr[1] = et;
+                                dr[2] = fmax(dr[2], fabs(de));
+                                dr[3] += de; dr[4] += (double)it * de; dr[5] += 1.0;
+                            }
                         }
                     }
                 }
@@ -653,9 +682,10 @@ k_replicas(KArgs A) {
                 if (MODE == MODE_FIRE) { A.fdt[rep] = fdt; A.falpha[rep] = fal; A.fnpos[rep] = fnp; }
             }
         }
-        if (MODE == MODE_NVE && A.drift && tid < nrep) {
-            double *d = A.drift + 6 * (size_t)A.pack_reps[pinfo.z + tid];
-            d[0] = dr0; d[1] = dr1; d[2] = dr2; d[3] = dr3; d[4] = dr4; d[5] = dr5;
+        if (MODE == MODE_NVE && A.drift && reducer && rq == 0) {
+            double *d = A.drift + 6 * (size_t)A.pack_reps[pinfo.z + rr];
+            const double *dr = s_drift + 6 * rr;
+            for (int k = 0; k < 6; ++k) d[k] = dr[k];
         }
         lds_sync();       // LDS is reused by the next pack
     }
@@ -707,6 +737,7 @@ static void fill_common(KArgs &A, const gff_topology *topo, const gff_plan *plan
     A.ke = topo->ke;
     A.packs = plan->d_packs; A.pack_reps = plan->d_pack_reps; A.atom_off = plan->d_atom_off;
     A.n_packs = plan->n_packs; A.N = plan->n_atoms; A.tres_max = plan->tres_max;
+    A.max_pack_reps = plan->max_pack_reps;
 }
 
 template <int STORE, int MODE, bool CACHE>
@@ -722,7 +753,7 @@ static void launch_one(int grid, int BT, size_t lds, const KArgs &A, hipStream_t
 template <int MODE>
 static gff_status launch_mode(const gff_grid *gr, const gff_plan *plan, KArgs &A, hipStream_t s) {
     const int BT = plan->block_threads;
-    const size_t lds = (size_t)BT * (5 * 16 + 4) + (size_t)plan->tres_max * 32 + 16;
+    const size_t lds = replica_lds_bytes(BT, plan->tres_max, plan->max_pack_reps);
     const int grid = plan->grid_blocks > 0 ? std::min(plan->grid_blocks, plan->n_packs) : plan->n_packs;
     if (grid <= 0) return GFF_OK;
     constexpr bool can_cache = MODE != MODE_EVAL;
