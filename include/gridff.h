@@ -243,6 +243,14 @@ gff_status gff_relax_batch(const gff_grid *grid, const gff_topology *topo, const
                            double *d_E_rep, float *d_fnorm_rep, int *d_steps_rep,
                            double *d_drift_rep, void *stream);
 
+/* Resident blocks per compute unit of the kernel gff_relax_batch (mode GFF_MODE_FIRE or
+ * GFF_MODE_NVE) or gff_eval_forces (mode -1) launches for this grid storage and plan,
+ * from the device's occupancy calculator (register and LDS limits); *lds_bytes_out
+ * (nullable) receives the dynamic LDS of one block.  GFF_EINVAL on null arguments or
+ * an unknown mode. */
+gff_status gff_relax_occupancy(const gff_grid *grid, const gff_plan *plan, int mode, int *blocks_per_cu,
+                               size_t *lds_bytes_out);
+
 /* ------------------------------------------------------------------ graphs and autotuning */
 
 /* One relaxation launch captured as a HIP graph (arguments and buffers fixed at capture);

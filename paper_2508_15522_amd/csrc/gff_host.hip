@@ -79,17 +79,19 @@ extern "C" gff_status gff_topology_create(const gff_mol_type *types, int n_types
     std::vector<TorDef> tdef;
     std::vector<int> tinc;
     std::vector<uint4> rotm;
+    std::vector<int4> blob;
     for (int t = 0; t < n_types; ++t) {
         const gff_mol_type &m = types[t];
         const int n = m.n_atoms;
-        ti[t] = TypeInfo{n, (int)plqm.size(), (int)tdef.size(), m.n_tors};
+        ti[t] = TypeInfo{n, (int)plqm.size(), (int)tdef.size(), m.n_tors, 0, 0, 0, 0};
+        const int tinc0 = (int)tinc.size();
         T->natoms.push_back(n);
         T->ntors.push_back(m.n_tors);
         for (int q = 0; q < m.n_tors; ++q) {
             const int *Q4 = m.tors + 4 * q;
             const double ph = m.tors_phi0[q];
-            tdef.push_back(TorDef{Q4[0] | (Q4[1] << 8) | (Q4[2] << 16) | (Q4[3] << 24), m.tors_n[q], m.tors_V[q], 0.f,
-                                  (float)std::cos(ph), (float)std::sin(ph), 0.f, 0.f});
+            tdef.push_back(TorDef{Q4[0] | (Q4[1] << 7) | (Q4[2] << 14) | (Q4[3] << 21) | (m.tors_n[q] << 28),
+                                  m.tors_V[q], (float)std::cos(ph), (float)std::sin(ph)});
         }
         T->nrot.push_back(m.n_rot);
         // adjacency and exclusions (self, 1-2, 1-3)
@@ -126,7 +128,11 @@ extern "C" gff_status gff_topology_create(const gff_mol_type *types, int n_types
             for (int q = 0; q < m.n_angles; ++q) {
                 const int *A3 = m.angles + 3 * q;
                 for (int s = 0; s < 3; ++s)
-                    if (A3[s] == a) { ang.push_back(AngInc{A3[0], A3[1], A3[2], s, m.angle_k[q], m.angle_cos0[q], 0, 0}); break; }
+                    if (A3[s] == a) {
+                        ang.push_back(AngInc{A3[0] | (A3[1] << 8) | (A3[2] << 16) | (s << 24), m.angle_k[q],
+                                             m.angle_cos0[q], 0.f});
+                        break;
+                    }
             }
             ia.w = (int)ang.size() - ia.z;
             incA.push_back(ia);
@@ -139,6 +145,28 @@ extern "C" gff_status gff_topology_create(const gff_mol_type *types, int n_types
             }
             it.y = (int)tinc.size() - it.x;
             incT.push_back(it);
+        }
+        // the type's torsion block (indices relative to its own sections)
+        {
+            TypeInfo &T0 = ti[t];
+            std::vector<int4> b;
+            auto words = [](size_t bytes) { return (int)((bytes + 15) / 16); };
+            std::vector<int> it2;
+            for (int a = 0; a < n; ++a) { it2.push_back(incT[T0.abase + a].x - tinc0); it2.push_back(incT[T0.abase + a].y); }
+            it2.resize((size_t)words(it2.size() * 4) * 4, 0);
+            for (size_t k = 0; k < it2.size(); k += 4) b.push_back(make_int4(it2[k], it2[k + 1], it2[k + 2], it2[k + 3]));
+            T0.o_tor = (int)b.size();
+            for (int q = 0; q < m.n_tors; ++q) {
+                int4 w; std::memcpy(&w, &tdef[T0.tbase + q], 16); b.push_back(w);
+            }
+            T0.o_tinc = (int)b.size();
+            std::vector<int> tc(tinc.begin() + tinc0, tinc.end());
+            tc.resize((size_t)words(tc.size() * 4) * 4, 0);
+            for (size_t k = 0; k < tc.size(); k += 4) b.push_back(make_int4(tc[k], tc[k + 1], tc[k + 2], tc[k + 3]));
+            T0.blob_off = (int)blob.size();
+            T0.blob_words = (int)b.size();
+            blob.insert(blob.end(), b.begin(), b.end());
+            T->blob_words.push_back(T0.blob_words);
         }
         rotinfo[t] = make_int2((int)rotq.size(), m.n_rot);
         for (int k = 0; k < m.n_rot; ++k) {
@@ -153,9 +181,8 @@ extern "C" gff_status gff_topology_create(const gff_mol_type *types, int n_types
     auto &o = T->allocations;
     DevTopo &d = T->dev;
     if ((rc = upload(o, ti, &d.types)) || (rc = upload(o, plqm, &d.plqm)) || (rc = upload(o, khalf, &d.khalf)) ||
-        (rc = upload(o, excl, &d.excl)) || (rc = upload(o, incA, &d.incA)) || (rc = upload(o, incT, &d.incT)) ||
-        (rc = upload(o, bnd, &d.bnd)) || (rc = upload(o, ang, &d.ang)) || (rc = upload(o, tdef, &d.tordef)) ||
-        (rc = upload(o, tinc, &d.torinc)) ||
+        (rc = upload(o, excl, &d.excl)) || (rc = upload(o, incA, &d.incA)) || (rc = upload(o, bnd, &d.bnd)) ||
+        (rc = upload(o, ang, &d.ang)) || (rc = upload(o, blob, &d.blob)) ||
         (rc = upload(o, refpos, &d.refpos)) || (rc = upload(o, rotq, &d.rotq)) || (rc = upload(o, rotm, &d.rotm)) ||
         (rc = upload(o, rotinfo, &d.rotinfo))) {
         free_all(o);
@@ -197,15 +224,19 @@ extern "C" gff_status gff_plan_create(const gff_topology *topo, int n_rep, const
     std::vector<int> order(topo->n_types);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return topo->natoms[a] > topo->natoms[b]; });
-    // LDS per block: 84 bytes per lane plus 32 bytes per (replica, torsion term); packs of
-    // torsion-heavy types hold fewer replicas when the block's LDS would overflow
+    // LDS per block: 84 bytes per lane, the largest torsion block, 48 bytes per replica and
+    // 32 bytes per (replica, torsion term); packs of torsion-heavy types hold fewer replicas
+    // when the block's LDS would overflow
     int dev = 0, lds_limit = 65536;
     if (hipGetDevice(&dev) == hipSuccess) {
         int v = 0;
         if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
             lds_limit = v;
     }
-    const long lane_lds = (long)BT * (5 * 16 + 4) + 16;
+    int topo_words = 0;                                   // largest torsion block of the batch
+    for (int t = 0; t < topo->n_types; ++t)
+        if (!by_type[t].empty()) topo_words = std::max(topo_words, topo->blob_words[t]);
+    const long lane_lds = (long)BT * (5 * 16 + 4) + 16 + 16L * topo_words;
     if (lane_lds >= lds_limit) return GFF_EUNSUPPORTED;
     std::vector<int4> packs;
     std::vector<int> reps;
@@ -231,8 +262,11 @@ extern "C" gff_status gff_plan_create(const gff_topology *topo, int n_rep, const
     auto *P = new gff_plan_s();
     P->n_rep = n_rep; P->n_atoms = atom_off[n_rep]; P->n_packs = (int)packs.size();
     P->block_threads = BT; P->grid_blocks = grid; P->max_n = max_n; P->tres_max = tres_max;
-    P->max_pack_reps = max_pack_reps;
-    if ((long)replica_lds_bytes(BT, tres_max, max_pack_reps) > lds_limit) { delete P; return GFF_EUNSUPPORTED; }
+    P->max_pack_reps = max_pack_reps; P->topo_words = topo_words;
+    if ((long)replica_lds_bytes(BT, tres_max, max_pack_reps, topo_words) > lds_limit) {
+        delete P;
+        return GFF_EUNSUPPORTED;
+    }
     P->atom_off_h = atom_off;
     P->rep_type_h.assign(rep_type_h, rep_type_h + n_rep);
     std::vector<void *> owned;

@@ -18,32 +18,37 @@ struct TypeInfo {              // per molecule type
     int abase;                 // first entry in the per-type-atom arrays
     int tbase;                 // first torsion of the type in the torsion-term table
     int nt;                    // torsion terms of the type
+    // the type's torsion topology as one block of 16-byte words, copied to LDS by the replica
+    // kernel: [incT: n int2, padded][torsion terms, one word each][torsion incidences, int,
+    // padded]; indices inside are relative to the block's own sections
+    int blob_off, blob_words;  // first word in the blob table, length in words
+    int o_tor, o_tinc;         // section starts (words); incT starts at word 0
 };
 
-// Torsion term: atoms (i,j,k,l) packed one byte each, multiplicity, barrier V and
-// (cos phi0, sin phi0).
-struct TorDef { int ijkl; int n; float V; float pad; float c0, s0, pad1, pad2; };
+// Torsion term: atoms (i,j,k,l) packed seven bits each with the multiplicity n in the top
+// four bits, barrier V and (cos phi0, sin phi0).
+struct TorDef { int ijkln; float V, c0, s0; };
 
 // One entry per (atom, incident term).  `slot` is the atom's position in the term; the
 // slot-0 entry carries the term's energy so every term is counted once.
 struct BondInc { int other; int slot; float k; float r0; };
-struct AngInc  { int a, b, c, slot; float k, cos0, pad0, pad1; };        // b = vertex
+struct AngInc  { int abcs; float k, cos0, pad; };   // a | b << 8 | c << 16 | slot << 24, b = vertex
 
 struct DevTopo {
     const TypeInfo *types;
     const float4 *plqm;        // [type atoms] P, L, Q, 1/(m * 103.6427)
     const float *khalf;        // [type atoms] m * 103.6427 / 2
     const uint4 *excl;         // [type atoms] bit j: pair excluded (self, 1-2, 1-3)
-    const int4 *incA;          // [type atoms] bond start, bond count, angle start, angle count
-    const int2 *incT;          // [type atoms] torsion-incidence start, count
-    const int *torinc;         // torsion incidences: (term within type) << 2 | slot
-    const TorDef *tordef;      // torsion terms
-    const BondInc *bnd;
-    const AngInc *ang;
     const float4 *refpos;      // [type atoms] reference geometry (pose construction)
     const int4 *rotq;          // [rotatable torsions of all types] quad
     const uint4 *rotm;         // [same] 128-bit moving mask
     const int2 *rotinfo;       // [types] first rotatable torsion, count
+    const int4 *incA;          // [type atoms] bond start, bond count, angle start, angle count
+    const BondInc *bnd;        // one per (atom, incident bond)
+    const AngInc *ang;         // one per (atom, incident angle)
+    // per-type torsion blocks (TypeInfo::blob_off): per atom (incidence start, count); TorDef
+    // terms; torsion incidences (term << 2 | slot)
+    const int4 *blob;
 };
 
 }  // namespace gff
@@ -51,6 +56,7 @@ struct DevTopo {
 struct gff_topology_s {
     int n_types;
     std::vector<int> ntors;
+    std::vector<int> blob_words;   // per type: LDS words of its torsion block
     float alpha, ke;
     std::vector<int> natoms;
     std::vector<int> nrot;
@@ -63,6 +69,7 @@ struct gff_plan_s {
     int block_threads, grid_blocks, max_n;
     int tres_max;              // largest (replicas per pack) x (torsion terms) of the batch
     int max_pack_reps;         // largest number of replicas in one pack
+    int topo_words;            // largest torsion block of the batch (16-byte words)
     int4 *d_packs;             // type, replicas in pack, first entry in d_pack_reps, pad
     int *d_pack_reps;          // replica ids in pack order
     int *d_atom_off;           // [n_rep+1]
@@ -76,7 +83,9 @@ inline gff_status hip_status(hipError_t e) { return e == hipSuccess ? GFF_OK : G
 }
 
 // Dynamic LDS of the replica kernel: five float4 slots and one int per lane, two float4 per
-// (replica, torsion term), six doubles of NVE drift record per replica, two flag words.
-inline size_t replica_lds_bytes(int block_threads, int tres_max, int max_pack_reps) {
-    return (size_t)block_threads * (5 * 16 + 4) + (size_t)tres_max * 32 + (size_t)max_pack_reps * 48 + 16;
+// (replica, torsion term), six doubles of NVE drift record per replica, two flag words and
+// the largest torsion block of the batch.
+inline size_t replica_lds_bytes(int block_threads, int tres_max, int max_pack_reps, int topo_words) {
+    return (size_t)block_threads * (5 * 16 + 4) + (size_t)tres_max * 32 + (size_t)max_pack_reps * 48 + 16 +
+           (size_t)topo_words * 16;
 }

@@ -39,7 +39,7 @@ struct KArgs {
     DevTopo t;
     float alpha_l2e, alpha, ke;
     const int4 *packs; const int *pack_reps; const int *atom_off;
-    int n_packs, N, tres_max, max_pack_reps;
+    int n_packs, N, tres_max, max_pack_reps, topo_words;
     float *pos, *vel;
     float *fdt, *falpha; int *fnpos; unsigned *status;
     float *F; float *E_atom; double *E_rep; float *fnorm; int *steps; double *drift;
@@ -335,7 +335,8 @@ __device__ __forceinline__ float bond_angle_terms(const KArgs &A, const float4 *
     }
     for (int q = ia.z; q < ia.z + ia.w; ++q) {
         const AngInc ai = A.t.ang[q];
-        const float3 pa = f3(sp[rbase + ai.a]), pb = f3(sp[rbase + ai.b]), pc = f3(sp[rbase + ai.c]);
+        const int ia0 = ai.abcs & 0xff, ib = (ai.abcs >> 8) & 0xff, ic = (ai.abcs >> 16) & 0xff, slot = ai.abcs >> 24;
+        const float3 pa = f3(sp[rbase + ia0]), pb = f3(sp[rbase + ib]), pc = f3(sp[rbase + ic]);
         const float3 u = pa - pb, v = pc - pb;
         const float uu = dot(u, u), vv = dot(v, v);
         const float inv = __builtin_amdgcn_rsqf(uu * vv);
@@ -343,9 +344,9 @@ __device__ __forceinline__ float bond_angle_terms(const KArgs &A, const float4 *
         const float de = ai.k * (cs - ai.cos0);
         const float3 ga = inv * v - (cs * __builtin_amdgcn_rcpf(uu)) * u;
         const float3 gc = inv * u - (cs * __builtin_amdgcn_rcpf(vv)) * v;
-        float3 gs = ai.slot == 0 ? ga : (ai.slot == 2 ? gc : make_float3(-ga.x - gc.x, -ga.y - gc.y, -ga.z - gc.z));
+        float3 gs = slot == 0 ? ga : (slot == 2 ? gc : make_float3(-ga.x - gc.x, -ga.y - gc.y, -ga.z - gc.z));
         fx -= de * gs.x; fy -= de * gs.y; fz -= de * gs.z;
-        if (ai.slot == 0) e += 0.5f * ai.k * (cs - ai.cos0) * (cs - ai.cos0);
+        if (slot == 0) e += 0.5f * ai.k * (cs - ai.cos0) * (cs - ai.cos0);
     }
     return e;
 }
@@ -355,7 +356,8 @@ __device__ __forceinline__ float bond_angle_terms(const KArgs &A, const float4 *
 //   F_i = A, F_l = B, F_j = -(1+p) A + q B, F_k = p A - (1+q) B,
 // with A = -dE/dphi dphi/dr_i, B = -dE/dphi dphi/dr_l, p = b1.b2/|b2|^2, q = b3.b2/|b2|^2.
 __device__ __forceinline__ float torsion_term(const TorDef td, const float4 *sp, int rbase, float4 &oA, float4 &oB) {
-    const int i0 = td.ijkl & 0xff, i1 = (td.ijkl >> 8) & 0xff, i2 = (td.ijkl >> 16) & 0xff, i3 = (td.ijkl >> 24) & 0xff;
+    const int i0 = td.ijkln & 0x7f, i1 = (td.ijkln >> 7) & 0x7f, i2 = (td.ijkln >> 14) & 0x7f;
+    const int i3 = (td.ijkln >> 21) & 0x7f, nmul = (td.ijkln >> 28) & 0xf;
     const float3 p0 = f3(sp[rbase + i0]), p1 = f3(sp[rbase + i1]), p2 = f3(sp[rbase + i2]), p3 = f3(sp[rbase + i3]);
     const float3 b1 = p1 - p0, b2 = p2 - p1, b3 = p3 - p2;
     const float3 mm = cross(b1, b2), nn = cross(b2, b3);
@@ -368,12 +370,12 @@ __device__ __forceinline__ float torsion_term(const TorDef td, const float4 *sp,
     const float inv = __builtin_amdgcn_rsqf(m2 * n2);
     const float c1 = dot(mm, nn) * inv, s1 = lb * dot(b1, nn) * inv;    // cos phi, sin phi
     float cn = c1, sn = s1;
-    for (int r = 1; r < td.n; ++r) {                                    // (cos n phi, sin n phi)
+    for (int r = 1; r < nmul; ++r) {                                    // (cos n phi, sin n phi)
         const float c2 = cn * c1 - sn * s1;
         sn = sn * c1 + cn * s1; cn = c2;
     }
     const float carg = cn * td.c0 + sn * td.s0, sarg = sn * td.c0 - cn * td.s0;
-    const float dEdphi = 0.5f * td.V * (float)td.n * sarg;
+    const float dEdphi = 0.5f * td.V * (float)nmul * sarg;
     const float fa = dEdphi * lb * __builtin_amdgcn_rcpf(m2), fb = -dEdphi * lb * __builtin_amdgcn_rcpf(n2);
     oA = make_float4(fa * mm.x, fa * mm.y, fa * mm.z, dot(b1, b2) * ibb);   // A = fa mm, B = fb nn
     oB = make_float4(fb * nn.x, fb * nn.y, fb * nn.z, dot(b3, b2) * ibb);
@@ -395,6 +397,7 @@ k_replicas(KArgs A) {
     //   s_sum          per-replica sums (index = replica in pack) and, earlier, gather indices
     //   s_plq          per-lane P, L, Q, 1/(m 103.6427)
     //   s_tres         torsion-term results, 2 float4 per term and replica
+    //   s_topo         the pack's molecule type: torsion block
     //   s_drift        per-replica NVE drift record (6 doubles)
     //   s_nf           per-replica non-finite flags (NVE)
     float4 *s_pos0 = reinterpret_cast<float4 *>(smem);
@@ -403,7 +406,8 @@ k_replicas(KArgs A) {
     float4 *s_sum = s_red + BT;
     float4 *s_plq = s_sum + BT;
     float4 *s_tres = s_plq + BT;
-    double *s_drift = reinterpret_cast<double *>(s_tres + 2 * A.tres_max);
+    int4 *s_topo = reinterpret_cast<int4 *>(s_tres + 2 * A.tres_max);
+    double *s_drift = reinterpret_cast<double *>(s_topo + A.topo_words);
     int *s_nf = reinterpret_cast<int *>(s_drift + 6 * A.max_pack_reps);
     int *s_any = s_nf + BT;
     double2 *s_red64 = reinterpret_cast<double2 *>(s_red);
@@ -440,6 +444,7 @@ k_replicas(KArgs A) {
         }
         s_plq[tid] = me;
         s_nf[tid] = 0;
+        for (int k = tid; k < ti.blob_words; k += BT) s_topo[k] = A.t.blob[ti.blob_off + k];
         if (MODE == MODE_NVE)
             for (int k = tid; k < 6 * nrep; k += BT) s_drift[k] = 0.0;
         if (tid == 0) { s_any[0] = 0; s_any[1] = 0; }
@@ -533,7 +538,8 @@ k_replicas(KArgs A) {
                 if (live) {
                     for (int q = at; q < nt; q += n) {
                         float4 oA, oB;
-                        e_intra += torsion_term(A.t.tordef[ti.tbase + q], sp, rbase, oA, oB);
+                        e_intra += torsion_term(reinterpret_cast<const TorDef *>(s_topo + ti.o_tor)[q], sp, rbase,
+                                                oA, oB);
                         s_tres[2 * (lr * nt + q)] = oA;
                         s_tres[2 * (lr * nt + q) + 1] = oB;
                     }
@@ -544,10 +550,11 @@ k_replicas(KArgs A) {
                 }
                 lds_sync();                                      // B: torsion results visible
                 if (live) {
-                    const int2 itc = A.t.incT[abase + at];
+                    const int2 itc = reinterpret_cast<const int2 *>(s_topo)[at];
+                    const int *tinc = reinterpret_cast<const int *>(s_topo + ti.o_tinc);
                     float fx = 0.f, fy = 0.f, fz = 0.f;
                     for (int c = itc.x; c < itc.x + itc.y; ++c) {
-                        const int code = A.t.torinc[c];
+                        const int code = tinc[c];
                         const int q = code >> 2, slot = code & 3;
                         const float4 ra = s_tres[2 * (lr * nt + q)], rb = s_tres[2 * (lr * nt + q) + 1];
                         float ca, cb;
@@ -737,7 +744,7 @@ static void fill_common(KArgs &A, const gff_topology *topo, const gff_plan *plan
     A.ke = topo->ke;
     A.packs = plan->d_packs; A.pack_reps = plan->d_pack_reps; A.atom_off = plan->d_atom_off;
     A.n_packs = plan->n_packs; A.N = plan->n_atoms; A.tres_max = plan->tres_max;
-    A.max_pack_reps = plan->max_pack_reps;
+    A.max_pack_reps = plan->max_pack_reps; A.topo_words = plan->topo_words;
 }
 
 template <int STORE, int MODE, bool CACHE>
@@ -753,7 +760,7 @@ static void launch_one(int grid, int BT, size_t lds, const KArgs &A, hipStream_t
 template <int MODE>
 static gff_status launch_mode(const gff_grid *gr, const gff_plan *plan, KArgs &A, hipStream_t s) {
     const int BT = plan->block_threads;
-    const size_t lds = replica_lds_bytes(BT, plan->tres_max, plan->max_pack_reps);
+    const size_t lds = replica_lds_bytes(BT, plan->tres_max, plan->max_pack_reps, plan->topo_words);
     const int grid = plan->grid_blocks > 0 ? std::min(plan->grid_blocks, plan->n_packs) : plan->n_packs;
     if (grid <= 0) return GFF_OK;
     constexpr bool can_cache = MODE != MODE_EVAL;
@@ -768,9 +775,39 @@ static gff_status launch_mode(const gff_grid *gr, const gff_plan *plan, KArgs &A
     return hip_status(hipGetLastError());
 }
 
+template <int STORE, int MODE, bool CACHE>
+static gff_status occupancy_one(int BT, size_t lds, int *blocks) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_replicas<STORE, MODE, CACHE>, BT, lds) ==
+                   hipSuccess ? GFF_OK : GFF_EHIP;
+}
+
+template <int MODE>
+static gff_status occupancy_mode(int storage, int BT, size_t lds, int *blocks) {
+    constexpr bool can_cache = MODE != MODE_EVAL;
+    const bool cache = can_cache && BT <= 512;
+    if (storage == GFF_STORE_F32)
+        return cache ? occupancy_one<GFF_STORE_F32, MODE, can_cache>(BT, lds, blocks)
+                     : occupancy_one<GFF_STORE_F32, MODE, false>(BT, lds, blocks);
+    return cache ? occupancy_one<GFF_STORE_F16, MODE, can_cache>(BT, lds, blocks)
+                 : occupancy_one<GFF_STORE_F16, MODE, false>(BT, lds, blocks);
+}
+
 }  // namespace gff
 
 using namespace gff;
+
+extern "C" gff_status gff_relax_occupancy(const gff_grid *grid, const gff_plan *plan, int mode, int *blocks_per_cu,
+                                          size_t *lds_bytes_out) {
+    if (!grid || !plan || !blocks_per_cu) return GFF_EINVAL;
+    if (grid->storage != GFF_STORE_F32 && grid->storage != GFF_STORE_F16) return GFF_EUNSUPPORTED;
+    const int BT = plan->block_threads;
+    const size_t lds = replica_lds_bytes(BT, plan->tres_max, plan->max_pack_reps, plan->topo_words);
+    if (lds_bytes_out) *lds_bytes_out = lds;
+    if (mode == -1) return occupancy_mode<MODE_EVAL>(grid->storage, BT, lds, blocks_per_cu);
+    if (mode == GFF_MODE_FIRE) return occupancy_mode<MODE_FIRE>(grid->storage, BT, lds, blocks_per_cu);
+    if (mode == GFF_MODE_NVE) return occupancy_mode<MODE_NVE>(grid->storage, BT, lds, blocks_per_cu);
+    return GFF_EINVAL;
+}
 
 extern "C" gff_status gff_eval_forces(const gff_grid *grid, const gff_topology *topo, const gff_plan *plan,
                                       int include_intra, const float *d_pos, float *d_F, float *d_E_atom,

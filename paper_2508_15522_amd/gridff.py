@@ -72,7 +72,7 @@ EXPORTS = [
     "gff_status_string", "gff_build_grid_workspace_bytes", "gff_build_grid", "gff_fit_workspace_bytes",
     "gff_fit_bspline", "gff_grid_bytes", "gff_pack_grid", "gff_topology_create", "gff_topology_destroy",
     "gff_plan_create", "gff_plan_destroy", "gff_plan_n_atoms", "gff_plan_n_packs", "gff_plan_atom_offsets",
-    "gff_eval_forces", "gff_interp_points", "gff_relax_batch",
+    "gff_eval_forces", "gff_interp_points", "gff_relax_batch", "gff_relax_occupancy",
 ]
 
 _lib = None
@@ -218,6 +218,15 @@ class Plan:
         if getattr(self, "handle", None) and _lib is not None:
             _lib.gff_plan_destroy(self.handle)
             self.handle = None
+
+
+def relax_occupancy(grid_desc, plan, mode):
+    """(resident blocks per compute unit, dynamic LDS bytes per block) of the replica kernel
+    for this grid and plan; mode MODE_FIRE, MODE_NVE or -1 (single evaluation)."""
+    blocks = C.c_int(0)
+    lds = C.c_size_t(0)
+    check(lib().gff_relax_occupancy(C.byref(grid_desc), plan.handle, C.c_int(mode), C.byref(blocks), C.byref(lds)))
+    return blocks.value, lds.value
 
 
 # ------------------------------------------------------------------ evaluation / relaxation

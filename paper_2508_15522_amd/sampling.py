@@ -20,7 +20,8 @@ import torch
 
 from . import device as D, gridff as G, synth as S
 
-H_LO, H_HI = 3.0, 5.0
+H_LO, H_HI = 3.0, 5.0            # uniform proposals: height of the lowest atom (A)
+DEC_LO, DEC_HI = 1.0, 8.0        # learned proposals: heights outside this range are clamped
 
 
 @dataclass
@@ -46,6 +47,7 @@ class RoundStats:
     new_minima: int
     fire_steps_converged: float
     seconds: float
+    rms_move_converged: float = float("nan")   # mean over converged replicas of the RMS atom move (A)
     new_pos: list = field(default_factory=list)
 
 
@@ -71,6 +73,7 @@ class Sampler:
               "fire_npos": torch.zeros(self.n_rep, dtype=torch.int32, device="cuda"),
               "status": torch.zeros(self.n_rep, dtype=torch.int32, device="cuda")}
         G.pose_from_dof(self.topo, self.plan, self.dof, 7 + self.T, self.Lx, self.Ly, 0.0, st["pos"])
+        pos0 = st["pos"].clone()
         prm = G.relax_params(G.MODE_FIRE, self.max_steps, True, f_conv=self.f_conv)
         G.relax_batch(self.grid.desc, self.topo, self.plan, prm, st, self.out["E"], self.out["fnorm"],
                       self.out["steps"])
@@ -81,16 +84,21 @@ class Sampler:
         okh = ok.cpu().numpy().astype(bool)
         steps = self.out["steps"].cpu().numpy()
         newh = self.is_new.cpu().numpy().astype(bool)
-        kept = [st["pos"].clone()] if keep_new else []
-        return okh, steps, newh, kept
+        kept = [st["pos"].clone(), self.out["E"].cpu().numpy()] if keep_new else []
+        # how far relaxation moved each replica: RMS over its atoms of |x_min - x_proposed|
+        d2 = ((st["pos"] - pos0) ** 2).sum(0).cpu().numpy().astype(np.float64)
+        off = self.plan.atom_off
+        rms = np.sqrt(np.add.reduceat(d2, off[:-1]) / np.diff(off))
+        move = float(rms[okh].mean()) if okh.any() else float("nan")
+        return okh, steps, newh, kept, move
 
     def round_uniform(self, archive, rnd, keep_new=False):
         t0 = time.time()
         G.propose_uniform(self.n_rep, self.T, self.seed, rnd, H_LO, H_HI, self.dof)
-        okh, steps, newh, kept = self._relax_and_dedupe(archive, keep_new)
+        okh, steps, newh, kept, move = self._relax_and_dedupe(archive, keep_new)
         rs = RoundStats(self.n_rep, int(okh.sum()), int(newh.sum()),
-                        float(steps[okh].mean()) if okh.any() else float("nan"), time.time() - t0)
-        rs.new_pos = [(kept[0], newh)] if keep_new else []
+                        float(steps[okh].mean()) if okh.any() else float("nan"), time.time() - t0, move)
+        rs.new_pos = [(kept[0], newh, okh, kept[1])] if keep_new else []
         return rs
 
     def round_learned(self, archive, mlp, rnd):
@@ -99,10 +107,10 @@ class Sampler:
         G.normal_philox(self.n_rep * 64, self.seed + 1, rnd, noise)
         enc = torch.empty(self.n_rep, 41, device="cuda")
         mlp.forward(noise, self.types, enc)
-        G.decode_dof(enc, self.T, H_LO, H_HI, self.dof)
-        okh, steps, newh, _ = self._relax_and_dedupe(archive, False)
+        G.decode_dof(enc, self.T, DEC_LO, DEC_HI, self.dof)
+        okh, steps, newh, _, move = self._relax_and_dedupe(archive, False)
         return RoundStats(self.n_rep, int(okh.sum()), int(newh.sum()),
-                          float(steps[okh].mean()) if okh.any() else float("nan"), time.time() - t0)
+                          float(steps[okh].mean()) if okh.any() else float("nan"), time.time() - t0, move)
 
     def encode_minima(self, pos, mask):
         """Encodings [m][41] of the replicas selected by mask (host bool array)."""
@@ -113,10 +121,13 @@ class Sampler:
         return enc.index_select(0, idx)
 
 
-def train_imle(mlp, targets, ntors, types, steps, batch=1024, K=16, lr=1e-3, seed=S.SEED_MLP, log=None):
-    """IMLE training on encoded minima (device tensors targets [m][41], ntors [m], types [m])."""
+def train_imle(mlp, targets, ntors, types, steps, batch=1024, K=64, lr=1e-3, seed=S.SEED_MLP, log=None,
+               weights=None):
+    """IMLE training on encoded minima (device tensors targets [m][41], ntors [m], types [m]);
+    batches draw minima with probabilities proportional to `weights` (host, default uniform)."""
     m = targets.shape[0]
     rng = np.random.default_rng(seed)
+    p = None if weights is None else np.asarray(weights, np.float64) / np.sum(weights)
     cand_noise = torch.empty(batch * K, 64, device="cuda")
     cand_out = torch.empty(batch * K, 41, device="cuda")
     best = torch.empty(batch, dtype=torch.int32, device="cuda")
@@ -125,7 +136,7 @@ def train_imle(mlp, targets, ntors, types, steps, batch=1024, K=16, lr=1e-3, see
     loss = torch.empty(batch, device="cuda")
     hist = []
     for s in range(steps):
-        idx = torch.from_numpy(rng.integers(0, m, batch)).cuda()
+        idx = torch.from_numpy(rng.integers(0, m, batch) if p is None else rng.choice(m, batch, p=p)).cuda()
         tg = targets.index_select(0, idx).contiguous()
         nt = ntors.index_select(0, idx).contiguous()
         ty = types.index_select(0, idx).contiguous()
@@ -145,19 +156,22 @@ def train_imle(mlp, targets, ntors, types, steps, batch=1024, K=16, lr=1e-3, see
 
 def compare_learned_vs_uniform(grid, mol, collect_rounds=6, collect_rep=4096, train_steps=400, eval_rounds=6,
                                eval_rep=1024, seed=S.SEED_PHILOX, log=None):
-    """Collect minima with uniform proposals, train the proposer on the distinct ones, then
-    run equal numbers of proposals with each method against fresh archives.  Returns a
-    dict of counts, wall times, minima/s and mean FIRE steps per converged minimum."""
+    """Collect minima with uniform proposals, train the proposer on every converged minimum
+    (the relaxed poses the method generated), each distinct minimum weighted equally, then
+    run equal numbers of proposals with each method against fresh archives.  Returns a dict
+    of counts, wall times, minima/s, mean FIRE steps and mean RMS relaxation move per
+    converged minimum."""
     say = log or (lambda m: None)
     col = Sampler(grid, mol, collect_rep, seed=seed)
     arch = Archive()
-    targets = []
+    targets, energies = [], []
     t0 = time.time()
     for r in range(collect_rounds):
         rs = col.round_uniform(arch, r, keep_new=True)
-        pos, newh = rs.new_pos[0]
-        if newh.any():
-            targets.append(col.encode_minima(pos, newh))
+        pos, newh, okh, E = rs.new_pos[0]
+        if okh.any():
+            targets.append(col.encode_minima(pos, okh))
+            energies.append(E[okh])
         say(f"collect round {r}: converged {rs.converged}/{rs.proposals}, new {rs.new_minima}, "
             f"mean steps {rs.fire_steps_converged:.0f}, {rs.seconds:.2f} s")
     collect_s = time.time() - t0
@@ -165,26 +179,33 @@ def compare_learned_vs_uniform(grid, mol, collect_rounds=6, collect_rep=4096, tr
     m = tg.shape[0]
     ntors = torch.full((m,), len(mol.rot_quads), dtype=torch.int32, device="cuda")
     types = torch.zeros(m, dtype=torch.int32, device="cuda")
+    # each distinct minimum (energy cluster of the archive) gets the same total weight, spread
+    # over its converged members: frequent basins do not crowd out rare ones
+    E = np.concatenate(energies)
+    aE = arch.E[:arch.count()].cpu().numpy()
+    cl = np.abs(E[:, None] - aE[None, :]).argmin(1)
+    w = 1.0 / np.bincount(cl, minlength=len(aE))[cl]
     mlp = G.MLP(1, S.mlp_init_params(1))
     t0 = time.time()
-    hist = train_imle(mlp, tg, ntors, types, train_steps, batch=min(1024, max(64, m)), log=say)
+    hist = train_imle(mlp, tg, ntors, types, train_steps, batch=min(1024, max(64, m)), log=say, weights=w)
     torch.cuda.synchronize()
     train_s = time.time() - t0
     ev = Sampler(grid, mol, eval_rep, seed=seed + 17)
     res = {}
     for name in ("uniform", "learned"):
         a = Archive()
-        secs, conv, props, steps = 0.0, 0, 0, []
+        secs, conv, props, steps, moves = 0.0, 0, 0, [], []
         for r in range(eval_rounds):
             rs = ev.round_uniform(a, 1000 + r) if name == "uniform" else ev.round_learned(a, mlp, 1000 + r)
             secs += rs.seconds; conv += rs.converged; props += rs.proposals
-            steps.append(rs.fire_steps_converged)
+            steps.append(rs.fire_steps_converged); moves.append(rs.rms_move_converged)
         n_min = a.count()
         res[name] = dict(distinct_minima=n_min, proposals=props, converged=conv, seconds=secs,
-                         minima_per_s=n_min / secs, mean_fire_steps=float(np.nanmean(steps)))
+                         minima_per_s=n_min / secs, mean_fire_steps=float(np.nanmean(steps)),
+                         mean_rms_move=float(np.nanmean(moves)))
         say(f"{name}: {n_min} distinct minima from {props} proposals ({conv} converged) in {secs:.2f} s, "
-            f"mean FIRE steps {res[name]['mean_fire_steps']:.0f}")
-    res["training"] = dict(minima=m, steps=train_steps, loss_first=hist[0][1], loss_last=hist[-1][1],
-                           collect_s=collect_s, train_s=train_s)
+            f"mean FIRE steps {res[name]['mean_fire_steps']:.0f}, mean RMS move {res[name]['mean_rms_move']:.2f} A")
+    res["training"] = dict(minima=m, distinct=arch.count(), steps=train_steps, loss_first=hist[0][1],
+                           loss_last=hist[-1][1], collect_s=collect_s, train_s=train_s)
     res["gain_minima_per_s"] = res["learned"]["minima_per_s"] / max(res["uniform"]["minima_per_s"], 1e-12)
     return res

@@ -4,8 +4,9 @@ reduced size: thousands of minima instead of a million).
 Minima are collected with uniform proposals relaxed by FIRE to |F| < 1e-4 eV/A, the
 proposer is trained on the distinct ones (IMLE), then both proposal forms run the same
 number of proposals against fresh archives (distinct within 0.01 eV).  Asserted: the
-training loss falls and learned proposals relax in fewer FIRE steps (they land near
-minima); minima/s of both forms are reported.
+training loss falls; learned proposals land nearer to minima (more of them converge, and
+relaxation moves their atoms less, RMS over the molecule) while still reaching most of the
+distinct minima.  Minima/s and mean FIRE steps of both forms are reported.
 """
 import numpy as np
 import pytest
@@ -16,7 +17,7 @@ from tests.gpu_common import announce
 pytestmark = pytest.mark.gpu
 
 
-def test_learned_proposals_relax_faster():
+def test_learned_proposals_land_near_minima():
     D.require_gpu()
     cfg = configs.GRID_SMALL
     grid = D.build_physical_grid(cfg.substrate(), D.spec_for(cfg))
@@ -26,4 +27,7 @@ def test_learned_proposals_relax_faster():
     tr = res["training"]
     assert tr["loss_last"] < 0.8 * tr["loss_first"]
     assert res["learned"]["converged"] > 0.5 * res["learned"]["proposals"]
-    assert res["learned"]["mean_fire_steps"] < res["uniform"]["mean_fire_steps"]
+    L, U = res["learned"], res["uniform"]
+    assert L["converged"] > U["converged"]
+    assert L["mean_rms_move"] < 0.95 * U["mean_rms_move"]
+    assert L["distinct_minima"] >= 0.75 * U["distinct_minima"]
