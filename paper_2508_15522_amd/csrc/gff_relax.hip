@@ -255,6 +255,39 @@ __device__ __forceinline__ void quad_fetch(const GridView &g, GridKey key, float
     }
 }
 
+// Quad side, split fetch for overlapping the loads with other work: quad_issue loads the
+// nodes of x-planes a0, a0+1 (8 columns) of the lane's plane; quad_mix mixes them into
+// m[4 a0 .. 4 a0 + 7] with the same arithmetic as quad_fetch.
+struct QuadAddr { int xoff[4], yoff[4]; };
+template <int STORE>
+__device__ __forceinline__ QuadAddr quad_addr(const GridView &g, int4 ki, int s) {
+    const int i = ki.x, j = ki.y;
+    int ix[4], jy[4];
+    ix[0] = (i == 0 ? g.nx : i) - 1; ix[1] = i;
+    ix[2] = (i + 1 == g.nx) ? 0 : i + 1; ix[3] = (i + 2 >= g.nx) ? i + 2 - g.nx : i + 2;
+    jy[0] = (j == 0 ? g.ny : j) - 1; jy[1] = j;
+    jy[2] = (j + 1 == g.ny) ? 0 : j + 1; jy[3] = (j + 2 >= g.ny) ? j + 2 - g.ny : j + 2;
+    constexpr int NB = STORE == GFF_STORE_F32 ? 16 : 8;
+    const int col_stride = g.nzp * NB;
+    QuadAddr q;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) q.yoff[b] = jy[b] * col_stride + (ki.z + s) * NB;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) q.xoff[a] = ix[a] * g.ny * col_stride;
+    return q;
+}
+template <int STORE>
+__device__ __forceinline__ void quad_issue(const GridView &g, const QuadAddr &q, int a0, float4 c[8]) {
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) c[4 * a + b] = load_node_buf<STORE>(g.rsrc, q.xoff[a0 + a] + q.yoff[b]);
+}
+__device__ __forceinline__ void quad_mix(const float4 c[8], float Ps, float Ls, float Qs, int a0, float m[16]) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) m[4 * a0 + k] = Ps * c[k].x + Ls * c[k].y + Qs * c[k].z;
+}
+
 // Quad side, contraction: the lane's share of the tensor-product sum over its plane; the
 // quad sum is the atom's energy and gradient (in grid units).  The z weights enter once
 // per lane: E = sum_s wz[s] (...), dE/dz = sum_s dz[s] (...).
@@ -286,20 +319,20 @@ __device__ __forceinline__ int stencil_id(const GridView &g, int4 ki) {
     return ki.w ? (ki.x * g.ny + ki.y) * g.nzp + ki.z : -1;
 }
 
-// Non-bonded pairs of this lane's atom (more than two bonds apart): Morse with depth
-// eps_i eps_j at R_i + R_j factorised as P_i P_j e^{-2 alpha r} - L_i L_j e^{-alpha r}/2,
-// plus k_e Q_i Q_j / r.  Returns the sum of full pair energies (the caller halves it).
-__device__ __forceinline__ float pair_terms(const KArgs &A, const float4 *sp, const float4 *splq, int rbase, int n,
-                                            float3 xi, float4 me, uint4 ex, float &fx, float &fy, float &fz) {
-    float e = 0.f;
+// Non-bonded pairs (i, j) of this lane's atom i with j in [j0, j1) that are more than two
+// bonds apart: Morse with depth eps_i eps_j at R_i + R_j factorised as
+// P_i P_j e^{-2 alpha r} - L_i L_j e^{-alpha r}/2, plus k_e Q_i Q_j / r.  Adds the force on i
+// to (fx, fy, fz) and the full pair energies to e (the caller halves the sum).  Ranges are
+// block-uniform; consecutive ranges accumulate in the order of one pass over [0, n).
+__device__ __forceinline__ void pair_range(const KArgs &A, const float4 *sp, const float4 *splq, int rbase, int j0,
+                                           int j1, float3 xi, float4 me, uint4 ex, float &fx, float &fy, float &fz,
+                                           float &e) {
     const float keQ = A.ke * me.z;
-#pragma unroll
-    for (int w = 0; w < 4; ++w) {
-        const int jb = w * 32;
-        if (jb >= n) break;
+    for (int jb = j0 & ~31; jb < j1; jb += 32) {
+        const int w = jb >> 5;
         const unsigned m = w == 0 ? ex.x : (w == 1 ? ex.y : (w == 2 ? ex.z : ex.w));
-        const int je = min(n, jb + 32);
-        for (int j = jb; j < je; ++j) {
+        const int js = max(j0, jb), je = min(j1, jb + 32);
+        for (int j = js; j < je; ++j) {
             const float4 pj = sp[rbase + j];
             const float4 qj = splq[rbase + j];
             const float ddx = xi.x - pj.x, ddy = xi.y - pj.y, ddz = xi.z - pj.z;
@@ -315,7 +348,6 @@ __device__ __forceinline__ float pair_terms(const KArgs &A, const float4 *sp, co
             e += skip ? 0.f : (eu - el + ec);
         }
     }
-    return e;
 }
 
 // Bonds and angles incident to this lane's atom (each term evaluated by every
@@ -480,6 +512,7 @@ k_replicas(KArgs A) {
             if (s_any[par] == 0) break;                          // every replica of the pack is done
             if (MODE == MODE_NVE && live && s_nf[lr]) { st |= GFF_REP_NONFINITE; live = false; }
 
+            float pfx = 0.f, pfy = 0.f, pfz = 0.f, pe = 0.f;    // non-bonded pair sums (CACHE)
             // --- grid: owner hand-off, then four quad-gather rounds within the wave
             {
                 float4 t;
@@ -492,22 +525,33 @@ k_replicas(KArgs A) {
                 wave_sync();
                 if constexpr (CACHE) {
                     // stencils stay in registers across steps; a quad reloads its plane
-                    // only when its atom has moved to another cell
+                    // only when its atom has moved to another cell.  The reload of each
+                    // half plane is issued before a slice of the non-bonded pair loop and
+                    // mixed after it, so the pair work covers the memory latency.
+                    const bool pairs = A.include_intra && live;
 #pragma unroll
                     for (int rnd = 0; rnd < 4; ++rnd) {
                         const int o = wb + 16 * rnd + (wl >> 2);
                         const int4 ki = s_gi[o];
-                        const float4 ko = s_gt[o];
                         const int id = stencil_id(gv, ki);
-                        if (id != cid[rnd]) {
-                            if (id >= 0) {
-                                const float4 po = s_plq[o];
-                                quad_fetch<STORE>(gv, GridKey{ki.x, ki.y, ki.z, ki.w}, po.x, po.y, po.z, quad_s,
-                                                  cm[rnd]);
-                            }
-                            cid[rnd] = id;
+                        const bool need = id != cid[rnd] && id >= 0;
+                        float4 c[8];
+                        if (need) quad_issue<STORE>(gv, quad_addr<STORE>(gv, ki, quad_s), 0, c);
+                        if (pairs) pair_range(A, sp, s_plq, rbase, (2 * rnd) * n / 8, (2 * rnd + 1) * n / 8, x, me, ex,
+                                              pfx, pfy, pfz, pe);
+                        if (need) {
+                            const float4 po = s_plq[o];
+                            quad_mix(c, po.x * gv.s0, po.y * gv.s1, po.z * gv.s2, 0, cm[rnd]);
+                            quad_issue<STORE>(gv, quad_addr<STORE>(gv, ki, quad_s), 2, c);
                         }
-                        const float4 r = quad_contract(cm[rnd], ko, quad_s, id >= 0);
+                        if (pairs) pair_range(A, sp, s_plq, rbase, (2 * rnd + 1) * n / 8, (2 * rnd + 2) * n / 8, x, me,
+                                              ex, pfx, pfy, pfz, pe);
+                        if (need) {
+                            const float4 po = s_plq[o];
+                            quad_mix(c, po.x * gv.s0, po.y * gv.s1, po.z * gv.s2, 2, cm[rnd]);
+                        }
+                        cid[rnd] = id;
+                        const float4 r = quad_contract(cm[rnd], s_gt[o], quad_s, id >= 0);
                         if (quad_s == 0) s_gres[o] = r;
                     }
                 } else {
@@ -544,7 +588,14 @@ k_replicas(KArgs A) {
                         s_tres[2 * (lr * nt + q) + 1] = oB;
                     }
                     float fx = 0.f, fy = 0.f, fz = 0.f;
-                    e_intra += 0.5f * pair_terms(A, sp, s_plq, rbase, n, x, me, ex, fx, fy, fz);
+                    if constexpr (CACHE) {
+                        fx = pfx; fy = pfy; fz = pfz;
+                        e_intra += 0.5f * pe;
+                    } else {
+                        float e = 0.f;
+                        pair_range(A, sp, s_plq, rbase, 0, n, x, me, ex, fx, fy, fz, e);
+                        e_intra += 0.5f * e;
+                    }
                     e_intra += bond_angle_terms(A, sp, rbase, abase, at, x, fx, fy, fz);
                     F = F + make_float3(fx, fy, fz);
                 }
