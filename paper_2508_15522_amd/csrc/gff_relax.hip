@@ -256,8 +256,8 @@ __device__ __forceinline__ void quad_fetch(const GridView &g, GridKey key, float
 }
 
 // Quad side, split fetch for overlapping the loads with other work: quad_issue loads the
-// nodes of x-planes a0, a0+1 (8 columns) of the lane's plane; quad_mix mixes them into
-// m[4 a0 .. 4 a0 + 7] with the same arithmetic as quad_fetch.
+// nodes of x-planes a0, a0+1 (8 columns) of the lane's plane; quad_mix decodes and mixes
+// them into m[4 a0 .. 4 a0 + 7] with the same arithmetic as quad_fetch.
 struct QuadAddr { int xoff[4], yoff[4]; };
 template <int STORE>
 __device__ __forceinline__ QuadAddr quad_addr(const GridView &g, int4 ki, int s) {
@@ -276,16 +276,48 @@ __device__ __forceinline__ QuadAddr quad_addr(const GridView &g, int4 ki, int s)
     for (int a = 0; a < 4; ++a) q.xoff[a] = ix[a] * g.ny * col_stride;
     return q;
 }
+// Raw node words as loaded (F32: three channel floats; F16: two words of packed halves);
+// decoding is left to the mixing step so that nothing waits on the load before then.
+template <int STORE> struct RawNode;
+template <> struct RawNode<GFF_STORE_F32> { unsigned w[3]; };
+template <> struct RawNode<GFF_STORE_F16> { unsigned w[2]; };
+
 template <int STORE>
-__device__ __forceinline__ void quad_issue(const GridView &g, const QuadAddr &q, int a0, float4 c[8]) {
+__device__ __forceinline__ RawNode<STORE> load_raw(__amdgpu_buffer_rsrc_t r, int off) {
+    RawNode<STORE> n;
+    if constexpr (STORE == GFF_STORE_F32) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b96(r, off, 0, 0);
+        n.w[0] = v[0]; n.w[1] = v[1]; n.w[2] = v[2];
+    } else {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+        n.w[0] = v[0]; n.w[1] = v[1];
+    }
+    return n;
+}
+
+template <int STORE>
+__device__ __forceinline__ float mix_raw(const RawNode<STORE> &n, float Ps, float Ls, float Qs) {
+    if constexpr (STORE == GFF_STORE_F32) {
+        return Ps * __uint_as_float(n.w[0]) + Ls * __uint_as_float(n.w[1]) + Qs * __uint_as_float(n.w[2]);
+    } else {
+        const unsigned lo = n.w[0], hi = n.w[1];
+        const float2 fa = __half22float2(*reinterpret_cast<const __half2 *>(&lo));
+        const float2 fb = __half22float2(*reinterpret_cast<const __half2 *>(&hi));
+        return Ps * fa.x + Ls * fa.y + Qs * fb.x;
+    }
+}
+
+template <int STORE>
+__device__ __forceinline__ void quad_issue(const GridView &g, const QuadAddr &q, int a0, RawNode<STORE> c[8]) {
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) c[4 * a + b] = load_node_buf<STORE>(g.rsrc, q.xoff[a0 + a] + q.yoff[b]);
+        for (int b = 0; b < 4; ++b) c[4 * a + b] = load_raw<STORE>(g.rsrc, q.xoff[a0 + a] + q.yoff[b]);
 }
-__device__ __forceinline__ void quad_mix(const float4 c[8], float Ps, float Ls, float Qs, int a0, float m[16]) {
+template <int STORE>
+__device__ __forceinline__ void quad_mix(const RawNode<STORE> c[8], float Ps, float Ls, float Qs, int a0, float m[16]) {
 #pragma unroll
-    for (int k = 0; k < 8; ++k) m[4 * a0 + k] = Ps * c[k].x + Ls * c[k].y + Qs * c[k].z;
+    for (int k = 0; k < 8; ++k) m[4 * a0 + k] = mix_raw<STORE>(c[k], Ps, Ls, Qs);
 }
 
 // Quad side, contraction: the lane's share of the tensor-product sum over its plane; the
@@ -535,20 +567,20 @@ k_replicas(KArgs A) {
                         const int4 ki = s_gi[o];
                         const int id = stencil_id(gv, ki);
                         const bool need = id != cid[rnd] && id >= 0;
-                        float4 c[8];
+                        RawNode<STORE> c[8];
                         if (need) quad_issue<STORE>(gv, quad_addr<STORE>(gv, ki, quad_s), 0, c);
                         if (pairs) pair_range(A, sp, s_plq, rbase, (2 * rnd) * n / 8, (2 * rnd + 1) * n / 8, x, me, ex,
                                               pfx, pfy, pfz, pe);
                         if (need) {
                             const float4 po = s_plq[o];
-                            quad_mix(c, po.x * gv.s0, po.y * gv.s1, po.z * gv.s2, 0, cm[rnd]);
+                            quad_mix<STORE>(c, po.x * gv.s0, po.y * gv.s1, po.z * gv.s2, 0, cm[rnd]);
                             quad_issue<STORE>(gv, quad_addr<STORE>(gv, ki, quad_s), 2, c);
                         }
                         if (pairs) pair_range(A, sp, s_plq, rbase, (2 * rnd + 1) * n / 8, (2 * rnd + 2) * n / 8, x, me,
                                               ex, pfx, pfy, pfz, pe);
                         if (need) {
                             const float4 po = s_plq[o];
-                            quad_mix(c, po.x * gv.s0, po.y * gv.s1, po.z * gv.s2, 2, cm[rnd]);
+                            quad_mix<STORE>(c, po.x * gv.s0, po.y * gv.s1, po.z * gv.s2, 2, cm[rnd]);
                         }
                         cid[rnd] = id;
                         const float4 r = quad_contract(cm[rnd], s_gt[o], quad_s, id >= 0);
