@@ -36,10 +36,10 @@ COUNTER_SCALE = {"fetch": 2.0, "write": 1.0}
 MEASURED_TRAFFIC = {
     ("f32", 16384, 5000): {
         "sources": {"paper_2508_15522_amd/csrc/gff_relax.hip":
-                    "c37adc7daf0e71445b1c50a0a775775d202afba4cc9bfb071b2531c7bfc5e12c",
+                    "6146a3a0baa165fa866240563ce1ede0c152c9d1ad377019eab1c5355ff97819",
                     "paper_2508_15522_amd/csrc/gff_internal.hpp":
-                    "2541d985592bf136de3a32b4ab68e73197f155600dca9b8bdd0ff59e5c74d948"},
-        "fetch_kib": 3420570078.5625, "write_kib": 16170.59375,
+                    "0f1b5c8a61f7e25dc89b990b2e2dc102cab89a75d27295dcb91d10cc002b91f4"},
+        "fetch_kib": 286451277.75, "write_kib": 11689164.53125,
     },
 }
 
