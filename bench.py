@@ -11,6 +11,10 @@ all inside the kernel).  value = replica-steps/s over the K timed launches.
 Prints one JSON line.  Roofline: the dominant kernel is the replica kernel; its algorithmic
 traffic is 64 stencil nodes x 3 channels x (4 B FP32 | 2 B FP16) per atom per force
 evaluation, divided by the kernel's mean launch time from HIP events on its stream.
+`traffic` (fabric bytes per launch) and `valu` (VALU wave instructions per launch, and
+their share of the issue slots in the measured time) come from rocprofv3 counters stored
+below with the digests of the kernel sources they were taken on; both are null once those
+sources change.
 """
 from __future__ import annotations
 
@@ -40,12 +44,15 @@ MEASURED_TRAFFIC = {
                     "paper_2508_15522_amd/csrc/gff_internal.hpp":
                     "0f1b5c8a61f7e25dc89b990b2e2dc102cab89a75d27295dcb91d10cc002b91f4"},
         "fetch_kib": 286451277.75, "write_kib": 11689164.53125,
+        "valu_insts": 222037590601.0,          # SQ_INSTS_VALU (wave instructions) of the launch
     },
 }
+# FP32 VALU issue slots per second: 256 CUs x 4 SIMDs x 2.4 GHz / 4 cycles per wave64 instruction
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 
 
-def measured_traffic(storage, n_rep, md_steps):
-    """Bytes per launch from the stored counters, or None if the kernel has changed since."""
+def _counters(storage, n_rep, md_steps):
+    """The stored counter record for this launch, or None if the kernel has changed since."""
     import hashlib
     rec = MEASURED_TRAFFIC.get((storage, n_rep, md_steps))
     if rec is None:
@@ -54,7 +61,25 @@ def measured_traffic(storage, n_rep, md_steps):
         with open(os.path.join(ROOT, path), "rb") as f:
             if hashlib.sha256(f.read()).hexdigest() != digest:
                 return None
+    return rec
+
+
+def measured_traffic(storage, n_rep, md_steps):
+    """Fabric bytes per launch from the stored counters (None if the kernel has changed)."""
+    rec = _counters(storage, n_rep, md_steps)
+    if rec is None:
+        return None
     return rec["fetch_kib"] * 1024 * COUNTER_SCALE["fetch"] + rec["write_kib"] * 1024 * COUNTER_SCALE["write"]
+
+
+def valu_utilisation(storage, n_rep, md_steps, kernel_s):
+    """Stored VALU instruction count of the launch over the issue slots of the measured
+    launch time (None if the kernel has changed since the counters were taken)."""
+    rec = _counters(storage, n_rep, md_steps)
+    if rec is None or "valu_insts" not in rec:
+        return None
+    return {"insts": rec["valu_insts"], "issue_frac": rec["valu_insts"] / (VALU_ISSUE_PEAK * kernel_s),
+            "peak_insts_per_s": VALU_ISSUE_PEAK}
 
 
 def log(msg):
@@ -183,6 +208,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(args.storage, n_rep, args.md_steps),
+                     "valu": valu_utilisation(args.storage, n_rep, args.md_steps, kern_avg),
                      "kernel": f"k_replicas<{args.storage},NVE>",
                      "bytes_per_launch": alg_bytes},
     }
