@@ -225,7 +225,10 @@ def main():
         cmp = SM.compare_learned_vs_uniform(g32, S.mol_chain24(), collect_rounds=4, collect_rep=4096,
                                             train_steps=300, eval_rounds=4, eval_rep=2048, log=log)
         res["minima_per_s"] = {"learned": cmp["learned"]["minima_per_s"], "uniform": cmp["uniform"]["minima_per_s"],
-                               "gain": cmp["gain_minima_per_s"], "detail": cmp,
+                               "gain": cmp["gain_minima_per_s"],
+                               "flow_learned": cmp["learned"]["flow"]["minima_per_s"],
+                               "flow_uniform": cmp["uniform"]["flow"]["minima_per_s"],
+                               "flow_gain": cmp["gain_minima_per_s_flow"], "detail": cmp,
                                "workload": "chain24 FIRE to 1e-4 eV/A (max 5000 steps), distinct within 0.01 eV"}
     for extra in args.extra:
         res.setdefault("other_workloads", {})[extra] = run_workload(extra, log)

@@ -287,6 +287,17 @@ gff_status gff_autotune(const gff_grid *grid, const gff_topology *topo, int n_re
 gff_status gff_propose_uniform(int n_rep, int n_tors, uint64_t seed, uint32_t round, float h_lo, float h_hi,
                                float *d_dof, uint32_t *d_raw, void *stream);
 
+/* Continuous-flow relaxation (the batching of Section "Configuration sampling on GPU" with
+ * replicas replaced as they finish): per replica r of `plan`, d_mode[r] = 1 loads a new
+ * proposal -- positions from d_pos_src [3][N] (same layout as state->d_pos), velocities 0,
+ * FIRE dt = dt0, alpha = alpha0, positive-power count 0 (FIRE arrays nullable), status 0;
+ * d_mode[r] = 2 freezes the replica (velocities 0, status GFF_REP_CONVERGED: later launches
+ * evaluate it without moving it); 0 leaves it.  Relaxing in launches of a fixed step count
+ * with refills in between gives each proposal the trajectory of one uninterrupted launch.
+ * All buffers are caller-owned device memory; asynchronous on `stream`. */
+gff_status gff_refill(const gff_plan *plan, const int *d_mode, const float *d_pos_src, float dt0, float alpha0,
+                      const gff_state *state, void *stream);
+
 /* Pose construction from DOF (rows of dof_stride floats) for every replica of `plan`:
  * reference geometry of the type; each rotatable torsion k in order set to phi_k by rotating
  * its moving atoms about the j->k bond; rotation about the centroid by the quaternion;

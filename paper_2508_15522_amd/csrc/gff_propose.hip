@@ -353,3 +353,45 @@ extern "C" gff_status gff_pose_from_dof(const gff_topology *topo, const gff_plan
                        d_pos);
     return hip_status(hipGetLastError());
 }
+
+// Continuous-flow relaxation: per replica, mode[r] = 1 replaces its state by a new proposal
+// (positions from src, zero velocities, FIRE scalars reset, status cleared), 2 freezes it
+// (zero velocities, status CONVERGED, so later launches only evaluate it), 0 leaves it.
+__global__ void k_refill(int n_rep, int N, const int *atom_off, const int *mode, const float *src, float *pos,
+                         float *vel, float *fdt, float *falpha, int *fnpos, unsigned *status, float dt0, float a0) {
+    const int r = blockIdx.x;
+    if (r >= n_rep) return;
+    const int m = mode[r];
+    if (m != 1 && m != 2) return;
+    const int b = atom_off[r], n = atom_off[r + 1] - b;
+    for (int a = threadIdx.x; a < n; a += blockDim.x) {
+        const int g = b + a;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            if (m == 1) pos[g + (size_t)c * N] = src[g + (size_t)c * N];
+            vel[g + (size_t)c * N] = 0.f;
+        }
+    }
+    if (threadIdx.x == 0) {
+        if (m == 1) {
+            if (fdt) fdt[r] = dt0;
+            if (falpha) falpha[r] = a0;
+            if (fnpos) fnpos[r] = 0;
+            status[r] = 0u;
+        } else {
+            status[r] = GFF_REP_CONVERGED;
+        }
+    }
+}
+
+extern "C" gff_status gff_refill(const gff_plan *plan, const int *d_mode, const float *d_pos_src, float dt0,
+                                 float alpha0, const gff_state *state, void *stream) {
+    if (!plan || !state || !state->d_pos || !state->d_vel || !state->d_status) return GFF_EINVAL;
+    if (plan->n_rep > 0 && (!d_mode || !d_pos_src)) return GFF_EINVAL;
+    if (plan->n_rep == 0) return GFF_OK;
+    hipLaunchKernelGGL(k_refill, dim3(plan->n_rep), dim3(64), 0, (hipStream_t)stream, plan->n_rep, plan->n_atoms,
+                       plan->d_atom_off, d_mode, d_pos_src, state->d_pos, state->d_vel, state->d_fire_dt,
+                       state->d_fire_alpha, state->d_fire_npos, state->d_status, dt0, alpha0);
+    return hip_status(hipGetLastError());
+}
+

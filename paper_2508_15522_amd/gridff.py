@@ -264,7 +264,8 @@ def relax_batch(grid_desc, topo, plan, params, st, d_E_rep, d_fnorm, d_steps, d_
 EXPORTS += ["gff_propose_uniform", "gff_pose_from_dof", "gff_encode_pose", "gff_decode_dof", "gff_dedupe_energy",
             "gff_mlp_n_params", "gff_mlp_create", "gff_mlp_destroy", "gff_mlp_get_params", "gff_mlp_workspace_bytes",
             "gff_mlp_forward", "gff_mlp_train_step", "gff_imle_select", "gff_normal_philox", "gff_gemm_bf16",
-            "gff_gather_rows", "gff_relax_graph_create", "gff_graph_launch", "gff_graph_destroy", "gff_autotune"]
+            "gff_gather_rows", "gff_relax_graph_create", "gff_graph_launch", "gff_graph_destroy", "gff_autotune",
+            "gff_refill"]
 N_ENC = 41
 
 
@@ -275,6 +276,17 @@ def _rt(name, restype):
 def propose_uniform(n_rep, n_tors, seed, rnd, h_lo, h_hi, d_dof, d_raw=None, stream=None):
     check(lib().gff_propose_uniform(C.c_int(n_rep), C.c_int(n_tors), C.c_uint64(seed), C.c_uint32(rnd),
                                     C.c_float(h_lo), C.c_float(h_hi), _ptr(d_dof), _ptr(d_raw), _stream(stream)))
+
+
+def refill(plan, d_mode, d_pos_src, st, dt0=0.05, alpha0=0.1, stream=None):
+    """Replace (mode 1) or freeze (mode 2) replicas of a relaxation state between launches."""
+    state = State(st["pos"].data_ptr(), st["vel"].data_ptr(),
+                  st["fire_dt"].data_ptr() if "fire_dt" in st else None,
+                  st["fire_alpha"].data_ptr() if "fire_alpha" in st else None,
+                  st["fire_npos"].data_ptr() if "fire_npos" in st else None,
+                  st["status"].data_ptr())
+    check(lib().gff_refill(plan.handle, _ptr(d_mode), _ptr(d_pos_src), C.c_float(dt0), C.c_float(alpha0),
+                           C.byref(state), _stream(stream)))
 
 
 def pose_from_dof(topo, plan, d_dof, dof_stride, Lx, Ly, z_top, d_pos, stream=None):

@@ -112,6 +112,101 @@ class Sampler:
         return RoundStats(self.n_rep, int(okh.sum()), int(newh.sum()),
                           float(steps[okh].mean()) if okh.any() else float("nan"), time.time() - t0, move)
 
+    # ---------------------------------------------------------------- continuous flow
+    def propose_uniform_rows(self, rnd):
+        G.propose_uniform(self.n_rep, self.T, self.seed, rnd, H_LO, H_HI, self.dof)
+
+    def propose_learned_rows(self, mlp):
+        noise = torch.empty(self.n_rep, 64, device="cuda")
+        enc = torch.empty(self.n_rep, 41, device="cuda")
+
+        def fill(rnd):
+            G.normal_philox(self.n_rep * 64, self.seed + 1, rnd, noise)
+            mlp.forward(noise, self.types, enc)
+            G.decode_dof(enc, self.T, DEC_LO, DEC_HI, self.dof)
+        return fill
+
+    def flow(self, archive, n_proposals, propose, chunk=250, record=False):
+        """Continuous-flow relaxation of n_proposals proposals through the n_rep slots:
+        FIRE launches of `chunk` steps continue every slot's state; between launches the
+        slots whose proposal converged, went non-finite or used its max_steps budget are
+        harvested (converged minima deduplicated into `archive`) and refilled with new
+        proposals (`propose(rnd)` fills self.dof for every slot; the refilled slots take
+        their rows).  Each proposal follows the trajectory one uninterrupted launch of
+        max_steps would give it (max_steps must be a multiple of chunk).  Returns a dict of
+        counts and the wall time; with record=True also each harvested proposal's DOF row,
+        energy, convergence flag and move count."""
+        assert self.max_steps % chunk == 0
+        n = self.n_rep
+        t0 = time.time()
+        st = {"pos": torch.empty(3, self.plan.n_atoms, device="cuda"),
+              "vel": torch.zeros(3, self.plan.n_atoms, device="cuda"),
+              "fire_dt": torch.full((n,), 0.05, device="cuda"),
+              "fire_alpha": torch.full((n,), 0.1, device="cuda"),
+              "fire_npos": torch.zeros(n, dtype=torch.int32, device="cuda"),
+              "status": torch.zeros(n, dtype=torch.int32, device="cuda")}
+        pos_new = torch.empty_like(st["pos"])
+        rnd = 0
+        propose(rnd)
+        G.pose_from_dof(self.topo, self.plan, self.dof, 7 + self.T, self.Lx, self.Ly, 0.0, st["pos"])
+        dof_slot = self.dof.cpu().numpy().copy() if record else None
+        active = np.ones(n, bool)
+        if n_proposals < n:
+            active[n_proposals:] = False
+        issued = int(active.sum())
+        moves = np.zeros(n, np.int64)
+        mode = torch.zeros(n, dtype=torch.int32, device="cuda")
+        if not active.all():
+            mode.copy_(torch.from_numpy(np.where(active, 0, 2).astype(np.int32)))
+            G.refill(self.plan, mode, st["pos"], st)
+        prm = G.relax_params(G.MODE_FIRE, chunk, True, f_conv=self.f_conv)
+        conv_total, new_total, done_total, steps_conv, rec = 0, 0, 0, [], []
+        launches = 0
+        while active.any():
+            G.relax_batch(self.grid.desc, self.topo, self.plan, prm, st, self.out["E"], self.out["fnorm"],
+                          self.out["steps"])
+            launches += 1
+            status = st["status"].cpu().numpy()
+            moves += np.where(active, self.out["steps"].cpu().numpy(), 0)
+            conv = active & ((status & G.REP_CONVERGED) != 0)
+            done = active & (conv | ((status & G.REP_NONFINITE) != 0) | (moves >= self.max_steps))
+            if not done.any():
+                continue
+            ok = torch.from_numpy(conv.astype(np.int32)).cuda()
+            G.dedupe_energy(self.out["E"], self.types, ok, 0.01, archive.capacity, archive.E, archive.types,
+                            archive.n, self.is_new)
+            new_total += int(self.is_new.sum().item())
+            conv_total += int(conv.sum()); done_total += int(done.sum())
+            steps_conv += list(moves[conv])
+            if record:
+                E = self.out["E"].cpu().numpy()
+                for k in np.where(done)[0]:
+                    rec.append((dof_slot[k].copy(), float(E[k]), bool(conv[k]), int(moves[k])))
+            idx = np.where(done)[0]
+            take = idx[:max(0, min(len(idx), n_proposals - issued))]
+            m = np.zeros(n, np.int32)
+            m[idx] = 2
+            if len(take):
+                rnd += 1
+                propose(rnd)
+                G.pose_from_dof(self.topo, self.plan, self.dof, 7 + self.T, self.Lx, self.Ly, 0.0, pos_new)
+                m[take] = 1
+                if record:
+                    rows = self.dof.cpu().numpy()
+                    dof_slot[take] = rows[take]
+                issued += len(take)
+            mode.copy_(torch.from_numpy(m))
+            G.refill(self.plan, mode, pos_new, st)
+            moves[idx] = 0
+            active[idx] = False
+            active[take] = True
+        torch.cuda.synchronize()
+        res = dict(proposals=done_total, converged=conv_total, new_minima=new_total, seconds=time.time() - t0,
+                   launches=launches, mean_steps_converged=float(np.mean(steps_conv)) if steps_conv else float("nan"))
+        if record:
+            res["records"] = rec
+        return res
+
     def encode_minima(self, pos, mask):
         """Encodings [m][41] of the replicas selected by mask (host bool array)."""
         work = torch.empty_like(pos)
@@ -205,6 +300,20 @@ def compare_learned_vs_uniform(grid, mol, collect_rounds=6, collect_rep=4096, tr
                          mean_rms_move=float(np.nanmean(moves)))
         say(f"{name}: {n_min} distinct minima from {props} proposals ({conv} converged) in {secs:.2f} s, "
             f"mean FIRE steps {res[name]['mean_fire_steps']:.0f}, mean RMS move {res[name]['mean_rms_move']:.2f} A")
+    # the same comparison in continuous flow (finished slots refilled between 250-step
+    # launches), where a proposal costs the steps it needs rather than its launch's slowest
+    for name in ("uniform", "learned"):
+        fl = Sampler(grid, mol, eval_rep, seed=seed + 29)
+        prop = fl.propose_uniform_rows if name == "uniform" else fl.propose_learned_rows(mlp)
+        a = Archive()
+        r = fl.flow(a, eval_rounds * eval_rep, prop, chunk=250)
+        res[name]["flow"] = dict(distinct_minima=r["new_minima"], proposals=r["proposals"], converged=r["converged"],
+                                 seconds=r["seconds"], minima_per_s=r["new_minima"] / r["seconds"],
+                                 mean_fire_steps=r["mean_steps_converged"], launches=r["launches"])
+        say(f"{name} (flow): {r['new_minima']} distinct minima from {r['proposals']} proposals ({r['converged']} "
+            f"converged) in {r['seconds']:.2f} s")
+    res["gain_minima_per_s_flow"] = (res["learned"]["flow"]["minima_per_s"] /
+                                     max(res["uniform"]["flow"]["minima_per_s"], 1e-12))
     res["training"] = dict(minima=m, distinct=arch.count(), steps=train_steps, loss_first=hist[0][1],
                            loss_last=hist[-1][1], collect_s=collect_s, train_s=train_s)
     res["gain_minima_per_s"] = res["learned"]["minima_per_s"] / max(res["uniform"]["minima_per_s"], 1e-12)

@@ -209,3 +209,41 @@ def test_mlp_forward_backward_adam_imle():
     bo, do = OS.imle_select(cand.cpu().numpy().astype(np.float64), target, ntors)
     assert (best.cpu().numpy() == bo).mean() > 0.99
     assert np.allclose(bd.cpu().numpy(), do, rtol=1e-5)
+
+
+def test_continuous_flow_matches_single_launch():
+    """Relaxing in 250-step launches with finished replicas replaced by new proposals gives
+    every proposal exactly the result of one uninterrupted launch (same energy, convergence
+    flag and move count, bit for bit)."""
+    announce("continuous flow")
+    from paper_2508_15522_amd import configs, sampling as SM
+    D.require_gpu()
+    cfg = configs.GRID_SMALL
+    grid = D.build_physical_grid(cfg.substrate(), D.spec_for(cfg))
+    mol = S.mol_chain24()
+    smp = SM.Sampler(grid, mol, 128, max_steps=1000)
+    arch = SM.Archive()
+    res = smp.flow(arch, 400, smp.propose_uniform_rows, chunk=250, record=True)
+    recs = res["records"]
+    assert res["proposals"] == 400 and len(recs) == 400
+    assert res["new_minima"] == arch.count() > 0
+    dof = torch.from_numpy(np.stack([r[0] for r in recs]).astype(np.float32)).cuda()
+    topo = G.Topology([mol])
+    plan = G.Plan(topo, np.zeros(len(recs), np.int32))
+    st = {"pos": torch.empty(3, plan.n_atoms, device="cuda"),
+          "vel": torch.zeros(3, plan.n_atoms, device="cuda"),
+          "fire_dt": torch.full((len(recs),), 0.05, device="cuda"),
+          "fire_alpha": torch.full((len(recs),), 0.1, device="cuda"),
+          "fire_npos": torch.zeros(len(recs), dtype=torch.int32, device="cuda"),
+          "status": torch.zeros(len(recs), dtype=torch.int32, device="cuda")}
+    G.pose_from_dof(topo, plan, dof, dof.shape[1], grid.Lx, grid.Ly, 0.0, st["pos"])
+    out = D.outputs(plan)
+    G.relax_batch(grid.desc, topo, plan, G.relax_params(G.MODE_FIRE, 1000, True), st, out["E"], out["fnorm"],
+                  out["steps"])
+    torch.cuda.synchronize()
+    conv = (st["status"].cpu().numpy() & G.REP_CONVERGED) != 0
+    E = out["E"].cpu().numpy()
+    steps = out["steps"].cpu().numpy()
+    assert np.array_equal(conv, np.array([r[2] for r in recs]))
+    assert np.array_equal(E, np.array([r[1] for r in recs]))
+    assert np.array_equal(steps, np.array([r[3] for r in recs]))
