@@ -223,7 +223,7 @@ def main():
         log("learned vs uniform proposals (minima found per second)")
         g32 = grid if args.storage == "f32" else setup(G.STORE_F32)
         cmp = SM.compare_learned_vs_uniform(g32, S.mol_chain24(), collect_rounds=4, collect_rep=4096,
-                                            train_steps=300, eval_rounds=4, eval_rep=2048, log=log)
+                                            train_steps=300, eval_rounds=4, eval_rep=8192, log=log)
         res["minima_per_s"] = {"learned": cmp["learned"]["minima_per_s"], "uniform": cmp["uniform"]["minima_per_s"],
                                "gain": cmp["gain_minima_per_s"],
                                "flow_learned": cmp["learned"]["flow"]["minima_per_s"],
