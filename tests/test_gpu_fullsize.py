@@ -1,0 +1,114 @@
+"""Parity at the workloads' full sizes, in the launch shapes the benchmark times.
+
+The replica kernel runs every replica of a workload (16 384 x 38 atoms NVE on the
+112 x 112 x 150 grid; 65 536 x 38 atoms FIRE on the 452 x 452 x 200 grid; 4096 replicas of
+eight sizes FIRE with the autotuned launch), on seeded random coefficients of the workload's
+grid size; a sample of replicas is then re-run one by one by the FP64 oracle on the same
+FP32-rounded coefficients and inputs.  Tolerances as in the short-run parity tests: FP32
+trajectories within 2e-4 A of the FP64 ones, identical step counts and status flags.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2508_15522_amd import autotune as AT, configs, device as D, gridff as G, synth as S
+from tests.gpu_common import COEF_SCALE, announce
+
+pytestmark = pytest.mark.gpu
+
+
+def _grid(cfg, seed):
+    B = S.random_coefficients(cfg.nx, cfg.ny, cfg.nz, seed, COEF_SCALE)     # FP32-representable
+    L = cfg.n_cells * S.SLAB_A
+    return D.pack_from_coefficients(B, D.spec_for(cfg), G.STORE_F32, L, L), B
+
+
+def _sample(n, extra=()):
+    return np.unique(np.array([0, 1, n // 3, n // 2 + 7, n - 2, n - 1, *extra]))
+
+
+def test_c2_nve_full_size_sampled():
+    D.require_gpu()
+    announce("full size: 16384 x pah38 NVE, block 256")
+    cfg = configs.GRID_SMALL
+    grid, Bref = _grid(cfg, 21)
+    mol = S.mol_pah38()
+    n_rep = configs.C2_PAH_NVE.n_rep
+    sub = cfg.substrate()
+    pos = S.f32(S.place_replicas(mol, n_rep, sub, S.SEED_PLACE * 2))
+    vel = S.f32(S.mb_velocities(mol.mass, n_rep, 300.0, S.SEED_NVE))
+    topo = G.Topology([mol])
+    plan = G.Plan(topo, np.zeros(n_rep, np.int32), block_threads=256)
+    st = D.fire_state(plan, list(pos), vel_per_rep=list(vel))
+    out = D.outputs(plan)
+    n = 20
+    G.relax_batch(grid.desc, topo, plan, G.relax_params(G.MODE_NVE, n, True, dt=0.5, drift_every=1), st,
+                  out["E"], out["fnorm"], out["steps"], out["drift"])
+    torch.cuda.synchronize()
+    idx = _sample(n_rep)
+    xg = D.unsoa(plan, st["pos"])
+    ref = O.nve_batch(Bref, grid.geometry, [mol], np.zeros(len(idx), np.int32), np.concatenate(pos[idx]),
+                      np.concatenate(vel[idx]), n, dt=0.5, drift_every=1)
+    dx = np.abs(np.concatenate([xg[i] for i in idx]) - ref["pos"]).max()
+    dr = out["drift"].cpu().numpy()[idx]
+    announce(f"  max |dx| = {dx:.3e} A; E0 diff {np.abs(dr[:, 0] - ref['drift'][:, 0]).max():.3e} eV")
+    assert dx < 2e-4
+    assert np.abs(dr[:, 0] - ref["drift"][:, 0]).max() < 2e-5 * mol.n
+    assert np.array_equal(dr[:, 5], ref["drift"][:, 5])
+    assert (out["steps"].cpu().numpy() == n).all()
+    assert np.isfinite(out["E"].cpu().numpy()).all()
+
+
+def _fire_check(grid, Bref, mols, rep_type, pos, plan, topo, n, idx):
+    st = D.fire_state(plan, pos)
+    out = D.outputs(plan)
+    G.relax_batch(grid.desc, topo, plan, G.relax_params(G.MODE_FIRE, n, True, f_conv=1e-4), st, out["E"],
+                  out["fnorm"], out["steps"])
+    torch.cuda.synchronize()
+    xg = D.unsoa(plan, st["pos"])
+    ref = O.fire_batch(Bref, grid.geometry, mols, rep_type[idx], np.concatenate([pos[i] for i in idx]), n)
+    dx = np.abs(np.concatenate([xg[i] for i in idx]) - ref["pos"]).max()
+    nat = np.array([mols[t].n for t in rep_type[idx]])
+    dE = np.abs(out["E"].cpu().numpy()[idx] - ref["E"])
+    announce(f"  max |dx| = {dx:.3e} A, max |dE|/atom = {(dE / nat).max():.3e} eV")
+    assert dx < 2e-4
+    assert (dE < 2e-5 * nat + 1e-6 * np.abs(ref["E"])).all()
+    assert np.array_equal(out["steps"].cpu().numpy()[idx], ref["steps"])
+    assert np.array_equal(st["status"].cpu().numpy()[idx], ref["status"])
+
+
+def test_c5_fire_large_grid_full_size_sampled():
+    D.require_gpu()
+    announce("full size: 65536 x pah38 FIRE on the 452 x 452 x 200 grid, block 256")
+    cfg = configs.GRID_LARGE
+    grid, Bref = _grid(cfg, 22)
+    mol = S.mol_pah38()
+    n_rep = configs.C5_PAH_FIRE_LARGE.n_rep
+    pos = list(S.f32(S.place_replicas(mol, n_rep, cfg.substrate(), S.SEED_PLACE)))
+    topo = G.Topology([mol])
+    rep_type = np.zeros(n_rep, np.int32)
+    plan = G.Plan(topo, rep_type, block_threads=256)
+    _fire_check(grid, Bref, [mol], rep_type, pos, plan, topo, 10, _sample(n_rep))
+
+
+def test_c3_sizes_autotuned_full_size_sampled():
+    D.require_gpu()
+    announce("full size: 4096 replicas of 8 sizes FIRE, autotuned launch")
+    cfg = configs.GRID_SMALL
+    grid, Bref = _grid(cfg, 23)
+    mols = S.molecule_types("sizes")
+    n_rep = configs.C3_SIZES_FIRE.n_rep
+    rep_type = (np.arange(n_rep) % len(mols)).astype(np.int32)
+    sub = cfg.substrate()
+    per_type = [iter(S.f32(S.place_replicas(m, int((rep_type == t).sum()), sub, S.SEED_PLACE * 3 + t)))
+                for t, m in enumerate(mols)]
+    pos = [next(per_type[t]) for t in rep_type]
+    topo = G.Topology(mols)
+    st0 = D.fire_state(G.Plan(topo, rep_type), pos)
+    launch, _ = AT.launch_for(grid, topo, rep_type, G.relax_params(G.MODE_FIRE, 20, True, f_conv=1e-4), st0,
+                              use_cache=False)
+    announce(f"  launch {launch}")
+    plan = G.Plan(topo, rep_type, *launch)
+    idx = _sample(n_rep, extra=range(8, 16))                   # every molecule size
+    _fire_check(grid, Bref, mols, rep_type, pos, plan, topo, 10, idx)
