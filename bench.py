@@ -33,28 +33,28 @@ HBM_PEAK_GBS = 8000.0
 
 # Fabric-side traffic of the replica kernel (L2 misses to MALL/HBM) from two rocprofv3 --pmc
 # passes, FETCH_SIZE then WRITE_SIZE, in KiB for one launch of the workload named by the key
-# (storage, replicas, MD steps).  A plain 1 GiB elementwise kernel reads as 512 MiB by
+# (storage, replicas, MD steps, block threads).  A plain 1 GiB elementwise kernel reads as 512 MiB by
 # FETCH_SIZE and writes as 1 GiB by WRITE_SIZE, so the counters are scaled by 2.0 and 1.0.
 # The figures hold only for the kernel sources whose SHA-256 they carry.
 COUNTER_SCALE = {"fetch": 2.0, "write": 1.0}
 MEASURED_TRAFFIC = {
-    ("f32", 16384, 5000): {
+    ("f32", 16384, 5000, 192): {
         "sources": {"paper_2508_15522_amd/csrc/gff_relax.hip":
                     "6146a3a0baa165fa866240563ce1ede0c152c9d1ad377019eab1c5355ff97819",
                     "paper_2508_15522_amd/csrc/gff_internal.hpp":
                     "0f1b5c8a61f7e25dc89b990b2e2dc102cab89a75d27295dcb91d10cc002b91f4"},
-        "fetch_kib": 286451277.75, "write_kib": 11689164.53125,
-        "valu_insts": 222037590601.0,          # SQ_INSTS_VALU (wave instructions) of the launch
+        "fetch_kib": 292215755.75, "write_kib": 11601174.0,
+        "valu_insts": 204741970915.0,          # SQ_INSTS_VALU (wave instructions) of the launch
     },
 }
 # FP32 VALU issue slots per second: 256 CUs x 4 SIMDs x 2.4 GHz / 4 cycles per wave64 instruction
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 
 
-def _counters(storage, n_rep, md_steps):
+def _counters(storage, n_rep, md_steps, block):
     """The stored counter record for this launch, or None if the kernel has changed since."""
     import hashlib
-    rec = MEASURED_TRAFFIC.get((storage, n_rep, md_steps))
+    rec = MEASURED_TRAFFIC.get((storage, n_rep, md_steps, block))
     if rec is None:
         return None
     for path, digest in rec["sources"].items():
@@ -64,18 +64,18 @@ def _counters(storage, n_rep, md_steps):
     return rec
 
 
-def measured_traffic(storage, n_rep, md_steps):
+def measured_traffic(storage, n_rep, md_steps, block):
     """Fabric bytes per launch from the stored counters (None if the kernel has changed)."""
-    rec = _counters(storage, n_rep, md_steps)
+    rec = _counters(storage, n_rep, md_steps, block)
     if rec is None:
         return None
     return rec["fetch_kib"] * 1024 * COUNTER_SCALE["fetch"] + rec["write_kib"] * 1024 * COUNTER_SCALE["write"]
 
 
-def valu_utilisation(storage, n_rep, md_steps, kernel_s):
+def valu_utilisation(storage, n_rep, md_steps, block, kernel_s):
     """Stored VALU instruction count of the launch over the issue slots of the measured
     launch time (None if the kernel has changed since the counters were taken)."""
-    rec = _counters(storage, n_rep, md_steps)
+    rec = _counters(storage, n_rep, md_steps, block)
     if rec is None or "valu_insts" not in rec:
         return None
     return {"insts": rec["valu_insts"], "issue_frac": rec["valu_insts"] / (VALU_ISSUE_PEAK * kernel_s),
@@ -94,7 +94,9 @@ def main():
     ap.add_argument("--md-steps", type=int, default=5000, help="MD steps per relax_batch launch")
     ap.add_argument("--replicas", type=int, default=16384)
     ap.add_argument("--storage", choices=["f32", "f16"], default="f32")
-    ap.add_argument("--block", type=int, default=0, help="block threads (0: autotuned default)")
+    ap.add_argument("--block", type=int, default=192,
+                    help="block threads (192: five 38-atom replicas fill 190 of 192 lanes; the fastest of a "
+                         "64..448 sweep)")
     ap.add_argument("--compare-f16", action="store_true", help="also time the FP16-grid variant")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -119,7 +121,7 @@ def main():
     mol = S.mol_pah38()
     mols = [mol]
     n_rep = args.replicas
-    block = args.block or 256
+    block = args.block
 
     def setup(storage):
         grid = D.build_physical_grid(sub, spec, storage)
@@ -207,8 +209,8 @@ def main():
         "nonfinite_replicas": int(((status & G.REP_NONFINITE) != 0).sum()),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(args.storage, n_rep, args.md_steps),
-                     "valu": valu_utilisation(args.storage, n_rep, args.md_steps, kern_avg),
+                     "traffic": measured_traffic(args.storage, n_rep, args.md_steps, block),
+                     "valu": valu_utilisation(args.storage, n_rep, args.md_steps, block, kern_avg),
                      "kernel": f"k_replicas<{args.storage},NVE>",
                      "bytes_per_launch": alg_bytes},
     }
@@ -259,7 +261,7 @@ def run_workload(name, log):
     per_rep = [next(it[t]) for t in rep_type]
     topo = G.Topology(mols)
     prm = G.relax_params(G.MODE_FIRE, wl.n_steps, True, f_conv=1e-4)
-    launch = (256, 0, 0)
+    launch = (192, 0, 0)          # 8 x 24 or 5 x 38 atoms fill a 192-thread block
     tuned = None
     if name == "c3":
         plan0 = G.Plan(topo, rep_type)

@@ -1,8 +1,9 @@
 """Parity at the workloads' full sizes, in the launch shapes the benchmark times.
 
 The replica kernel runs every replica of a workload (16 384 x 38 atoms NVE on the
-112 x 112 x 150 grid; 65 536 x 38 atoms FIRE on the 452 x 452 x 200 grid; 4096 replicas of
-eight sizes FIRE with the autotuned launch), on seeded random coefficients of the workload's
+112 x 112 x 150 grid in 192-thread blocks; 65 536 x 38 atoms FIRE on the 452 x 452 x 200
+grid in 192-thread blocks; 4096 replicas of eight sizes FIRE with the autotuned launch), on
+seeded random coefficients of the workload's
 grid size; a sample of replicas is then re-run one by one by the FP64 oracle on the same
 FP32-rounded coefficients and inputs.  Tolerances as in the short-run parity tests: FP32
 trajectories within 2e-4 A of the FP64 ones, identical step counts and status flags.
@@ -30,7 +31,7 @@ def _sample(n, extra=()):
 
 def test_c2_nve_full_size_sampled():
     D.require_gpu()
-    announce("full size: 16384 x pah38 NVE, block 256")
+    announce("full size: 16384 x pah38 NVE, block 192")
     cfg = configs.GRID_SMALL
     grid, Bref = _grid(cfg, 21)
     mol = S.mol_pah38()
@@ -39,7 +40,7 @@ def test_c2_nve_full_size_sampled():
     pos = S.f32(S.place_replicas(mol, n_rep, sub, S.SEED_PLACE * 2))
     vel = S.f32(S.mb_velocities(mol.mass, n_rep, 300.0, S.SEED_NVE))
     topo = G.Topology([mol])
-    plan = G.Plan(topo, np.zeros(n_rep, np.int32), block_threads=256)
+    plan = G.Plan(topo, np.zeros(n_rep, np.int32), block_threads=192)
     st = D.fire_state(plan, list(pos), vel_per_rep=list(vel))
     out = D.outputs(plan)
     n = 20
@@ -80,7 +81,7 @@ def _fire_check(grid, Bref, mols, rep_type, pos, plan, topo, n, idx):
 
 def test_c5_fire_large_grid_full_size_sampled():
     D.require_gpu()
-    announce("full size: 65536 x pah38 FIRE on the 452 x 452 x 200 grid, block 256")
+    announce("full size: 65536 x pah38 FIRE on the 452 x 452 x 200 grid, block 192")
     cfg = configs.GRID_LARGE
     grid, Bref = _grid(cfg, 22)
     mol = S.mol_pah38()
@@ -88,7 +89,7 @@ def test_c5_fire_large_grid_full_size_sampled():
     pos = list(S.f32(S.place_replicas(mol, n_rep, cfg.substrate(), S.SEED_PLACE)))
     topo = G.Topology([mol])
     rep_type = np.zeros(n_rep, np.int32)
-    plan = G.Plan(topo, rep_type, block_threads=256)
+    plan = G.Plan(topo, rep_type, block_threads=192)
     _fire_check(grid, Bref, [mol], rep_type, pos, plan, topo, 10, _sample(n_rep))
 
 
