@@ -40,7 +40,7 @@ COUNTER_SCALE = {"fetch": 2.0, "write": 1.0}
 MEASURED_TRAFFIC = {
     ("f32", 16384, 5000, 192): {
         "sources": {"paper_2508_15522_amd/csrc/gff_relax.hip":
-                    "6146a3a0baa165fa866240563ce1ede0c152c9d1ad377019eab1c5355ff97819",
+                    "53bf2704ec834bfd0ed68befc350404dd7980df992f5d14ef312779a5bf4efd9",
                     "paper_2508_15522_amd/csrc/gff_internal.hpp":
                     "0f1b5c8a61f7e25dc89b990b2e2dc102cab89a75d27295dcb91d10cc002b91f4"},
         "fetch_kib": 292215755.75, "write_kib": 11601174.0,

@@ -6,9 +6,11 @@
 //
 // Mapping: a block holds a pack of same-type replicas, one lane per atom, replicas
 // packed densely (no lane rounding to powers of two).  Positions are exchanged through
-// LDS (double-buffered, so one barrier per step suffices for them); per-replica sums
-// (|F|^2, F.v, |v|^2, energies) are formed by every lane of the replica from LDS in the
-// same fixed order, so results are deterministic and identical on all lanes.
+// LDS (double-buffered by step parity); per-replica sums (|F|^2, F.v, |v|^2, energies)
+// are formed by a quad of reducer lanes per replica from LDS partials in a fixed order,
+// so results are deterministic and do not depend on how replicas are packed.  In
+// relaxation and MD launches each atom's pre-mixed stencil stays in registers and is
+// reloaded only when the atom changes grid cell.
 #include "gff_internal.hpp"
 #include <cstring>
 #include <algorithm>
