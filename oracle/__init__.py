@@ -115,6 +115,23 @@ def coulomb_fourier_above(sub, pts, ke=K_E):
     return V, g
 
 
+def direct_images(sub, pts, plq, alpha=1.6, ke=K_E, nimg=1):
+    """All-atom molecule-substrate energy and force at points (mixing plq [n][3]) summed over
+    the cell and its lateral images |a|, |b| <= nimg: (E [n], F [n][3])."""
+    pts, pp = _d(pts)
+    plq, qp = _d(plq)
+    n = len(pts)
+    E, F = np.zeros(n), np.zeros((n, 3))
+    sp, spp = _d(sub.pos)
+    sq, sqp = _d(sub.q)
+    se, sep = _d(sub.eps)
+    sr, srp = _d(sub.R)
+    lib().orc_direct_images(C.c_int(sub.n), spp, sqp, sep, srp, C.c_double(sub.Lx), C.c_double(sub.Ly),
+                            C.c_double(alpha), C.c_double(ke), C.c_int(nimg), C.c_int(n), pp, qp,
+                            _nullable(E), _nullable(F))
+    return E, F
+
+
 def channels_direct(sub, pts, alpha=1.6, rcut=30.0, eta=0.35):
     """Exact V^P, V^L, V^C and gradients at points: (V[3][n], g[3][n][3])."""
     VP, VL, gP, gL = morse_direct(sub, pts, alpha, rcut)

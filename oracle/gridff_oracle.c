@@ -39,6 +39,42 @@ static void cross3(const double *a, const double *b, double *c) {
     c[0] = a[1]*b[2] - a[2]*b[1]; c[1] = a[2]*b[0] - a[0]*b[2]; c[2] = a[0]*b[1] - a[1]*b[0];
 }
 
+/* All-atom molecule-substrate energy of the comparison in Section "Configuration sampling
+ * on GPU": a plain sum over every substrate atom of the cell and of its lateral periodic
+ * images (a, b) with |a|, |b| <= nimg (nimg = 1: the cell and its 8 neighbours, 9 cells),
+ * no cutoff and no Ewald treatment.  Per point with mixing (P, L, Q):
+ *   E = sum_j sum_ab [ P eps_j e^{2 alpha R_j} e^{-2 alpha r} + L eps_j e^{alpha R_j} e^{-alpha r}
+ *                      + k_e Q q_j / r ],
+ * the same Pauli/London factorisation as the grids (Eq. V_Morse), and F = -grad E. */
+void orc_direct_images(int nsub, const double *spos, const double *sq, const double *seps, const double *sR,
+                       double Lx, double Ly, double alpha, double ke, int nimg,
+                       int npts, const double *pts, const double *plq, double *E, double *F)
+{
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int p = 0; p < npts; ++p) {
+        const double *r = pts + 3 * p;
+        const double P = plq[3 * p], L = plq[3 * p + 1], Q = plq[3 * p + 2];
+        double e = 0, f[3] = {0, 0, 0};
+        for (int j = 0; j < nsub; ++j) {
+            const double aP = seps[j] * exp(2.0 * alpha * sR[j]), aL = seps[j] * exp(alpha * sR[j]);
+            for (int a = -nimg; a <= nimg; ++a)
+                for (int b = -nimg; b <= nimg; ++b) {
+                    const double d[3] = { r[0] - spos[3*j] - a * Lx, r[1] - spos[3*j+1] - b * Ly,
+                                          r[2] - spos[3*j+2] };
+                    const double dist = sqrt(dot3(d, d));
+                    const double ep = P * aP * exp(-2.0 * alpha * dist);
+                    const double el = L * aL * exp(-alpha * dist);
+                    const double ec = ke * Q * sq[j] / dist;
+                    e += ep + el + ec;
+                    const double g = 2.0 * alpha * ep + alpha * el + ec / dist;   /* -dE/dr */
+                    for (int c = 0; c < 3; ++c) f[c] += g * d[c] / dist;
+                }
+        }
+        E[p] = e;
+        for (int c = 0; c < 3; ++c) F[3 * p + c] = f[c];
+    }
+}
+
 /* Scaled complementary error function erfcx(x) = exp(x^2) erfc(x).  For x < 5 from
  * the library erfc; above, from the Laplace continued fraction
  * erfc(x) = exp(-x^2)/sqrt(pi) * 1/(x + (1/2)/(x + 1/(x + (3/2)/(x + 2/(x + ...))))). */

@@ -387,3 +387,35 @@ def test_uniform_proposals_and_pose():
             assert abs(np.linalg.norm(x[i] - x[j]) - r0) < 1e-9
         assert abs(x[:, 2].min() - dof[r, 2]) < 1e-12
         assert np.allclose(x[:, :2].mean(0), dof[r, :2] * [Lx, Ly], atol=1e-12)
+
+
+def test_direct_image_sum_pins():
+    """The all-atom comparison's image sum (Section "Configuration sampling on GPU"):
+    its Pauli/London part equals the pinned Morse image sums where the atoms beyond the 3x3
+    cell block lie more than 15 A away (tail below 1e-8 relative); its Coulomb part
+    converges to the 2D Ewald sum of the neutral zero-dipole slab as the square block of
+    images grows (error falling about 8x per doubling); F = -grad E by central differences."""
+    sub = S.rocksalt_slab(2, 3)
+    rng = np.random.default_rng(0)
+    pts = np.stack([rng.uniform(0.4, 0.6, 6) * sub.Lx, rng.uniform(0.4, 0.6, 6) * sub.Ly,
+                    rng.uniform(2.5, 5.0, 6)], 1)
+    plq = np.tile([0.7, -1.3, 0.0], (6, 1))
+    VP, VL, gP, gL = O.morse_direct(sub, pts, 1.6, 40.0)
+    E, F = O.direct_images(sub, pts, plq, nimg=1)
+    ref = 0.7 * VP - 1.3 * VL
+    assert np.abs(E - ref).max() < 1e-8 * np.abs(ref).max()
+    assert np.abs(F + (0.7 * gP - 1.3 * gL)).max() < 1e-8 * np.abs(0.7 * gP - 1.3 * gL).max()
+    plq = np.tile([0.0, 0.0, 1.0], (6, 1))
+    VC, gC = O.coulomb_ewald2d(sub, pts)
+    err = [np.abs(O.direct_images(sub, pts, plq, nimg=k)[0] - VC).max() for k in (10, 20, 40)]
+    assert err[2] < 1e-6 and err[0] / err[1] > 6 and err[1] / err[2] > 6
+    Ec, Fc = O.direct_images(sub, pts, plq, nimg=40)
+    assert np.abs(Fc + gC).max() < 1e-6
+    # force = -grad E, all channels together
+    plq = np.tile([0.7, -1.3, 0.4], (6, 1))
+    E0, F0 = O.direct_images(sub, pts, plq, nimg=1)
+    h = 1e-5
+    for c in range(3):
+        d = np.zeros(3); d[c] = h
+        fd = -(O.direct_images(sub, pts + d, plq)[0] - O.direct_images(sub, pts - d, plq)[0]) / (2 * h)
+        assert np.abs(fd - F0[:, c]).max() < 1e-6 * max(1.0, np.abs(F0).max())
