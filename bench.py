@@ -40,7 +40,7 @@ COUNTER_SCALE = {"fetch": 2.0, "write": 1.0}
 MEASURED_TRAFFIC = {
     ("f32", 16384, 5000, 192): {
         "sources": {"paper_2508_15522_amd/csrc/gff_relax.hip":
-                    "53bf2704ec834bfd0ed68befc350404dd7980df992f5d14ef312779a5bf4efd9",
+                    "be6bc648aecc09ae081e909e30fa0d199ffcb5cc5a0508dc945c93eaab9aa3f4",
                     "paper_2508_15522_amd/csrc/gff_internal.hpp":
                     "0f1b5c8a61f7e25dc89b990b2e2dc102cab89a75d27295dcb91d10cc002b91f4"},
         "fetch_kib": 292215755.75, "write_kib": 11601174.0,
@@ -103,6 +103,9 @@ def main():
     ap.add_argument("--minima", action="store_true", help="learned vs uniform proposals: minima found per second")
     ap.add_argument("--extra", nargs="*", default=[], choices=["c1", "c3", "c5"],
                     help="also time the chain (c1), uneven-size (c3) or large-substrate (c5) workloads")
+    ap.add_argument("--direct", nargs="*", default=[], choices=["c2", "c5"],
+                    help="also time the all-atom comparison mode (direct substrate sums over 9 cells) against "
+                         "GridFF on the C2 (48 substrate atoms) or C5 (3072) replicas")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a 1 GiB device copy first (reference for HBM counter scaling)")
     args = ap.parse_args()
@@ -234,6 +237,8 @@ def main():
                                "workload": "chain24 FIRE to 1e-4 eV/A (max 5000 steps), distinct within 0.01 eV"}
     for extra in args.extra:
         res.setdefault("other_workloads", {})[extra] = run_workload(extra, log)
+    for name in args.direct:
+        res.setdefault("all_atom_comparison", {})[name] = run_direct(name, log)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(mol, cfg, args.cpu_seconds)
     print(json.dumps(res), flush=True)
@@ -291,6 +296,58 @@ def run_workload(name, log):
     if tuned is not None:
         r["autotune_rate"] = tuned
     log(f"{name}: {r}")
+    return r
+
+
+def run_direct(name, log):
+    """GridFF against the all-atom comparison mode on the same replicas, molecule and
+    integrator (C2: NVE on the 48-atom slab; C5: FIRE on the 3072-atom slab): replica-steps/s
+    of each over a short launch (HIP events) and their ratio."""
+    import torch
+    from paper_2508_15522_amd import configs, device as D, gridff as G, synth as S
+    wl = {"c2": configs.C2_PAH_NVE, "c5": configs.C5_PAH_FIRE_LARGE}[name]
+    cfg = wl.grid
+    sub = cfg.substrate()
+    mol = S.mol_pah38()
+    grid = D.build_physical_grid(sub, D.spec_for(cfg), G.STORE_F32)
+    direct = G.Direct(sub, cfg.alpha, 1)
+    topo = G.Topology([mol])
+    plan = G.Plan(topo, np.zeros(wl.n_rep, np.int32), block_threads=192)
+    pos = S.place_replicas(mol, wl.n_rep, sub, S.SEED_PLACE * (2 if name == "c2" else 1))
+    if name == "c2":
+        vel = S.mb_velocities(mol.mass, wl.n_rep, 300.0, S.SEED_NVE)
+        prm = G.relax_params(G.MODE_NVE, 200, True, dt=0.5, drift_every=1)
+        steps = 200
+    else:
+        vel = None
+        prm = G.relax_params(G.MODE_FIRE, 10, True, f_conv=1e-4)
+        steps = 10
+    out = D.outputs(plan)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        st = D.fire_state(plan, pos, vel_per_rep=vel)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn(st)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3
+
+    drift = out["drift"] if name == "c2" else None
+    grid_run = lambda st: G.relax_batch(grid.desc, topo, plan, prm, st, out["E"], out["fnorm"], out["steps"],
+                                        drift, stream)
+    direct_run = lambda st: G.relax_batch_direct(direct, topo, plan, prm, st, out["E"], out["fnorm"],
+                                                 out["steps"], drift, stream)
+    timed(grid_run)
+    tg = timed(grid_run)
+    timed(direct_run)
+    td = timed(direct_run)
+    r = {"workload": wl.name, "substrate_atoms": sub.n, "substrate_terms_per_atom": 9 * sub.n, "steps": steps,
+         "gridff_replica_steps_per_s": wl.n_rep * steps / tg, "all_atom_replica_steps_per_s": wl.n_rep * steps / td,
+         "gridff_speedup": td / tg}
+    log(f"all-atom comparison {name}: {r}")
     return r
 
 

@@ -243,6 +243,29 @@ gff_status gff_relax_batch(const gff_grid *grid, const gff_topology *topo, const
                            double *d_E_rep, float *d_fnorm_rep, int *d_steps_rep,
                            double *d_drift_rep, void *stream);
 
+/* ------------------------------------------------------------------ all-atom comparison mode */
+
+/* The all-atom molecule-substrate evaluation that the paper compares GridFF with (Section
+ * "Configuration sampling on GPU"): every substrate atom of the cell and of its lateral
+ * periodic images (a, b), |a|, |b| <= n_img (n_img = 1: the cell and its 8 neighbours, 9
+ * cells), summed directly per molecule atom with no cutoff and bare Coulomb:
+ *   E_i = sum_j sum_ab [ P_i eps_j e^{2 alpha R_j} e^{-2 alpha r} + L_i eps_j e^{alpha R_j} e^{-alpha r}
+ *                        + k_e Q_i q_j / r ].
+ * gff_direct_create uploads the substrate (synchronous; allocates device memory); alpha must
+ * equal the topology's.  gff_eval_forces_direct and gff_relax_batch_direct take the place
+ * of gff_eval_forces and gff_relax_batch with the grid replaced by this sum; everything
+ * else (intramolecular field, FIRE, NVE, outputs, status flags) is the same.  Errors as
+ * for those calls; GFF_EINVAL also when alpha differs from the topology's. */
+typedef struct gff_direct_s gff_direct;
+gff_status gff_direct_create(const gff_substrate *sub, float alpha, int n_img, gff_direct **out);
+void gff_direct_destroy(gff_direct *direct);
+gff_status gff_eval_forces_direct(const gff_direct *direct, const gff_topology *topo, const gff_plan *plan,
+                                  int include_intra, const float *d_pos, float *d_F, float *d_E_atom,
+                                  double *d_E_rep, unsigned *d_status, void *stream);
+gff_status gff_relax_batch_direct(const gff_direct *direct, const gff_topology *topo, const gff_plan *plan,
+                                  const gff_relax_params *params, const gff_state *state, double *d_E_rep,
+                                  float *d_fnorm_rep, int *d_steps_rep, double *d_drift_rep, void *stream);
+
 /* Resident blocks per compute unit of the kernel gff_relax_batch (mode GFF_MODE_FIRE or
  * GFF_MODE_NVE) or gff_eval_forces (mode -1) launches for this grid storage and plan,
  * from the device's occupancy calculator (register and LDS limits); *lds_bytes_out

@@ -89,3 +89,13 @@ inline size_t replica_lds_bytes(int block_threads, int tres_max, int max_pack_re
     return (size_t)block_threads * (5 * 16 + 4) + (size_t)tres_max * 32 + (size_t)max_pack_reps * 48 + 16 +
            (size_t)topo_words * 16;
 }
+
+// All-atom comparison mode: substrate atoms with their Pauli/London factors on the device.
+struct gff_direct_s {
+    int n, nimg;
+    float alpha, Lx, Ly;
+    float4 *d_xyza;            // x, y, z, eps e^{2 alpha R}
+    float2 *d_bq;              // eps e^{alpha R}, q
+    std::vector<void *> allocations;
+};
+

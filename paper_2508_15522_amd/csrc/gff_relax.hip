@@ -12,12 +12,22 @@
 // relaxation and MD launches each atom's pre-mixed stencil stays in registers and is
 // reloaded only when the atom changes grid cell.
 #include "gff_internal.hpp"
+#include <cmath>
 #include <cstring>
 #include <algorithm>
 
 namespace gff {
 
 enum { MODE_EVAL = 0, MODE_FIRE = 1, MODE_NVE = 2 };
+// storage slot of the all-atom comparison mode (no grid: direct substrate sums)
+constexpr int STORE_DIRECT = 2;
+
+struct DirectView {
+    const float4 *xyza;        // substrate x, y, z, eps e^{2 alpha R}
+    const float2 *bq;          // eps e^{alpha R}, q
+    int n, nimg;
+    float Lx, Ly;
+};
 
 struct GridView {
     const void *coef;
@@ -47,6 +57,7 @@ struct KArgs {
     float *F; float *E_atom; double *E_rep; float *fnorm; int *steps; double *drift;
     int n_steps, include_intra, drift_every, nmin;
     float dt, f_conv, max_disp, finc, fdec, a0, falpha_f, dtmax;
+    DirectView d;                       // all-atom comparison mode only
 };
 
 __device__ __forceinline__ void lds_sync() {
@@ -448,6 +459,38 @@ __device__ __forceinline__ float torsion_term(const TorDef td, const float4 *sp,
     return 0.5f * td.V * (1.f - carg);
 }
 
+// All-atom comparison (Section "Configuration sampling on GPU"): the molecule-substrate
+// energy of this lane's atom summed directly over every substrate atom of the cell and of
+// its lateral images |a|, |b| <= nimg, with the grids' Pauli/London factorisation and bare
+// Coulomb, no cutoff.  The substrate index is wave-uniform, so its data arrive through
+// scalar loads.
+__device__ __forceinline__ float direct_terms(const KArgs &A, float3 xi, float4 me, float3 &F) {
+    const DirectView &d = A.d;
+    float e = 0.f, fx = 0.f, fy = 0.f, fz = 0.f;
+    const float keQ = A.ke * me.z;
+    for (int j = 0; j < d.n; ++j) {
+        const float4 s = d.xyza[j];
+        const float2 t = d.bq[j];
+        const float ap = me.x * s.w, al = me.y * t.x, ac = keQ * t.y;
+        const float ddz = xi.z - s.z;
+        for (int a = -d.nimg; a <= d.nimg; ++a) {
+            const float ddx = xi.x - (s.x + (float)a * d.Lx);
+            for (int b = -d.nimg; b <= d.nimg; ++b) {
+                const float ddy = xi.y - (s.y + (float)b * d.Ly);
+                const float r2 = ddx * ddx + ddy * ddy + ddz * ddz;
+                const float rinv = __builtin_amdgcn_rsqf(r2);
+                const float u = __builtin_amdgcn_exp2f(-A.alpha_l2e * (r2 * rinv));
+                const float ep = ap * u * u, el = al * u, ec = ac * rinv;
+                e += ep + el + ec;
+                const float sc = (A.alpha * (2.f * ep + el) + ec * rinv) * rinv;   // -dE/dr / r
+                fx += sc * ddx; fy += sc * ddy; fz += sc * ddz;
+            }
+        }
+    }
+    F = make_float3(fx, fy, fz);
+    return e;
+}
+
 // CACHE: keep each lane's four pre-mixed stencil planes (64 values) in registers from step
 // to step; this needs blocks of at most 512 threads (up to 256 registers per lane).
 template <int STORE, int MODE, bool CACHE>
@@ -482,7 +525,7 @@ k_replicas(KArgs A) {
     const int N = A.N;
     const int wl = tid & 63, wb = tid - wl, quad_s = wl & 3;
     GridView gv = A.g;
-    fetch_scales(gv);
+    if constexpr (STORE != STORE_DIRECT) fetch_scales(gv);
 
     for (int pk = blockIdx.x; pk < A.n_packs; pk += gridDim.x) {
         const int4 pinfo = A.packs[pk];
@@ -547,8 +590,20 @@ k_replicas(KArgs A) {
             if (MODE == MODE_NVE && live && s_nf[lr]) { st |= GFF_REP_NONFINITE; live = false; }
 
             float pfx = 0.f, pfy = 0.f, pfz = 0.f, pe = 0.f;    // non-bonded pair sums (CACHE)
-            // --- grid: owner hand-off, then four quad-gather rounds within the wave
-            {
+            // --- grid: owner hand-off, then four quad-gather rounds within the wave (in the
+            // all-atom comparison mode: the direct substrate sum instead)
+            if constexpr (STORE == STORE_DIRECT) {
+                if (!(__builtin_isfinite(x.x) && __builtin_isfinite(x.y) && __builtin_isfinite(x.z))) {
+                    if (live) fl |= GFF_REP_NONFINITE;
+                    e_grid = __builtin_nanf("");
+                    F = make_float3(e_grid, e_grid, e_grid);
+                } else if (live) {
+                    e_grid = direct_terms(A, x, me, F);
+                } else {
+                    e_grid = 0.f;
+                    F = make_float3(0.f, 0.f, 0.f);
+                }
+            } else {
                 float4 t;
                 unsigned fk = 0;
                 GridKey key = grid_key(gv, x.x, x.y, x.z, t, fk);
@@ -843,14 +898,16 @@ static void launch_one(int grid, int BT, size_t lds, const KArgs &A, hipStream_t
 // Relaxation and MD launches keep stencils in registers when the block fits the cached
 // variant's register budget (<= 512 threads); single evaluations never reuse a stencil.
 template <int MODE>
-static gff_status launch_mode(const gff_grid *gr, const gff_plan *plan, KArgs &A, hipStream_t s) {
+static gff_status launch_mode(int storage, const gff_plan *plan, KArgs &A, hipStream_t s) {
     const int BT = plan->block_threads;
     const size_t lds = replica_lds_bytes(BT, plan->tres_max, plan->max_pack_reps, plan->topo_words);
     const int grid = plan->grid_blocks > 0 ? std::min(plan->grid_blocks, plan->n_packs) : plan->n_packs;
     if (grid <= 0) return GFF_OK;
     constexpr bool can_cache = MODE != MODE_EVAL;
     const bool cache = can_cache && BT <= 512;
-    if (gr->storage == GFF_STORE_F32) {
+    if (storage == STORE_DIRECT) {
+        launch_one<STORE_DIRECT, MODE, false>(grid, BT, lds, A, s);
+    } else if (storage == GFF_STORE_F32) {
         if (cache) launch_one<GFF_STORE_F32, MODE, can_cache>(grid, BT, lds, A, s);
         else launch_one<GFF_STORE_F32, MODE, false>(grid, BT, lds, A, s);
     } else {
@@ -894,37 +951,30 @@ extern "C" gff_status gff_relax_occupancy(const gff_grid *grid, const gff_plan *
     return GFF_EINVAL;
 }
 
-extern "C" gff_status gff_eval_forces(const gff_grid *grid, const gff_topology *topo, const gff_plan *plan,
-                                      int include_intra, const float *d_pos, float *d_F, float *d_E_atom,
-                                      double *d_E_rep, unsigned *d_status, void *stream) {
-    if (!topo || !plan || !d_pos || !d_F) return GFF_EINVAL;
-    KArgs A;
-    std::memset(&A, 0, sizeof(A));
-    gff_status rc = make_view(grid, A.g);
-    if (rc != GFF_OK) return rc;
-    hipStream_t s = (hipStream_t)stream;
+static gff_status eval_common(int storage, KArgs &A, const gff_topology *topo, const gff_plan *plan,
+                              int include_intra, const float *d_pos, float *d_F, float *d_E_atom, double *d_E_rep,
+                              unsigned *d_status, hipStream_t s) {
     fill_common(A, topo, plan);
     A.pos = const_cast<float *>(d_pos);
     A.F = d_F; A.E_atom = d_E_atom; A.E_rep = d_E_rep; A.status = d_status;
     A.include_intra = include_intra;
-    return launch_mode<MODE_EVAL>(grid, plan, A, s);
+    return launch_mode<MODE_EVAL>(storage, plan, A, s);
 }
 
-extern "C" gff_status gff_relax_batch(const gff_grid *grid, const gff_topology *topo, const gff_plan *plan,
-                                      const gff_relax_params *p, const gff_state *state,
-                                      double *d_E_rep, float *d_fnorm_rep, int *d_steps_rep,
-                                      double *d_drift_rep, void *stream) {
+static gff_status relax_check(const gff_topology *topo, const gff_plan *plan, const gff_relax_params *p,
+                              const gff_state *state, double *d_drift_rep) {
     if (!topo || !plan || !p || !state || !state->d_pos || !state->d_vel || !state->d_status) return GFF_EINVAL;
     if (p->n_steps < 0) return GFF_EINVAL;
     if (p->mode != GFF_MODE_FIRE && p->mode != GFF_MODE_NVE) return GFF_EINVAL;
     if (p->mode == GFF_MODE_FIRE && (!state->d_fire_dt || !state->d_fire_alpha || !state->d_fire_npos))
         return GFF_EINVAL;
     if (p->mode == GFF_MODE_NVE && d_drift_rep && p->drift_every < 1) return GFF_EINVAL;
-    KArgs A;
-    std::memset(&A, 0, sizeof(A));
-    gff_status rc = make_view(grid, A.g);
-    if (rc != GFF_OK) return rc;
-    hipStream_t s = (hipStream_t)stream;
+    return GFF_OK;
+}
+
+static gff_status relax_common(int storage, KArgs &A, const gff_topology *topo, const gff_plan *plan,
+                               const gff_relax_params *p, const gff_state *state, double *d_E_rep,
+                               float *d_fnorm_rep, int *d_steps_rep, double *d_drift_rep, hipStream_t s) {
     fill_common(A, topo, plan);
     A.pos = state->d_pos; A.vel = state->d_vel;
     A.fdt = state->d_fire_dt; A.falpha = state->d_fire_alpha; A.fnpos = state->d_fire_npos;
@@ -937,8 +987,100 @@ extern "C" gff_status gff_relax_batch(const gff_grid *grid, const gff_topology *
     A.dt = p->dt; A.f_conv = p->f_conv; A.max_disp = p->max_disp;
     A.finc = p->fire_finc; A.fdec = p->fire_fdec; A.a0 = p->fire_alpha0; A.falpha_f = p->fire_falpha;
     A.dtmax = p->fire_dtmax;
-    if (p->mode == GFF_MODE_FIRE) return launch_mode<MODE_FIRE>(grid, plan, A, s);
-    return launch_mode<MODE_NVE>(grid, plan, A, s);
+    if (p->mode == GFF_MODE_FIRE) return launch_mode<MODE_FIRE>(storage, plan, A, s);
+    return launch_mode<MODE_NVE>(storage, plan, A, s);
+}
+
+static gff_status direct_view(const gff_direct *d, const gff_topology *topo, DirectView &v) {
+    if (!d || !topo) return GFF_EINVAL;
+    if (d->alpha != topo->alpha) return GFF_EINVAL;           // the factors were formed with alpha
+    v.xyza = d->d_xyza; v.bq = d->d_bq; v.n = d->n; v.nimg = d->nimg; v.Lx = d->Lx; v.Ly = d->Ly;
+    return GFF_OK;
+}
+
+extern "C" gff_status gff_eval_forces(const gff_grid *grid, const gff_topology *topo, const gff_plan *plan,
+                                      int include_intra, const float *d_pos, float *d_F, float *d_E_atom,
+                                      double *d_E_rep, unsigned *d_status, void *stream) {
+    if (!topo || !plan || !d_pos || !d_F) return GFF_EINVAL;
+    KArgs A;
+    std::memset(&A, 0, sizeof(A));
+    gff_status rc = make_view(grid, A.g);
+    if (rc != GFF_OK) return rc;
+    return eval_common(grid->storage, A, topo, plan, include_intra, d_pos, d_F, d_E_atom, d_E_rep, d_status,
+                       (hipStream_t)stream);
+}
+
+extern "C" gff_status gff_relax_batch(const gff_grid *grid, const gff_topology *topo, const gff_plan *plan,
+                                      const gff_relax_params *p, const gff_state *state,
+                                      double *d_E_rep, float *d_fnorm_rep, int *d_steps_rep,
+                                      double *d_drift_rep, void *stream) {
+    gff_status rc = relax_check(topo, plan, p, state, d_drift_rep);
+    if (rc != GFF_OK) return rc;
+    KArgs A;
+    std::memset(&A, 0, sizeof(A));
+    if ((rc = make_view(grid, A.g)) != GFF_OK) return rc;
+    return relax_common(grid->storage, A, topo, plan, p, state, d_E_rep, d_fnorm_rep, d_steps_rep, d_drift_rep,
+                        (hipStream_t)stream);
+}
+
+extern "C" gff_status gff_direct_create(const gff_substrate *sub, float alpha, int n_img, gff_direct **out) {
+    if (!sub || !out || sub->n_atoms < 1 || !sub->pos_h || !sub->q_h || !sub->eps_h || !sub->R_h) return GFF_EINVAL;
+    if (!(alpha > 0.f) || !(sub->Lx > 0.0) || !(sub->Ly > 0.0) || n_img < 0 || n_img > 64) return GFF_EINVAL;
+    const int n = sub->n_atoms;
+    std::vector<float4> xyza(n);
+    std::vector<float2> bq(n);
+    for (int j = 0; j < n; ++j) {
+        const double e = sub->eps_h[j], R = sub->R_h[j];
+        xyza[j] = make_float4((float)sub->pos_h[3 * j], (float)sub->pos_h[3 * j + 1], (float)sub->pos_h[3 * j + 2],
+                              (float)(e * std::exp(2.0 * (double)alpha * R)));
+        bq[j] = make_float2((float)(e * std::exp((double)alpha * R)), (float)sub->q_h[j]);
+    }
+    auto *d = new gff_direct_s();
+    d->n = n; d->nimg = n_img; d->alpha = alpha; d->Lx = (float)sub->Lx; d->Ly = (float)sub->Ly;
+    d->d_xyza = nullptr; d->d_bq = nullptr;
+    if (hipMalloc(&d->d_xyza, n * sizeof(float4)) != hipSuccess ||
+        hipMalloc(&d->d_bq, n * sizeof(float2)) != hipSuccess ||
+        hipMemcpy(d->d_xyza, xyza.data(), n * sizeof(float4), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(d->d_bq, bq.data(), n * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess) {
+        if (d->d_xyza) (void)hipFree(d->d_xyza);
+        if (d->d_bq) (void)hipFree(d->d_bq);
+        delete d;
+        return GFF_EHIP;
+    }
+    *out = d;
+    return GFF_OK;
+}
+
+extern "C" void gff_direct_destroy(gff_direct *d) {
+    if (!d) return;
+    (void)hipFree(d->d_xyza);
+    (void)hipFree(d->d_bq);
+    delete d;
+}
+
+extern "C" gff_status gff_eval_forces_direct(const gff_direct *direct, const gff_topology *topo, const gff_plan *plan,
+                                             int include_intra, const float *d_pos, float *d_F, float *d_E_atom,
+                                             double *d_E_rep, unsigned *d_status, void *stream) {
+    if (!topo || !plan || !d_pos || !d_F) return GFF_EINVAL;
+    KArgs A;
+    std::memset(&A, 0, sizeof(A));
+    gff_status rc = direct_view(direct, topo, A.d);
+    if (rc != GFF_OK) return rc;
+    return eval_common(STORE_DIRECT, A, topo, plan, include_intra, d_pos, d_F, d_E_atom, d_E_rep, d_status,
+                       (hipStream_t)stream);
+}
+
+extern "C" gff_status gff_relax_batch_direct(const gff_direct *direct, const gff_topology *topo,
+                                             const gff_plan *plan, const gff_relax_params *p,
+                                             const gff_state *state, double *d_E_rep, float *d_fnorm_rep,
+                                             int *d_steps_rep, double *d_drift_rep, void *stream) {
+    gff_status rc = relax_check(topo, plan, p, state, d_drift_rep);
+    if (rc != GFF_OK) return rc;
+    KArgs A;
+    std::memset(&A, 0, sizeof(A));
+    if ((rc = direct_view(direct, topo, A.d)) != GFF_OK) return rc;
+    return relax_common(STORE_DIRECT, A, topo, plan, p, state, d_E_rep, d_fnorm_rep, d_steps_rep, d_drift_rep,
+                        (hipStream_t)stream);
 }
 
 extern "C" gff_status gff_interp_points(const gff_grid *grid, int n, const float *d_pos, const float *d_plq,

@@ -260,6 +260,45 @@ def relax_batch(grid_desc, topo, plan, params, st, d_E_rep, d_fnorm, d_steps, d_
                                 _ptr(d_E_rep), _ptr(d_fnorm), _ptr(d_steps), _ptr(d_drift), _stream(stream)))
 
 
+# ------------------------------------------------------------------ all-atom comparison mode
+EXPORTS += ["gff_direct_create", "gff_direct_destroy", "gff_eval_forces_direct", "gff_relax_batch_direct"]
+
+
+class Direct:
+    """Substrate atoms on the device for the all-atom comparison (cell + lateral images
+    |a|, |b| <= n_img, bare sums, no cutoff)."""
+
+    def __init__(self, sub, alpha=1.6, n_img=1):
+        keep = _Keep()
+        s = substrate(sub, keep)
+        self.handle = C.c_void_p()
+        check(lib().gff_direct_create(C.byref(s), C.c_float(alpha), C.c_int(n_img), C.byref(self.handle)))
+        self.n_img = n_img
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.gff_direct_destroy(self.handle)
+            self.handle = None
+
+
+def eval_forces_direct(direct, topo, plan, include_intra, d_pos, d_F, d_E_atom=None, d_E_rep=None, d_status=None,
+                       stream=None):
+    check(lib().gff_eval_forces_direct(direct.handle, topo.handle, plan.handle, C.c_int(int(include_intra)),
+                                       _ptr(d_pos), _ptr(d_F), _ptr(d_E_atom), _ptr(d_E_rep), _ptr(d_status),
+                                       _stream(stream)))
+
+
+def relax_batch_direct(direct, topo, plan, params, st, d_E_rep, d_fnorm, d_steps, d_drift=None, stream=None):
+    state = State(st["pos"].data_ptr(), st["vel"].data_ptr(),
+                  st["fire_dt"].data_ptr() if "fire_dt" in st else None,
+                  st["fire_alpha"].data_ptr() if "fire_alpha" in st else None,
+                  st["fire_npos"].data_ptr() if "fire_npos" in st else None,
+                  st["status"].data_ptr())
+    check(lib().gff_relax_batch_direct(direct.handle, topo.handle, plan.handle, C.byref(params), C.byref(state),
+                                       _ptr(d_E_rep), _ptr(d_fnorm), _ptr(d_steps), _ptr(d_drift),
+                                       _stream(stream)))
+
+
 # ------------------------------------------------------------------ proposals / minima
 EXPORTS += ["gff_propose_uniform", "gff_pose_from_dof", "gff_encode_pose", "gff_decode_dof", "gff_dedupe_energy",
             "gff_mlp_n_params", "gff_mlp_create", "gff_mlp_destroy", "gff_mlp_get_params", "gff_mlp_workspace_bytes",
