@@ -396,6 +396,25 @@ def nve_batch(B, spec, mols, rep_type, pos, vel, n_steps, dt=0.5, drift_every=1,
     return dict(pos=pos, vel=vel, status=st, E=E, drift=drift)
 
 
+def langevin_batch(B, spec, mols, rep_type, pos, vel, n_steps, dt=0.5, T=300.0, gamma=0.01, seed=0, rnd=0,
+                   rep_id=None, intra_on=True, alpha=1.6, status=None):
+    """BAOAB Langevin dynamics (Philox normals keyed by the replica ids rep_id)."""
+    tv, gv = TypesView(mols, alpha), GridView(B, spec)
+    rep_type, off = _batch_arrays(mols, rep_type)
+    nr = len(rep_type)
+    rid = np.arange(nr, dtype=np.int32) if rep_id is None else np.asarray(rep_id, np.int32)
+    pos = np.array(pos, dtype=np.float64)
+    vel = np.array(vel, dtype=np.float64)
+    st = np.zeros(nr, np.int32) if status is None else np.array(status, np.int32)
+    E = np.zeros(nr)
+    kT = 8.617333262e-5 * T
+    lib().orc_langevin_batch(C.byref(gv.s), C.byref(tv.s), C.c_int(n_steps), C.c_double(dt), C.c_double(kT),
+                             C.c_double(gamma), C.c_uint64(seed), C.c_uint32(rnd), C.c_int(int(intra_on)),
+                             C.c_int(nr), _i(rep_type)[1], rid.ctypes.data_as(C.POINTER(C.c_int)), _i(off)[1],
+                             _nullable(pos), _nullable(vel), st.ctypes.data_as(C.POINTER(C.c_int)), _nullable(E))
+    return dict(pos=pos, vel=vel, status=st, E=E)
+
+
 # ------------------------------------------------------------------ RNG / proposals
 def philox4x32_10(ctr, key):
     c = (C.c_uint32 * 4)(*[int(v) & 0xFFFFFFFF for v in ctr])

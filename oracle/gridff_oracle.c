@@ -689,6 +689,67 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
     out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
+/* Langevin dynamics, the thermal perturbation of the paper's minima hopping (Section
+ * "Configuration sampling on GPU": 1000 steps at 300 K before each relaxation), integrated
+ * by the BAOAB splitting (Leimkuhler & Matthews 2013); the paper names no scheme.  Per step
+ *   v += dt/2 F/m;  x += dt/2 v;  v = c1 v + c2 sqrt(kT/m) xi;  x += dt/2 v;  F = F(x);
+ *   v += dt/2 F/m,   c1 = exp(-gamma dt), c2 = sqrt(1 - c1^2),
+ * masses in amu (m -> m * 103.6427 eV fs^2/A^2).  The normals xi of replica id r, atom a,
+ * step s (1-based) come from Philox4x32-10 with counter (r, a, s, round) and key (seed low,
+ * seed high): with u_k = ((x_k >> 9) + 1/2) 2^-23 (exact in single precision, never 0 or 1),
+ * xi_x = sqrt(-2 ln u0) cos(2 pi u1),
+ * xi_y = sqrt(-2 ln u0) sin(2 pi u1), xi_z = sqrt(-2 ln u2) cos(2 pi u3).  A replica whose
+ * energy becomes non-finite is frozen with status bit 4. */
+void orc_langevin_batch(const orc_grid *g, const orc_types *T, int n_steps, double dt, double kT, double gamma,
+                        uint64_t seed, uint32_t round, int intra, int n_rep, const int *rep_type, const int *rep_id,
+                        const int *atom_off, double *pos, double *vel, int *status, double *E_rep)
+{
+    const double conv = 103.6426965268;
+    const double c1 = exp(-gamma * dt), c2 = sqrt(1.0 - c1 * c1);
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int r = 0; r < n_rep; ++r) {
+        int t = rep_type[r];
+        orc_mol m = type_mol(T, t);
+        int n = m.n, a0 = atom_off[r];
+        const double *mass = T->mass + T->atom_off[t];
+        double *x = pos + 3 * a0, *v = vel + 3 * a0;
+        double *plq = malloc(sizeof(double) * 3 * n), *F = malloc(sizeof(double) * 3 * n);
+        double *Ft = malloc(sizeof(double) * 3 * n);
+        unsigned char *ex = malloc((size_t)n * n);
+        exclusion_matrix(&m, ex);
+        orc_mixing(n, m.eps, m.R, m.q, T->alpha, plq);
+        int st = status[r];
+        double E = 0;
+        if (!(st & 4)) st |= replica_force(g, &m, plq, intra, ex, x, F, &E, NULL, Ft);
+        for (int s = 1; s <= n_steps && !(st & 4); ++s) {
+            for (int i = 0; i < n; ++i) {
+                const double mi = mass[i] * conv, sig = sqrt(kT / mi);
+                const uint32_t ctr[4] = {(uint32_t)rep_id[r], (uint32_t)i, (uint32_t)s, round};
+                uint32_t o[4];
+                orc_philox4x32_10(ctr, key, o);
+                double u[4];
+                for (int k = 0; k < 4; ++k) u[k] = ((double)(o[k] >> 9) + 0.5) / 8388608.0;
+                const double r0 = sqrt(-2.0 * log(u[0])), r2 = sqrt(-2.0 * log(u[2]));
+                const double xi[3] = {r0 * cos(2.0 * M_PI * u[1]), r0 * sin(2.0 * M_PI * u[1]),
+                                      r2 * cos(2.0 * M_PI * u[3])};
+                for (int c = 0; c < 3; ++c) {
+                    v[3*i+c] += 0.5 * dt * F[3*i+c] / mi;
+                    x[3*i+c] += 0.5 * dt * v[3*i+c];
+                    v[3*i+c] = c1 * v[3*i+c] + c2 * sig * xi[c];
+                    x[3*i+c] += 0.5 * dt * v[3*i+c];
+                }
+            }
+            st |= replica_force(g, &m, plq, intra, ex, x, F, &E, NULL, Ft);
+            if (st & 4) break;
+            for (int i = 0; i < n; ++i) for (int c = 0; c < 3; ++c)
+                v[3*i+c] += 0.5 * dt * F[3*i+c] / (mass[i] * conv);
+        }
+        status[r] = st; E_rep[r] = E;
+        free(plq); free(F); free(Ft); free(ex);
+    }
+}
+
 /* uniform in [0,1) from the top 24 bits */
 static double u01(uint32_t x) { return (double)(x >> 8) * (1.0 / 16777216.0); }
 

@@ -389,6 +389,81 @@ def test_uniform_proposals_and_pose():
         assert np.allclose(x[:, :2].mean(0), dof[r, :2] * [Lx, Ly], atol=1e-12)
 
 
+# ------------------------------------------------------------------ Langevin (BAOAB)
+KB = 8.617333262e-5
+AMU = 103.6426965268
+
+
+def test_langevin_without_friction_is_velocity_verlet():
+    """gamma = 0 removes the O step (c1 = 1, c2 = 0): BAOAB is then velocity Verlet."""
+    spec = dict(nx=8, ny=8, nz=12, x0=0.0, y0=0.0, z0=1.0, dx=0.5, dy=0.5, dz=0.5)
+    B = O.fit_bspline(RNG.normal(size=(3, 8, 8, 12)) * 0.01)
+    mol = S.mol_chain24()
+    x0 = mol.pos + [2.0, 2.0, 4.0]
+    v0 = S.mb_velocities(mol.mass, 1, 300.0, 7001)[0]
+    a = O.nve_batch(B, spec, [mol], [0], x0, v0, 60, dt=0.5)
+    b = O.langevin_batch(B, spec, [mol], [0], x0, v0, 60, dt=0.5, gamma=0.0, seed=3)
+    assert np.abs(a["pos"] - b["pos"]).max() < 1e-10
+    assert np.abs(a["vel"] - b["vel"]).max() < 1e-10
+    assert abs(a["E"][0] - b["E"][0]) < 1e-9
+
+
+def test_langevin_noise_keyed_by_replica_id_seed_and_round():
+    spec = dict(nx=8, ny=8, nz=12, x0=0.0, y0=0.0, z0=1.0, dx=0.5, dy=0.5, dz=0.5)
+    B = O.fit_bspline(RNG.normal(size=(3, 8, 8, 12)) * 0.01)
+    mol = S.mol_chain24()
+    xa, xb = mol.pos + [2.0, 2.0, 4.0], mol.pos + [2.5, 1.0, 4.2]
+    v = np.zeros((2 * mol.n, 3))
+    run = lambda x, ids, **kw: O.langevin_batch(B, spec, [mol], [0, 0], x, v, 30, gamma=0.05, rep_id=ids, **kw)
+    r1 = run(np.concatenate([xa, xb]), [5, 9], seed=11, rnd=2)
+    r2 = run(np.concatenate([xb, xa]), [9, 5], seed=11, rnd=2)     # same ids, other batch order
+    assert np.array_equal(r1["pos"], np.concatenate([r2["pos"][mol.n:], r2["pos"][:mol.n]]))
+    r3 = run(np.concatenate([xa, xb]), [5, 9], seed=11, rnd=3)
+    r4 = run(np.concatenate([xa, xb]), [5, 9], seed=12, rnd=2)
+    assert np.abs(r3["pos"] - r1["pos"]).max() > 1e-4 and np.abs(r4["pos"] - r1["pos"]).max() > 1e-4
+
+
+def test_langevin_harmonic_stationary_moments():
+    """One-atom molecules (q = 1) in a Coulomb channel whose B-spline model is exactly
+    k (z - zc)^2 and flat laterally.  For a quadratic potential BAOAB samples positions
+    with the exact variance kT/K (K = 2k) at any stable step, and velocities along z with
+    variance (kT/m)(1 - (w dt/2)^2), w^2 = K/m (the stationary solution of the scheme's
+    linear recurrence); the force-free lateral velocities are an exact Ornstein-Uhlenbeck
+    process with variance kT/m.  A wrong splitting order or a dropped half kick moves these
+    moments by 25 % or more for the light atom (w dt = 1)."""
+    d, nz, zc = 0.5, 16, 3.75
+    z = np.arange(nz) * d
+    T, dt, gamma = 300.0, 1.0, 0.2
+    kT = KB * T
+    m_h, m_c = 1.008, 12.011
+    K = m_h * AMU * 1.0 ** 2                  # w dt = 1 for the light atom
+    B = np.zeros((3, 6, 6, nz))
+    B[2] = (0.5 * K * ((z - zc) ** 2 - d * d / 3))[None, None, :]
+    spec = dict(nx=6, ny=6, nz=nz, x0=0.0, y0=0.0, z0=0.0, dx=d, dy=d, dz=d)
+    mols = []
+    for m in (m_h, m_c):
+        a = _one_atom(); a.q = np.array([1.0]); a.mass = np.array([m]); mols.append(a)
+    nr = 300
+    rep_type = np.repeat([0, 1], nr)
+    x = np.zeros((2 * nr, 3)); x[:, :2] = np.random.default_rng(5).random((2 * nr, 2)) * 3.0; x[:, 2] = zc
+    v = np.zeros((2 * nr, 3))
+    zz, vz, vl = [], [], []
+    for rnd in range(260):
+        out = O.langevin_batch(B, spec, mols, rep_type, x, v, 10, dt=dt, T=T, gamma=gamma, seed=77, rnd=rnd,
+                               intra_on=False)
+        x, v = out["pos"], out["vel"]
+        assert (out["status"] == 0).all()
+        if rnd >= 20:
+            zz.append((x[:, 2] - zc) ** 2); vz.append(v[:, 2] ** 2); vl.append(0.5 * (v[:, 0] ** 2 + v[:, 1] ** 2))
+    zz, vz, vl = np.array(zz), np.array(vz), np.array(vl)
+    for t, m in enumerate((m_h, m_c)):
+        sel = rep_type == t
+        w = np.sqrt(K / (m * AMU))
+        assert zz[:, sel].mean() / (kT / K) == pytest.approx(1.0, abs=0.03)
+        assert vz[:, sel].mean() / (kT / (m * AMU) * (1 - (w * dt / 2) ** 2)) == pytest.approx(1.0, abs=0.03)
+        assert vl[:, sel].mean() / (kT / (m * AMU)) == pytest.approx(1.0, abs=0.03)
+
+
 def test_direct_image_sum_pins():
     """The all-atom comparison's image sum (Section "Configuration sampling on GPU"):
     its Pauli/London part equals the pinned Morse image sums where the atoms beyond the 3x3
