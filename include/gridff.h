@@ -62,7 +62,7 @@ enum {
     GFF_REP_MAXSTEPS = 8       /* FIRE with f_conv > 0 ended without converging */
 };
 
-enum { GFF_MODE_FIRE = 0, GFF_MODE_NVE = 1 };
+enum { GFF_MODE_FIRE = 0, GFF_MODE_NVE = 1, GFF_MODE_LANGEVIN = 2 };
 
 const char *gff_status_string(int status);
 
@@ -201,15 +201,19 @@ gff_status gff_interp_points(const gff_grid *grid, int n, const float *d_pos, co
 /* ------------------------------------------------------------------ relaxation / dynamics */
 
 typedef struct {
-    int mode;                 /* GFF_MODE_FIRE or GFF_MODE_NVE */
-    int n_steps;              /* moves (FIRE) or time steps (NVE); >= 0 */
+    int mode;                 /* GFF_MODE_FIRE, GFF_MODE_NVE or GFF_MODE_LANGEVIN */
+    int n_steps;              /* moves (FIRE) or time steps (NVE, Langevin); >= 0 */
     int include_intra;
-    float dt;                 /* NVE time step [fs]; FIRE: unused (per-replica dt is state) */
+    float dt;                 /* NVE/Langevin time step [fs]; FIRE: unused (per-replica dt is state) */
     float f_conv;             /* FIRE convergence on |F|_2 [eV/A]; <= 0: never */
     float max_disp;           /* FIRE per-atom displacement cap per step [A] */
     float fire_finc, fire_fdec, fire_alpha0, fire_falpha, fire_dtmax;
     int fire_nmin;
     int drift_every;          /* NVE: FP64 total-energy sample every k steps (>= 1) */
+    float kT;                 /* Langevin: bath temperature k_B T [eV] (>= 0) */
+    float gamma;              /* Langevin: friction [1/fs] (>= 0) */
+    unsigned long long seed;  /* Langevin: Philox key (low word, high word) */
+    unsigned round;           /* Langevin: fourth Philox counter word; use a new value per launch */
 } gff_relax_params;
 
 /* Caller-owned replica state (in/out). */
@@ -234,6 +238,17 @@ typedef struct {
  * E_pot + sum m v^2/2 is formed in FP64 and accumulated in d_drift_rep[r][6] =
  * {E(0), E(last sample), max|E(s)-E(0)|, sum dE, sum s dE, samples}; non-finite energies
  * freeze the replica at those samples.
+ *
+ * Langevin (the thermal perturbation of minima hopping, Section "Configuration sampling on
+ * GPU"; the paper names no integrator, this is BAOAB, Leimkuhler & Matthews 2013): per step
+ * v += dt/2 a; x += dt/2 v; v <- c1 v + c2 sqrt(kT/m) xi; x += dt/2 v; a = a(x); v += dt/2 a,
+ * c1 = exp(-gamma dt), c2 = sqrt(1 - c1^2), masses as in NVE.  The three normals xi of
+ * replica r (its index in the plan), atom a of the molecule and step s = 1..n_steps come
+ * from Philox4x32-10 with counter (r, a, s, round) and key (seed low, seed high): with
+ * u_k = ((x_k >> 9) + 1/2) 2^-23, xi = (sqrt(-2 ln u0) cos 2pi u1, sqrt(-2 ln u0) sin 2pi u1,
+ * sqrt(-2 ln u2) cos 2pi u3).  d_drift_rep must be NULL; d_fnorm_rep receives 0.  A replica
+ * whose coordinates become non-finite ends with GFF_REP_NONFINITE and a NaN energy; its
+ * final positions are unspecified.
  *
  * Outputs: d_E_rep [n_rep] (FP64 total energy at the last evaluation), d_fnorm_rep
  * [n_rep] (|F|_2 there, FP32), d_steps_rep [n_rep] (moves made), d_drift_rep nullable.

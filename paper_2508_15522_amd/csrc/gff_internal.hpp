@@ -13,6 +13,34 @@ constexpr int kMaxAtoms = 128;             // atoms per molecule type (4 x 32-bi
 constexpr float kEvPerAmuA2Fs2 = 103.6426965268f;  // 1 amu A^2 / fs^2 in eV
 constexpr double kDefaultKe = 14.3996454784;
 
+// Philox4x32 with 10 rounds (Salmon, Moraes, Dror & Shaw, SC'11), counter c in place, key
+// (k0, k1) bumped by the Weyl constants between rounds.
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c[0]), lo0 = 0xD2511F53u * c[0];
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c[2]), lo1 = 0xCD9E8D57u * c[2];
+        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+    }
+}
+
+// Three standard normals from one Philox block by the Box-Muller transform, with the
+// uniforms u = ((x >> 9) + 1/2) 2^-23 (exact in FP32, strictly inside (0, 1)).
+__device__ __forceinline__ float3 philox_normal3(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                                 uint32_t k0, uint32_t k1) {
+    uint32_t c[4] = {c0, c1, c2, c3};
+    philox4x32_10(c, k0, k1);
+    float u[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) u[k] = ((float)(c[k] >> 9) + 0.5f) * (1.f / 8388608.f);
+    const float r0 = sqrtf(-2.f * logf(u[0])), r2 = sqrtf(-2.f * logf(u[2]));
+    float s1, co1;
+    sincospif(2.f * u[1], &s1, &co1);
+    return make_float3(r0 * co1, r0 * s1, r2 * cospif(2.f * u[3]));
+}
+
 struct TypeInfo {              // per molecule type
     int n;                     // atoms
     int abase;                 // first entry in the per-type-atom arrays

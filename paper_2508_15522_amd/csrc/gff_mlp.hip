@@ -191,23 +191,13 @@ __global__ void k_adam(long n, float *p, const float *g, float *m, float *v, flo
     p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
-__device__ __forceinline__ void philox(uint32_t c[4], uint32_t k0, uint32_t k1) {
-    for (int r = 0; r < 10; ++r) {
-        if (r > 0) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
-        const uint32_t hi0 = __umulhi(0xD2511F53u, c[0]), lo0 = 0xD2511F53u * c[0];
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c[2]), lo1 = 0xCD9E8D57u * c[2];
-        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
-        c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
-    }
-}
-
 // Standard normals by Box-Muller from Philox counter (i/4, round, 1, 0): each counter gives
 // two pairs; uniforms (x >> 8 + 0.5) 2^-24 lie in (0, 1).
 __global__ void k_normal(long n, uint32_t k0, uint32_t k1, uint32_t round, float *out) {
     const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (q * 4 >= n) return;
     uint32_t c[4] = {(uint32_t)q, round, 1u, (uint32_t)(q >> 32)};
-    philox(c, k0, k1);
+    philox4x32_10(c, k0, k1);
     float u[4];
     for (int k = 0; k < 4; ++k) u[k] = ((float)(c[k] >> 8) + 0.5f) * (1.f / 16777216.f);
     float z[4];

@@ -1,8 +1,8 @@
 // GridFF replica kernels for gfx950: per-atom tricubic B-spline interpolation of the
 // Pauli/London/Coulomb grids mixed with the atom's (P, L, Q) (Section "Interpolation",
 // Eqs. Bspline1D/Bspline; Section "Principles", Eqs. E, E_Coulomb, E_Morse, V_Morse),
-// fused with the intramolecular field and a FIRE or velocity-Verlet step, with the whole
-// step loop inside one launch (Section "Configuration sampling on GPU").
+// fused with the intramolecular field and a FIRE, velocity-Verlet or Langevin (BAOAB) step,
+// with the whole step loop inside one launch (Section "Configuration sampling on GPU").
 //
 // Mapping: a block holds a pack of same-type replicas, one lane per atom, replicas
 // packed densely (no lane rounding to powers of two).  Positions are exchanged through
@@ -18,7 +18,7 @@
 
 namespace gff {
 
-enum { MODE_EVAL = 0, MODE_FIRE = 1, MODE_NVE = 2 };
+enum { MODE_EVAL = 0, MODE_FIRE = 1, MODE_NVE = 2, MODE_LANGEVIN = 3 };
 // storage slot of the all-atom comparison mode (no grid: direct substrate sums)
 constexpr int STORE_DIRECT = 2;
 
@@ -57,6 +57,8 @@ struct KArgs {
     float *F; float *E_atom; double *E_rep; float *fnorm; int *steps; double *drift;
     int n_steps, include_intra, drift_every, nmin;
     float dt, f_conv, max_disp, finc, fdec, a0, falpha_f, dtmax;
+    float lg_c1, lg_c2, kT;             // Langevin: exp(-gamma dt), sqrt(1 - c1^2), k_B T
+    unsigned seed_lo, seed_hi, round;   // Langevin: Philox key and fourth counter word
     DirectView d;                       // all-atom comparison mode only
 };
 
@@ -582,6 +584,14 @@ k_replicas(KArgs A) {
                 v = v + (0.5f * A.dt * me.w) * F;
                 x = x + A.dt * v;
             }
+            if (MODE == MODE_LANGEVIN && it > 0 && live) {  // BAOAB: half kick, half drift,
+                v = v + (0.5f * A.dt * me.w) * F;            // Ornstein-Uhlenbeck, half drift
+                x = x + (0.5f * A.dt) * v;
+                const float3 xi = philox_normal3((uint32_t)rep, (uint32_t)at, (uint32_t)it, A.round,
+                                                 A.seed_lo, A.seed_hi);
+                v = A.lg_c1 * v + (A.lg_c2 * sqrtf(A.kT * me.w)) * xi;
+                x = x + (0.5f * A.dt) * v;
+            }
             if (live) s_any[par] = 1;
             if (tid == 0) s_any[par ^ 1] = 0;
             sp[tid] = make_float4(x.x, x.y, x.z, 0.f);
@@ -793,6 +803,11 @@ k_replicas(KArgs A) {
                 }
                 if (live && it > 0) steps++;
             }
+
+            if (MODE == MODE_LANGEVIN && live && it > 0) {   // closing half kick
+                v = v + (0.5f * A.dt * me.w) * F;
+                steps++;
+            }
         }
 
         // ---- outputs: per-atom state, then per-replica sums (FP64) and flags
@@ -948,6 +963,7 @@ extern "C" gff_status gff_relax_occupancy(const gff_grid *grid, const gff_plan *
     if (mode == -1) return occupancy_mode<MODE_EVAL>(grid->storage, BT, lds, blocks_per_cu);
     if (mode == GFF_MODE_FIRE) return occupancy_mode<MODE_FIRE>(grid->storage, BT, lds, blocks_per_cu);
     if (mode == GFF_MODE_NVE) return occupancy_mode<MODE_NVE>(grid->storage, BT, lds, blocks_per_cu);
+    if (mode == GFF_MODE_LANGEVIN) return occupancy_mode<MODE_LANGEVIN>(grid->storage, BT, lds, blocks_per_cu);
     return GFF_EINVAL;
 }
 
@@ -965,10 +981,14 @@ static gff_status relax_check(const gff_topology *topo, const gff_plan *plan, co
                               const gff_state *state, double *d_drift_rep) {
     if (!topo || !plan || !p || !state || !state->d_pos || !state->d_vel || !state->d_status) return GFF_EINVAL;
     if (p->n_steps < 0) return GFF_EINVAL;
-    if (p->mode != GFF_MODE_FIRE && p->mode != GFF_MODE_NVE) return GFF_EINVAL;
+    if (p->mode != GFF_MODE_FIRE && p->mode != GFF_MODE_NVE && p->mode != GFF_MODE_LANGEVIN) return GFF_EINVAL;
     if (p->mode == GFF_MODE_FIRE && (!state->d_fire_dt || !state->d_fire_alpha || !state->d_fire_npos))
         return GFF_EINVAL;
     if (p->mode == GFF_MODE_NVE && d_drift_rep && p->drift_every < 1) return GFF_EINVAL;
+    if (p->mode == GFF_MODE_LANGEVIN &&
+        (d_drift_rep || !(p->kT >= 0.f) || !(p->gamma >= 0.f) || !std::isfinite(p->kT) || !std::isfinite(p->gamma) ||
+         !std::isfinite(p->dt)))
+        return GFF_EINVAL;
     return GFF_OK;
 }
 
@@ -987,7 +1007,11 @@ static gff_status relax_common(int storage, KArgs &A, const gff_topology *topo, 
     A.dt = p->dt; A.f_conv = p->f_conv; A.max_disp = p->max_disp;
     A.finc = p->fire_finc; A.fdec = p->fire_fdec; A.a0 = p->fire_alpha0; A.falpha_f = p->fire_falpha;
     A.dtmax = p->fire_dtmax;
+    const double c1 = std::exp(-(double)p->gamma * (double)p->dt);
+    A.lg_c1 = (float)c1; A.lg_c2 = (float)std::sqrt(std::max(0.0, 1.0 - c1 * c1)); A.kT = p->kT;
+    A.seed_lo = (unsigned)(p->seed & 0xffffffffull); A.seed_hi = (unsigned)(p->seed >> 32); A.round = p->round;
     if (p->mode == GFF_MODE_FIRE) return launch_mode<MODE_FIRE>(storage, plan, A, s);
+    if (p->mode == GFF_MODE_LANGEVIN) return launch_mode<MODE_LANGEVIN>(storage, plan, A, s);
     return launch_mode<MODE_NVE>(storage, plan, A, s);
 }
 

@@ -15,7 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgridff.so")
 
 STORE_F32, STORE_F16 = 0, 1
-MODE_FIRE, MODE_NVE = 0, 1
+MODE_FIRE, MODE_NVE, MODE_LANGEVIN = 0, 1, 2
+K_B = 8.617333262e-5                    # Boltzmann constant [eV/K]
 REP_CONVERGED, REP_OUT_OF_DOMAIN, REP_NONFINITE, REP_MAXSTEPS = 1, 2, 4, 8
 
 
@@ -60,7 +61,8 @@ class RelaxParams(C.Structure):
     _fields_ = [("mode", C.c_int), ("n_steps", C.c_int), ("include_intra", C.c_int), ("dt", C.c_float),
                 ("f_conv", C.c_float), ("max_disp", C.c_float), ("fire_finc", C.c_float),
                 ("fire_fdec", C.c_float), ("fire_alpha0", C.c_float), ("fire_falpha", C.c_float),
-                ("fire_dtmax", C.c_float), ("fire_nmin", C.c_int), ("drift_every", C.c_int)]
+                ("fire_dtmax", C.c_float), ("fire_nmin", C.c_int), ("drift_every", C.c_int),
+                ("kT", C.c_float), ("gamma", C.c_float), ("seed", C.c_ulonglong), ("round", C.c_uint)]
 
 
 class State(C.Structure):
@@ -244,9 +246,11 @@ def interp_points(grid_desc, d_pos, d_plq, d_F, d_E=None, stream=None):
 
 
 def relax_params(mode=MODE_FIRE, n_steps=1000, include_intra=True, dt=0.5, f_conv=1e-4, max_disp=0.1,
-                 finc=1.1, fdec=0.5, alpha0=0.1, falpha=0.99, dtmax=0.1, nmin=5, drift_every=1):
+                 finc=1.1, fdec=0.5, alpha0=0.1, falpha=0.99, dtmax=0.1, nmin=5, drift_every=1,
+                 T=300.0, gamma=0.01, seed=0, rnd=0):
+    """T is the Langevin bath temperature in K (kT = k_B T in the C struct)."""
     return RelaxParams(mode, n_steps, int(include_intra), dt, f_conv, max_disp, finc, fdec, alpha0, falpha,
-                       dtmax, nmin, drift_every)
+                       dtmax, nmin, drift_every, K_B * T, gamma, seed, rnd)
 
 
 def relax_batch(grid_desc, topo, plan, params, st, d_E_rep, d_fnorm, d_steps, d_drift=None, stream=None):

@@ -72,3 +72,29 @@ def test_soa_layout_helpers_roundtrip():
     x = S.place_replicas(m, 3, S.rocksalt_slab(2, 3), 5)
     assert x.shape == (3, 24, 3)
     assert np.all(x[:, :, 2].min(1) >= 3.0 - 1e-6) and np.all(x[:, :, 2].min(1) <= 5.0 + 1e-6)
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """Every ctypes mirror of a public struct has the size and field offsets that a C
+    compiler gives the declaration in include/gridff.h."""
+    import subprocess
+    from paper_2508_15522_amd import gridff as G
+    pairs = [(G.Substrate, "gff_substrate"), (G.GridSpec, "gff_grid_spec"), (G.Grid, "gff_grid"),
+             (G.MolType, "gff_mol_type"), (G.Launch, "gff_launch"), (G.RelaxParams, "gff_relax_params"),
+             (G.State, "gff_state")]
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "gridff.h"', "int main(void) {"]
+    for py, c in pairs:
+        lines.append(f'    printf("{c} %zu\\n", sizeof({c}));')
+        for f in py._fields_:
+            lines.append(f'    printf("{c}.{f[0]} %zu\\n", offsetof({c}, {f[0]}));')
+    lines += ["    return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(ROOT, "include")
+    subprocess.check_call(["gcc", "-std=c11", "-I", inc, str(src), "-o", str(exe)])
+    got = dict(line.split() for line in subprocess.check_output([str(exe)], text=True).splitlines())
+    for py, c in pairs:
+        assert int(got[c]) == C.sizeof(py), c
+        for f in py._fields_:
+            assert int(got[f"{c}.{f[0]}"]) == getattr(py, f[0]).offset, (c, f[0])

@@ -1,7 +1,7 @@
 """Parity at the workloads' full sizes, in the launch shapes the benchmark times.
 
-The replica kernel runs every replica of a workload (16 384 x 38 atoms NVE on the
-112 x 112 x 150 grid in 192-thread blocks; 65 536 x 38 atoms FIRE on the 452 x 452 x 200
+The replica kernel runs every replica of a workload (16 384 x 38 atoms NVE and Langevin
+on the 112 x 112 x 150 grid in 192-thread blocks; 65 536 x 38 atoms FIRE on the 452 x 452 x 200
 grid in 192-thread blocks; 4096 replicas of eight sizes FIRE with the autotuned launch), on
 seeded random coefficients of the workload's
 grid size; a sample of replicas is then re-run one by one by the FP64 oracle on the same
@@ -59,6 +59,39 @@ def test_c2_nve_full_size_sampled():
     assert np.array_equal(dr[:, 5], ref["drift"][:, 5])
     assert (out["steps"].cpu().numpy() == n).all()
     assert np.isfinite(out["E"].cpu().numpy()).all()
+
+
+def test_c2_langevin_full_size_sampled():
+    """The thermal perturbation on the same workload: sampled replicas re-run by the oracle
+    with their batch indices as Philox replica ids."""
+    D.require_gpu()
+    announce("full size: 16384 x pah38 Langevin, block 192")
+    cfg = configs.GRID_SMALL
+    grid, Bref = _grid(cfg, 24)
+    mol = S.mol_pah38()
+    n_rep = configs.C2_PAH_NVE.n_rep
+    pos = S.f32(S.place_replicas(mol, n_rep, cfg.substrate(), S.SEED_PLACE * 5))
+    vel = S.f32(S.mb_velocities(mol.mass, n_rep, 300.0, S.SEED_NVE + 1))
+    topo = G.Topology([mol])
+    plan = G.Plan(topo, np.zeros(n_rep, np.int32), block_threads=192)
+    st = D.fire_state(plan, list(pos), vel_per_rep=list(vel))
+    out = D.outputs(plan)
+    n, seed, rnd = 20, 0xC0FFEE, 11
+    G.relax_batch(grid.desc, topo, plan, G.relax_params(G.MODE_LANGEVIN, n, True, dt=0.5, T=300.0, gamma=0.01,
+                                                        seed=seed, rnd=rnd), st, out["E"], out["fnorm"], out["steps"])
+    torch.cuda.synchronize()
+    idx = _sample(n_rep)
+    xg = D.unsoa(plan, st["pos"])
+    ref = O.langevin_batch(Bref, grid.geometry, [mol], np.zeros(len(idx), np.int32), np.concatenate(pos[idx]),
+                           np.concatenate(vel[idx]), n, dt=0.5, T=300.0, gamma=0.01, seed=seed, rnd=rnd,
+                           rep_id=idx)
+    dx = np.abs(np.concatenate([xg[i] for i in idx]) - ref["pos"]).max()
+    dE = np.abs(out["E"].cpu().numpy()[idx] - ref["E"]).max()
+    announce(f"  max |dx| = {dx:.3e} A, max |dE| = {dE:.3e} eV")
+    assert dx < 2e-4
+    assert dE < 2e-5 * mol.n
+    assert (out["steps"].cpu().numpy() == n).all()
+    assert (st["status"].cpu().numpy()[idx] == ref["status"]).all()
 
 
 def _fire_check(grid, Bref, mols, rep_type, pos, plan, topo, n, idx):

@@ -1,0 +1,166 @@
+"""GPU parity of the Langevin (BAOAB) thermal perturbation of minima hopping (Section
+"Configuration sampling on GPU") against the FP64 oracle.
+
+Both sides draw the same Philox4x32-10 normals (counter: replica index, atom, step, round;
+key: the seed), so trajectories are compared element by element over short runs from
+identical seeded starts, as for NVE: positions within 2e-4 A after 50 steps, energies
+within 2e-5 eV per atom, identical step counts and flags.  The sampled distribution is
+checked on the GPU at large batch through the moments BAOAB fixes exactly for a quadratic
+potential (position variance kT/K at any stable step, velocity variance
+(kT/m)(1 - (w dt/2)^2) along the spring, kT/m across it).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2508_15522_amd import device as D, gridff as G, synth as S
+from tests.gpu_common import announce, oracle_relax_grid
+
+pytestmark = pytest.mark.gpu
+AMU = 103.6426965268                     # 1 amu A^2 / fs^2 in eV
+
+
+@pytest.fixture(scope="module")
+def world():
+    D.require_gpu()
+    sub, geo, B = oracle_relax_grid()
+    spec = G.grid_spec(geo["nx"], geo["ny"], geo["nz"], 0.0, 0.0, geo["z0"], geo["dz"])
+    grid = D.pack_from_coefficients(B, spec, G.STORE_F32, sub.Lx, sub.Ly)
+    assert grid.geometry == geo
+    mols = [S.mol_size(18, 2), S.mol_chain24(), S.mol_pah38(), S.mol_size(52, 6)]
+    return dict(sub=sub, geo=geo, B=B, grid=grid, mols=mols, topo=G.Topology(mols))
+
+
+def _positions(w, rep_type, seed, h=(2.8, 4.0)):
+    return [S.place_replicas(w["mols"][t], 1, w["sub"], seed + r, h)[0] for r, t in enumerate(rep_type)]
+
+
+def _velocities(w, rep_type, seed):
+    return [S.mb_velocities(w["mols"][t].mass, 1, 300.0, seed + r)[0] for r, t in enumerate(rep_type)]
+
+
+def _launch(w, plan, st, n, gamma, seed, rnd, T=300.0, dt=0.5):
+    out = D.outputs(plan)
+    prm = G.relax_params(G.MODE_LANGEVIN, n, True, dt=dt, T=T, gamma=gamma, seed=seed, rnd=rnd)
+    G.relax_batch(w["grid"].desc, w["topo"], plan, prm, st, out["E"], out["fnorm"], out["steps"])
+    torch.cuda.synchronize()
+    return out
+
+
+@pytest.mark.parametrize("gamma", [0.01, 0.2])
+def test_langevin_short_run_parity_across_two_launches(world, gamma):
+    w = world
+    announce(f"langevin parity gamma={gamma}")
+    rng = np.random.default_rng(8)
+    rep_type = rng.integers(0, len(w["mols"]), 37)
+    plan = G.Plan(w["topo"], rep_type, block_threads=256)
+    pos, vel = _positions(w, rep_type, 4100), _velocities(w, rep_type, 4200)
+    st = D.fire_state(plan, pos, vel_per_rep=vel)
+    seed = 0x1234_5678_9ABC_DEF0
+    ref = dict(pos=np.concatenate(pos), vel=np.concatenate(vel))
+    for rnd in (3, 4):                                    # a launch per round, 25 steps each
+        out = _launch(w, plan, st, 25, gamma, seed, rnd)
+        ref = O.langevin_batch(w["B"], w["geo"], w["mols"], rep_type, ref["pos"], ref["vel"], 25, dt=0.5,
+                               T=300.0, gamma=gamma, seed=seed, rnd=rnd)
+    xg = np.concatenate(D.unsoa(plan, st["pos"]))
+    vg = np.concatenate(D.unsoa(plan, st["vel"]))
+    nat = np.array([w["mols"][t].n for t in rep_type])
+    dx = np.abs(xg - ref["pos"]).max()
+    dv = np.abs(vg - ref["vel"]).max()
+    dE = np.abs(out["E"].cpu().numpy() - ref["E"])
+    announce(f"  max |dx| = {dx:.3e} A, max |dv| = {dv:.3e} A/fs, max |dE|/atom = {(dE / nat).max():.3e}")
+    assert dx < 2e-4
+    assert dv < 2e-4
+    assert (dE < 2e-5 * nat).all()
+    assert (out["steps"].cpu().numpy() == 25).all()
+    assert np.array_equal(st["status"].cpu().numpy(), ref["status"])
+    assert (out["fnorm"].cpu().numpy() == 0).all()
+
+
+def test_langevin_zero_steps_and_determinism(world):
+    w = world
+    announce("langevin zero steps, determinism")
+    rep_type = np.array([2, 2, 1, 0, 3])
+    plan = G.Plan(w["topo"], rep_type)
+    pos, vel = _positions(w, rep_type, 4300), _velocities(w, rep_type, 4400)
+    st = D.fire_state(plan, pos, vel_per_rep=vel)
+    x0 = st["pos"].clone()
+    out = _launch(w, plan, st, 0, 0.05, 1, 0)
+    assert torch.equal(st["pos"], x0) and (out["steps"].cpu().numpy() == 0).all()
+    _, Er, _, _ = O.eval_batch(w["B"], w["geo"], w["mols"], rep_type, np.concatenate(pos))
+    nat = np.array([w["mols"][t].n for t in rep_type])
+    assert (np.abs(out["E"].cpu().numpy() - Er) < 2e-5 * nat).all()
+    runs = []
+    for _ in range(2):
+        s2 = D.fire_state(plan, pos, vel_per_rep=vel)
+        _launch(w, plan, s2, 40, 0.05, 99, 7)
+        runs.append(s2["pos"].clone())
+    assert torch.equal(runs[0], runs[1])
+    s3 = D.fire_state(plan, pos, vel_per_rep=vel)
+    _launch(w, plan, s3, 40, 0.05, 99, 8)
+    assert (runs[0] - s3["pos"]).abs().max().item() > 1e-4
+
+
+def test_langevin_rejects_invalid_parameters(world):
+    w = world
+    plan = G.Plan(w["topo"], np.array([0]))
+    st = D.fire_state(plan, _positions(w, [0], 4500))
+    out = D.outputs(plan)
+    for kw in (dict(T=-1.0), dict(gamma=-0.1), dict(gamma=float("nan"))):
+        prm = G.relax_params(G.MODE_LANGEVIN, 5, True, **kw)
+        with pytest.raises(G.GffError):
+            G.relax_batch(w["grid"].desc, w["topo"], plan, prm, st, out["E"], out["fnorm"], out["steps"])
+    prm = G.relax_params(G.MODE_LANGEVIN, 5, True)
+    with pytest.raises(G.GffError):          # no drift record in Langevin mode
+        G.relax_batch(w["grid"].desc, w["topo"], plan, prm, st, out["E"], out["fnorm"], out["steps"], out["drift"])
+
+
+def _one_atom(mass):
+    return S.Molecule(name="atom", elem=["C"], pos=np.zeros((1, 3)), q=np.array([1.0]), eps=np.array([0.0]),
+                      R=np.array([0.0]), mass=np.array([mass]), bonds=np.zeros((0, 2), np.int32),
+                      bond_k=np.zeros(0), bond_r0=np.zeros(0), angles=np.zeros((0, 3), np.int32),
+                      angle_k=np.zeros(0), angle_cos0=np.zeros(0), tors=np.zeros((0, 4), np.int32),
+                      tors_V=np.zeros(0), tors_n=np.zeros(0, np.int32), tors_phi0=np.zeros(0))
+
+
+def test_langevin_harmonic_moments_at_large_batch():
+    """16 384 one-atom replicas of two masses (q = 1) in a Coulomb channel whose B-spline
+    model is exactly (K/2)(z - zc)^2 and flat laterally, on a 6 x 6 x 16 grid."""
+    D.require_gpu()
+    announce("langevin harmonic moments, 16384 replicas")
+    d, nz, zc = 0.5, 16, 3.75
+    z = np.arange(nz) * d
+    T, dt, gamma = 300.0, 1.0, 0.2
+    kT = G.K_B * T
+    masses = (1.008, 12.011)
+    K = masses[0] * AMU * 1.0 ** 2           # w dt = 1 for the light atom
+    B = np.zeros((3, 6, 6, nz))
+    B[2] = (0.5 * K * ((z - zc) ** 2 - d * d / 3))[None, None, :]
+    spec = G.grid_spec(6, 6, nz, 0.0, 0.0, 0.0, d)
+    grid = D.pack_from_coefficients(B, spec, G.STORE_F32, 3.0, 3.0)
+    mols = [_one_atom(m) for m in masses]
+    topo = G.Topology(mols)
+    nr = 8192
+    rep_type = np.repeat([0, 1], nr).astype(np.int32)
+    plan = G.Plan(topo, rep_type, block_threads=256)
+    x = np.zeros((2 * nr, 1, 3)); x[:, 0, :2] = np.random.default_rng(5).random((2 * nr, 2)) * 3.0; x[:, 0, 2] = zc
+    st = D.fire_state(plan, list(x), vel_per_rep=list(np.zeros_like(x)))
+    w = dict(grid=grid, topo=topo)
+    zz, vz, vl = [], [], []
+    for rnd in range(100):
+        out = _launch(w, plan, st, 10, gamma, 2024, rnd, T=T, dt=dt)
+        if rnd >= 10:
+            xg, vg = D.unsoa(plan, st["pos"]), D.unsoa(plan, st["vel"])
+            xg = np.concatenate(xg).astype(np.float64); vg = np.concatenate(vg).astype(np.float64)
+            zz.append((xg[:, 2] - zc) ** 2); vz.append(vg[:, 2] ** 2); vl.append(0.5 * (vg[:, 0] ** 2 + vg[:, 1] ** 2))
+    assert (st["status"].cpu().numpy() == 0).all()
+    zz, vz, vl = np.array(zz), np.array(vz), np.array(vl)
+    for t, m in enumerate(masses):
+        sel = rep_type == t
+        wdt = np.sqrt(K / (m * AMU)) * dt
+        rz = zz[:, sel].mean() / (kT / K)
+        rv = vz[:, sel].mean() / (kT / (m * AMU) * (1 - (wdt / 2) ** 2))
+        rl = vl[:, sel].mean() / (kT / (m * AMU))
+        announce(f"  mass {m}: <z^2> ratio {rz:.4f}, <vz^2> ratio {rv:.4f}, <vxy^2> ratio {rl:.4f}")
+        assert abs(rz - 1) < 0.02 and abs(rv - 1) < 0.02 and abs(rl - 1) < 0.02
