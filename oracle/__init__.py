@@ -38,6 +38,11 @@ PINS = {
     "philox4x32_10": "published known-answer vectors",
     "pose": "torsion set to target, rigid-body invariants",
     "mlp": "FD gradient check (P12)",
+    "direct_images": "Morse image sums, 2D Ewald convergence, FD gradient",
+    "langevin_batch": "velocity Verlet at zero friction, exact BAOAB harmonic moments",
+    "sampling.dedupe_energy": "hand-worked discovery-order cases",
+    "sampling.rmsd_lattice": "lattice/continuous shift, rotation and permutation closed forms",
+    "sampling.dedupe_rmsd": "hand-worked discovery-order chain, type, NaN and carried-archive cases",
 }
 
 

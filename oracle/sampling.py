@@ -2,7 +2,7 @@
 
 * pose encoding (the inverse of pose construction): torsions measured, the reference
   re-posed with them, the best rigid rotation by Horn's quaternion method;
-* energy deduplication in discovery order;
+* deduplication in discovery order, by energy and by the lattice-translated RMSD;
 * the proposer MLP (4 layers, SiLU) forward and backward in FP64 on BF16-rounded weights,
   IMLE nearest-candidate selection, Adam;
 * standard normals from Philox4x32-10 by Box-Muller.
@@ -86,6 +86,42 @@ def dedupe_energy(E, types, ok, tol, archive=None):
             continue
         if all(not (t == types[c] and abs(e - E[c]) <= tol) for e, t in arch):
             arch.append((E[c], types[c]))
+            new[c] = 1
+    return new, arch
+
+
+def rmsd_lattice(A, B, Lx, Ly):
+    """RMSD of two minima of one molecule type (same atom order), minimised over the lateral
+    lattice translations (a Lx, b Ly) of the substrate: adsorption site and orientation
+    count, with no rotation fit and no atom permutation (Section "Configuration sampling on
+    GPU").  The mean square over atoms equals |t - m|^2 + const with m the mean difference,
+    so its minimum lies at a lattice vector within one cell of m; all lattice vectors within
+    two cells of m are tried."""
+    D = np.asarray(A, np.float64) - np.asarray(B, np.float64)
+    m = D.mean(0)
+    a0, b0 = int(np.floor(m[0] / Lx)), int(np.floor(m[1] / Ly))
+    best = np.inf
+    for a in range(a0 - 2, a0 + 4):
+        for b in range(b0 - 2, b0 + 4):
+            t = np.array([a * Lx, b * Ly, 0.0])
+            best = min(best, float(np.sqrt(np.mean(np.sum((D - t) ** 2, axis=1)))))
+    return best
+
+
+def dedupe_rmsd(pos, types, ok, tol, Lx, Ly, archive=None):
+    """Discovery-order RMSD dedupe: candidate c is new when rmsd_lattice > tol against every
+    archived minimum of its type, including those accepted earlier in the batch; candidates
+    with ok[c] == 0 or non-finite coordinates are never new.  pos: list of (n_c, 3) arrays.
+    Returns (is_new flags, archive list of (coordinates, type))."""
+    arch = list(archive or [])
+    new = np.zeros(len(pos), np.int32)
+    for c, x in enumerate(pos):
+        if ok is not None and not ok[c]:
+            continue
+        if not np.isfinite(x).all():
+            continue
+        if all(not (t == types[c] and rmsd_lattice(x, y, Lx, Ly) <= tol) for y, t in arch):
+            arch.append((np.array(x, np.float64), types[c]))
             new[c] = 1
     return new, arch
 

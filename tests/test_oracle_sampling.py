@@ -49,6 +49,47 @@ def test_dedupe_semantics():
     assert list(new2) == [0, 1]
 
 
+def test_rmsd_lattice_closed_forms():
+    mol = S.mol_chain24()
+    A = mol.pos + [2.0, 3.0, 4.0]
+    Lx, Ly = 11.28, 8.46
+    assert OS.rmsd_lattice(A, A, Lx, Ly) == 0.0
+    assert OS.rmsd_lattice(A + [3 * Lx, -2 * Ly, 0.0], A, Lx, Ly) < 1e-12
+    # a rigid shift s: the distance from s to the nearest lattice vector, here (Lx, 0, 0)
+    s = np.array([0.7 * Lx, -0.2 * Ly, 0.15])
+    want = np.sqrt((0.3 * Lx) ** 2 + (0.2 * Ly) ** 2 + 0.15 ** 2)
+    assert abs(OS.rmsd_lattice(A + s, A, Lx, Ly) - want) < 1e-12
+    assert abs(OS.rmsd_lattice(A, A + s, Lx, Ly) - want) < 1e-12
+    # a rotation by th about the vertical axis through the centroid is not fitted away:
+    # |R r - r|^2 = 2 rho^2 (1 - cos th), rho the distance from the axis
+    th = 0.3
+    c = A.mean(0)
+    R = np.array([[np.cos(th), -np.sin(th), 0], [np.sin(th), np.cos(th), 0], [0, 0, 1]])
+    Arot = (A - c) @ R.T + c
+    rho2 = ((A - c)[:, :2] ** 2).sum(1)
+    assert abs(OS.rmsd_lattice(Arot, A, Lx, Ly) - np.sqrt(np.mean(2 * rho2 * (1 - np.cos(th))))) < 1e-12
+    # nor is a permutation: swapping atoms i and j moves two atoms by |x_i - x_j|
+    P = A.copy(); P[[3, 10]] = P[[10, 3]]
+    assert abs(OS.rmsd_lattice(P, A, Lx, Ly) - np.sqrt(2 * ((A[3] - A[10]) ** 2).sum() / len(A))) < 1e-12
+
+
+def test_dedupe_rmsd_discovery_order():
+    mol = S.mol_chain24()
+    A = mol.pos + [2.0, 3.0, 4.0]
+    Lx = Ly = 11.28
+    s = np.array([0.08, 0.0, 0.0])
+    B, Cc = A + s, A + 2 * s                  # rmsd(A,B) = rmsd(B,C) = 0.08, rmsd(A,C) = 0.16
+    new, arch = OS.dedupe_rmsd([A, B, Cc], [0, 0, 0], None, 0.1, Lx, Ly)
+    assert list(new) == [1, 0, 1]             # C is compared with the accepted A only
+    new, _ = OS.dedupe_rmsd([B, A, Cc], [0, 0, 0], None, 0.1, Lx, Ly)
+    assert list(new) == [1, 0, 0]
+    N = A.copy(); N[5, 1] = np.nan
+    new, _ = OS.dedupe_rmsd([A, A, N, A + [Lx, 0, 0], A], [0, 1, 0, 0, 0], [1, 1, 1, 1, 0], 0.1, Lx, Ly)
+    assert list(new) == [1, 1, 0, 0, 0]       # another type is new; NaN, lattice image, ok=0 are not
+    new2, arch2 = OS.dedupe_rmsd([Cc + [0, Ly, 0], A + [0, 0, 0.5]], [0, 0], None, 0.1, Lx, Ly, arch)
+    assert list(new2) == [0, 1] and len(arch2) == 3
+
+
 def test_mlp_backward_matches_finite_differences():
     """P12: the FP64 oracle's gradient against central differences of its own loss."""
     n_types = 3
