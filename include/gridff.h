@@ -332,6 +332,7 @@ gff_status gff_propose_uniform(int n_rep, int n_tors, uint64_t seed, uint32_t ro
  * d_mode[r] = 2 freezes the replica (velocities 0, status GFF_REP_CONVERGED: later launches
  * evaluate it without moving it); 0 leaves it.  Relaxing in launches of a fixed step count
  * with refills in between gives each proposal the trajectory of one uninterrupted launch.
+ * d_pos_src may be state->d_pos itself (mode 1 then only resets velocities and FIRE state).
  * All buffers are caller-owned device memory; asynchronous on `stream`. */
 gff_status gff_refill(const gff_plan *plan, const int *d_mode, const float *d_pos_src, float dt0, float alpha0,
                       const gff_state *state, void *stream);
@@ -364,6 +365,25 @@ gff_status gff_decode_dof(int n, const float *d_enc, int n_tors, float h_lo, flo
 gff_status gff_dedupe_energy(int n_new, const double *d_E, const int *d_type, const int *d_ok, double tol,
                              int capacity, double *d_arch_E, int *d_arch_type, int *d_arch_n, int *d_is_new,
                              void *stream);
+
+/* Distinct minima in discovery order (RMSD criterion, Section "Configuration sampling on
+ * GPU"): two minima of one molecule type are the same when
+ *   min over lattice vectors t = (a Lx, b Ly), a, b integers, of sqrt((1/n) sum_i |x_i - y_i - t|^2) <= tol,
+ * atoms compared in the type's order (adsorption site and orientation count; no rotation fit,
+ * no permutation); the minimising t is the lattice vector nearest the mean difference.  The
+ * candidates are the plan's replicas, positions d_pos [3][N] in the plan's layout, skipped
+ * where d_ok[r] == 0 (d_ok nullable) or a coordinate is non-finite; in replica order, r is
+ * new when it matches no archived minimum of its type, including those accepted earlier in
+ * the call, and the archive has room.  The decision is taken in FP64.
+ * Archive (caller-owned, device): entry k holds atoms d_arch_pos [k][max_atoms][3] (FP32),
+ * centroid d_arch_cen [k][3] (FP64, the mean of its atoms in order), type d_arch_type [k];
+ * *d_arch_n (device int) entries are in use, new minima are appended up to `capacity`.
+ * d_is_new [n_rep] receives 1 for the new minima.  max_atoms must cover every type in the
+ * plan (<= 128).  Two kernels: all candidates against the prior archive in parallel, then
+ * one workgroup walks the survivors in order. */
+gff_status gff_dedupe_rmsd(const gff_plan *plan, const float *d_pos, const int *d_ok, float tol, float Lx, float Ly,
+                           int capacity, int max_atoms, float *d_arch_pos, double *d_arch_cen, int *d_arch_type,
+                           int *d_arch_n, int *d_is_new, void *stream);
 
 /* ------------------------------------------------------------------ learned proposer */
 

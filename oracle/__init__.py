@@ -368,8 +368,8 @@ def fire_batch(B, spec, mols, rep_type, pos, n_steps, vel=None, state=None, intr
     tv, gv = TypesView(mols, alpha), GridView(B, spec)
     rep_type, off = _batch_arrays(mols, rep_type)
     nr = len(rep_type)
-    pos = np.array(pos, dtype=np.float64)
-    vel = np.zeros_like(pos) if vel is None else np.array(vel, dtype=np.float64)
+    pos = np.array(pos, dtype=np.float64, order="C")
+    vel = np.zeros_like(pos) if vel is None else np.array(vel, dtype=np.float64, order="C")
     st = state or {}
     fdt = np.array(st.get("dt", np.full(nr, p["dt0"])), np.float64)
     fal = np.array(st.get("alpha", np.full(nr, p["alpha0"])), np.float64)
@@ -390,9 +390,9 @@ def nve_batch(B, spec, mols, rep_type, pos, vel, n_steps, dt=0.5, drift_every=1,
     tv, gv = TypesView(mols, alpha), GridView(B, spec)
     rep_type, off = _batch_arrays(mols, rep_type)
     nr = len(rep_type)
-    pos = np.array(pos, dtype=np.float64)
-    vel = np.array(vel, dtype=np.float64)
-    st = np.zeros(nr, np.int32) if status is None else np.array(status, np.int32)
+    pos = np.array(pos, dtype=np.float64, order="C")
+    vel = np.array(vel, dtype=np.float64, order="C")
+    st = np.zeros(nr, np.int32) if status is None else np.array(status, np.int32, order="C")
     E, drift = np.zeros(nr), np.zeros((nr, 6))
     lib().orc_nve_batch(C.byref(gv.s), C.byref(tv.s), C.c_int(n_steps), C.c_double(dt),
                         C.c_int(int(intra_on)), C.c_int(drift_every), C.c_int(nr), _i(rep_type)[1],
@@ -407,10 +407,10 @@ def langevin_batch(B, spec, mols, rep_type, pos, vel, n_steps, dt=0.5, T=300.0, 
     tv, gv = TypesView(mols, alpha), GridView(B, spec)
     rep_type, off = _batch_arrays(mols, rep_type)
     nr = len(rep_type)
-    rid = np.arange(nr, dtype=np.int32) if rep_id is None else np.asarray(rep_id, np.int32)
-    pos = np.array(pos, dtype=np.float64)
-    vel = np.array(vel, dtype=np.float64)
-    st = np.zeros(nr, np.int32) if status is None else np.array(status, np.int32)
+    rid = np.arange(nr, dtype=np.int32) if rep_id is None else np.ascontiguousarray(rep_id, np.int32)
+    pos = np.array(pos, dtype=np.float64, order="C")
+    vel = np.array(vel, dtype=np.float64, order="C")
+    st = np.zeros(nr, np.int32) if status is None else np.array(status, np.int32, order="C")
     E = np.zeros(nr)
     kT = 8.617333262e-5 * T
     lib().orc_langevin_batch(C.byref(gv.s), C.byref(tv.s), C.c_int(n_steps), C.c_double(dt), C.c_double(kT),

@@ -99,13 +99,12 @@ def rmsd_lattice(A, B, Lx, Ly):
     two cells of m are tried."""
     D = np.asarray(A, np.float64) - np.asarray(B, np.float64)
     m = D.mean(0)
-    a0, b0 = int(np.floor(m[0] / Lx)), int(np.floor(m[1] / Ly))
-    best = np.inf
-    for a in range(a0 - 2, a0 + 4):
-        for b in range(b0 - 2, b0 + 4):
-            t = np.array([a * Lx, b * Ly, 0.0])
-            best = min(best, float(np.sqrt(np.mean(np.sum((D - t) ** 2, axis=1)))))
-    return best
+    a = np.arange(int(np.floor(m[0] / Lx)) - 2, int(np.floor(m[0] / Lx)) + 4)
+    b = np.arange(int(np.floor(m[1] / Ly)) - 2, int(np.floor(m[1] / Ly)) + 4)
+    T = np.zeros((len(a), len(b), 1, 3))
+    T[..., 0] = a[:, None, None] * Lx
+    T[..., 1] = b[None, :, None] * Ly
+    return float(np.sqrt(np.mean(np.sum((D - T) ** 2, axis=-1), axis=-1)).min())
 
 
 def dedupe_rmsd(pos, types, ok, tol, Lx, Ly, archive=None):

@@ -153,6 +153,119 @@ __global__ void __launch_bounds__(1024) k_dedupe(int n_new, const double *E, con
     if (threadIdx.x == 0) *arch_n = s_n;
 }
 
+// ---------------------------------------------------------------- RMSD deduplication
+// Two minima of one molecule type (same atom order) are the same when the RMSD of their
+// atoms, minimised over the lateral lattice translations t = (a Lx, b Ly), is at most tol
+// (Section "Configuration sampling on GPU": site and orientation count; no rotation fit, no
+// permutation).  The mean square is |t - m|^2 + const with m the mean coordinate
+// difference, so the best t is the lattice vector nearest m.  The sum of squares runs in
+// FP64 over the atoms in order and stops once it exceeds n tol^2: its terms are
+// non-negative, so stopping never changes the decision.
+struct RmsdArgs {
+    const int *rep_type, *atom_off, *ok;
+    const float *pos;                    // [3][N]
+    int N, n_rep, capacity, max_atoms;
+    double Lx, Ly, tol2;
+    float *arch_pos;                     // [capacity][max_atoms][3]
+    double *arch_cen;                    // [capacity][3]
+    int *arch_type, *arch_n, *is_new;
+};
+
+// Candidate c's atoms into LDS (x, y, z per atom); returns whether all are finite.
+__device__ bool stage_candidate(const RmsdArgs &A, int c, float *s_x, double *s_c) {
+    const int g0 = A.atom_off[c], n = A.atom_off[c + 1] - g0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        s_x[3 * i] = A.pos[g0 + i]; s_x[3 * i + 1] = A.pos[g0 + i + A.N]; s_x[3 * i + 2] = A.pos[g0 + i + 2 * A.N];
+    }
+    __syncthreads();
+    bool fin = true;
+    if (threadIdx.x == 0) {             // centroid in FP64, atoms in order
+        double sx = 0.0, sy = 0.0, sz = 0.0;
+        for (int i = 0; i < n; ++i) {
+            const float x = s_x[3 * i], y = s_x[3 * i + 1], z = s_x[3 * i + 2];
+            fin = fin && __builtin_isfinite(x) && __builtin_isfinite(y) && __builtin_isfinite(z);
+            sx += x; sy += y; sz += z;
+        }
+        s_c[0] = sx / n; s_c[1] = sy / n; s_c[2] = sz / n;
+    }
+    return fin;
+}
+
+__device__ bool same_minimum(const RmsdArgs &A, const float *s_x, const double *s_c, int n, int k) {
+    const double *ac = A.arch_cen + 3 * (size_t)k;
+    const double tx = rint((s_c[0] - ac[0]) / A.Lx) * A.Lx, ty = rint((s_c[1] - ac[1]) / A.Ly) * A.Ly;
+    const float *ap = A.arch_pos + (size_t)k * 3 * A.max_atoms;
+    const double lim = n * A.tol2;
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) {
+        const double dx = (double)s_x[3 * i] - (double)ap[3 * i] - tx;
+        const double dy = (double)s_x[3 * i + 1] - (double)ap[3 * i + 1] - ty;
+        const double dz = (double)s_x[3 * i + 2] - (double)ap[3 * i + 2];
+        s += dx * dx + dy * dy + dz * dz;
+        if (s > lim) return false;
+    }
+    return true;
+}
+
+// Pass 1, one block per candidate: is_new[c] = 1 when candidate c (ok, finite) matches no
+// minimum archived before this call.
+__global__ void __launch_bounds__(256) k_rmsd_archive(RmsdArgs A) {
+    __shared__ float s_x[3 * kMaxAtoms];
+    __shared__ double s_c[3];
+    __shared__ int s_state;              // 0 candidate, no match yet; 1 match; 2 not a candidate
+    const int c = blockIdx.x;
+    const bool fin = stage_candidate(A, c, s_x, s_c);
+    if (threadIdx.x == 0) s_state = (fin && (A.ok == nullptr || A.ok[c] != 0)) ? 0 : 2;
+    __syncthreads();
+    if (s_state == 0) {
+        const int n = A.atom_off[c + 1] - A.atom_off[c], t = A.rep_type[c];
+        const int na = min(*A.arch_n, A.capacity);
+        volatile int *vs = &s_state;
+        for (int k = threadIdx.x; k < na && *vs == 0; k += blockDim.x)
+            if (A.arch_type[k] == t && same_minimum(A, s_x, s_c, n, k)) *vs = 1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) A.is_new[c] = s_state == 0;
+}
+
+// Pass 2, one workgroup: the surviving candidates in order against the minima accepted
+// earlier in this call; the new ones are appended.
+__global__ void __launch_bounds__(1024) k_rmsd_batch(RmsdArgs A) {
+    __shared__ float s_x[3 * kMaxAtoms];
+    __shared__ double s_c[3];
+    __shared__ int s_n, s_hit;
+    if (threadIdx.x == 0) s_n = min(*A.arch_n, A.capacity);
+    __syncthreads();
+    const int na0 = s_n;
+    for (int c = 0; c < A.n_rep; ++c) {
+        if (A.is_new[c] == 0) continue;                // uniform across the block
+        stage_candidate(A, c, s_x, s_c);
+        if (threadIdx.x == 0) s_hit = 0;
+        __syncthreads();
+        const int n = A.atom_off[c + 1] - A.atom_off[c], t = A.rep_type[c], na = s_n;
+        for (int k = na0 + threadIdx.x; k < na; k += blockDim.x)
+            if (A.arch_type[k] == t && same_minimum(A, s_x, s_c, n, k)) s_hit = 1;
+        __syncthreads();
+        const bool fresh = !s_hit && na < A.capacity;
+        if (fresh) {
+            float *ap = A.arch_pos + (size_t)na * 3 * A.max_atoms;
+            for (int i = threadIdx.x; i < 3 * n; i += blockDim.x) ap[i] = s_x[i];
+            if (threadIdx.x == 0) {
+                A.arch_cen[3 * (size_t)na] = s_c[0]; A.arch_cen[3 * (size_t)na + 1] = s_c[1];
+                A.arch_cen[3 * (size_t)na + 2] = s_c[2];
+                A.arch_type[na] = t;
+            }
+        }
+        __syncthreads();                               // every thread has read s_n and s_x
+        if (threadIdx.x == 0) {
+            A.is_new[c] = fresh;
+            if (fresh) s_n = na + 1;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *A.arch_n = s_n;
+}
+
 // ---------------------------------------------------------------- pose -> encoding
 // Symmetric 4x4 eigenvector of the largest eigenvalue by cyclic Jacobi rotations.
 __device__ void top_eigvec4(float A[4][4], float v[4]) {
@@ -298,6 +411,22 @@ extern "C" gff_status gff_dedupe_energy(int n_new, const double *d_E, const int 
     if (!d_arch_E || !d_arch_type || !d_arch_n) return GFF_EINVAL;
     hipLaunchKernelGGL(k_dedupe, dim3(1), dim3(1024), 0, (hipStream_t)stream, n_new, d_E, d_type, d_ok, tol, capacity,
                        d_arch_E, d_arch_type, d_arch_n, d_is_new);
+    return hip_status(hipGetLastError());
+}
+
+extern "C" gff_status gff_dedupe_rmsd(const gff_plan *plan, const float *d_pos, const int *d_ok, float tol, float Lx,
+                                      float Ly, int capacity, int max_atoms, float *d_arch_pos, double *d_arch_cen,
+                                      int *d_arch_type, int *d_arch_n, int *d_is_new, void *stream) {
+    if (!plan || !(tol >= 0.f) || !std::isfinite(tol) || !(Lx > 0.f) || !(Ly > 0.f) || capacity < 0) return GFF_EINVAL;
+    if (max_atoms < plan->max_n || max_atoms > kMaxAtoms) return GFF_EINVAL;
+    if (!d_arch_pos || !d_arch_cen || !d_arch_type || !d_arch_n) return GFF_EINVAL;
+    if (plan->n_rep == 0) return GFF_OK;
+    if (!d_pos || !d_is_new) return GFF_EINVAL;
+    RmsdArgs A{plan->d_rep_type, plan->d_atom_off, d_ok, d_pos, plan->n_atoms, plan->n_rep, capacity, max_atoms,
+               (double)Lx, (double)Ly, (double)tol * (double)tol, d_arch_pos, d_arch_cen, d_arch_type, d_arch_n,
+               d_is_new};
+    hipLaunchKernelGGL(k_rmsd_archive, dim3(plan->n_rep), dim3(256), 0, (hipStream_t)stream, A);
+    hipLaunchKernelGGL(k_rmsd_batch, dim3(1), dim3(1024), 0, (hipStream_t)stream, A);
     return hip_status(hipGetLastError());
 }
 

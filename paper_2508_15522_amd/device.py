@@ -81,7 +81,7 @@ def soa(plan, per_rep):
 
 def unsoa(plan, t):
     a = t.detach().cpu().numpy().astype(np.float64)
-    return [a[:, plan.atom_off[r]:plan.atom_off[r + 1]].T for r in range(plan.n_rep)]
+    return [np.ascontiguousarray(a[:, plan.atom_off[r]:plan.atom_off[r + 1]].T) for r in range(plan.n_rep)]
 
 
 def fire_state(plan, pos_per_rep, dt0=0.05, alpha0=0.1, vel_per_rep=None):

@@ -308,7 +308,7 @@ EXPORTS += ["gff_propose_uniform", "gff_pose_from_dof", "gff_encode_pose", "gff_
             "gff_mlp_n_params", "gff_mlp_create", "gff_mlp_destroy", "gff_mlp_get_params", "gff_mlp_workspace_bytes",
             "gff_mlp_forward", "gff_mlp_train_step", "gff_imle_select", "gff_normal_philox", "gff_gemm_bf16",
             "gff_gather_rows", "gff_relax_graph_create", "gff_graph_launch", "gff_graph_destroy", "gff_autotune",
-            "gff_refill"]
+            "gff_refill", "gff_dedupe_rmsd"]
 N_ENC = 41
 
 
@@ -351,6 +351,13 @@ def dedupe_energy(d_E, d_type, d_ok, tol, capacity, d_arch_E, d_arch_type, d_arc
     check(lib().gff_dedupe_energy(C.c_int(d_E.numel()), _ptr(d_E), _ptr(d_type), _ptr(d_ok), C.c_double(tol),
                                   C.c_int(capacity), _ptr(d_arch_E), _ptr(d_arch_type), _ptr(d_arch_n),
                                   _ptr(d_is_new), _stream(stream)))
+
+
+def dedupe_rmsd(plan, d_pos, d_ok, tol, Lx, Ly, capacity, max_atoms, d_arch_pos, d_arch_cen, d_arch_type, d_arch_n,
+                d_is_new, stream=None):
+    check(lib().gff_dedupe_rmsd(plan.handle, _ptr(d_pos), _ptr(d_ok), C.c_float(tol), C.c_float(Lx), C.c_float(Ly),
+                                C.c_int(capacity), C.c_int(max_atoms), _ptr(d_arch_pos), _ptr(d_arch_cen),
+                                _ptr(d_arch_type), _ptr(d_arch_n), _ptr(d_is_new), _stream(stream)))
 
 
 def normal_philox(n, seed, rnd, d_out, stream=None):

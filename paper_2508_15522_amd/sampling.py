@@ -1,11 +1,13 @@
-"""Configuration sampling with uniform or learned proposals (host orchestration only).
+"""Configuration sampling: minima hopping, uniform or learned proposals (host orchestration only).
 
-Each round: proposals (uniform Philox DOF, or the MLP's output from Philox noise,
-decoded) -> poses -> FIRE relaxation to |F| < f_conv in one persistent launch -> energy
-dedupe of the converged minima against the method's archive.  The sampling loop of the
-paper perturbs replicas with Langevin dynamics before relaxing (Section "Configuration
-sampling on GPU"); here proposals are drawn directly and relaxed, and the relaxation
-decides which of them end in minima.
+Minima hopping (Section "Configuration sampling on GPU"): every replica starts from a relaxed
+uniform proposal; each hop runs Langevin dynamics at 300 K from the replica's last minimum,
+relaxes with FIRE to |F| < f_conv and deduplicates the converged minima; replicas continue
+from their new minimum (from the previous one if the relaxation did not converge).
+Proposal rounds: proposals (uniform Philox DOF, or the MLP's output from Philox noise,
+decoded) -> poses -> FIRE relaxation in one persistent launch -> dedupe.  Every converged
+minimum is deduplicated twice, by energy (0.01 eV) and by the lattice-translated RMSD
+(0.1 A), against the archive of the run.
 Training (IMLE): the distinct minima are encoded; for each training minimum K noise rows
 are decoded by the network, the nearest output is kept and a step on it follows.
 Every numerical step is a libgridff call; this module only sequences them.
@@ -24,9 +26,17 @@ H_LO, H_HI = 3.0, 5.0            # uniform proposals: height of the lowest atom 
 DEC_LO, DEC_HI = 1.0, 8.0        # learned proposals: heights outside this range are clamped
 
 
+RMSD_TOL = 0.1                   # A, the paper's uniqueness threshold
+E_TOL = 0.01                     # eV
+
+
 @dataclass
 class Archive:
+    """Distinct minima found so far: energies (energy criterion) and coordinates with their
+    centroids (RMSD criterion), on the device."""
     capacity: int = 200000
+    max_atoms: int = 128
+    rmsd_capacity: int = 50000
     E: torch.Tensor = None
     types: torch.Tensor = None
     n: torch.Tensor = None
@@ -35,9 +45,16 @@ class Archive:
         self.E = torch.zeros(self.capacity, dtype=torch.float64, device="cuda")
         self.types = torch.zeros(self.capacity, dtype=torch.int32, device="cuda")
         self.n = torch.zeros(1, dtype=torch.int32, device="cuda")
+        self.pos = torch.zeros(self.rmsd_capacity, self.max_atoms, 3, device="cuda")
+        self.cen = torch.zeros(self.rmsd_capacity, 3, dtype=torch.float64, device="cuda")
+        self.rtypes = torch.zeros(self.rmsd_capacity, dtype=torch.int32, device="cuda")
+        self.rn = torch.zeros(1, dtype=torch.int32, device="cuda")
 
     def count(self):
         return int(self.n.item())
+
+    def count_rmsd(self):
+        return int(self.rn.item())
 
 
 @dataclass
@@ -49,6 +66,7 @@ class RoundStats:
     seconds: float
     rms_move_converged: float = float("nan")   # mean over converged replicas of the RMS atom move (A)
     new_pos: list = field(default_factory=list)
+    new_minima_rmsd: int = 0
 
 
 class Sampler:
@@ -63,7 +81,17 @@ class Sampler:
         self.types = torch.zeros(n_rep, dtype=torch.int32, device="cuda")
         self.ntors = torch.full((n_rep,), self.T, dtype=torch.int32, device="cuda")
         self.is_new = torch.empty(n_rep, dtype=torch.int32, device="cuda")
+        self.is_new_rmsd = torch.empty(n_rep, dtype=torch.int32, device="cuda")
         self.out = D.outputs(self.plan)
+
+    def _dedupe(self, archive, pos, ok):
+        """Energy and RMSD dedupe of the replicas flagged in ok (device int32 [n_rep]);
+        returns the two counts of new minima."""
+        G.dedupe_energy(self.out["E"], self.types, ok, E_TOL, archive.capacity, archive.E, archive.types, archive.n,
+                        self.is_new)
+        G.dedupe_rmsd(self.plan, pos, ok, RMSD_TOL, self.Lx, self.Ly, archive.rmsd_capacity, archive.max_atoms,
+                      archive.pos, archive.cen, archive.rtypes, archive.rn, self.is_new_rmsd)
+        return int(self.is_new.sum().item()), int(self.is_new_rmsd.sum().item())
 
     def _relax_and_dedupe(self, archive, keep_new):
         st = {"pos": torch.empty(3, self.plan.n_atoms, device="cuda"),
@@ -78,8 +106,7 @@ class Sampler:
         G.relax_batch(self.grid.desc, self.topo, self.plan, prm, st, self.out["E"], self.out["fnorm"],
                       self.out["steps"])
         ok = ((st["status"] & G.REP_CONVERGED) != 0).to(torch.int32)
-        G.dedupe_energy(self.out["E"], self.types, ok, 0.01, archive.capacity, archive.E, archive.types, archive.n,
-                        self.is_new)
+        _, self._last_new_rmsd = self._dedupe(archive, st["pos"], ok)
         torch.cuda.synchronize()
         okh = ok.cpu().numpy().astype(bool)
         steps = self.out["steps"].cpu().numpy()
@@ -99,6 +126,7 @@ class Sampler:
         rs = RoundStats(self.n_rep, int(okh.sum()), int(newh.sum()),
                         float(steps[okh].mean()) if okh.any() else float("nan"), time.time() - t0, move)
         rs.new_pos = [(kept[0], newh, okh, kept[1])] if keep_new else []
+        rs.new_minima_rmsd = self._last_new_rmsd
         return rs
 
     def round_learned(self, archive, mlp, rnd):
@@ -110,7 +138,61 @@ class Sampler:
         G.decode_dof(enc, self.T, DEC_LO, DEC_HI, self.dof)
         okh, steps, newh, _, move = self._relax_and_dedupe(archive, False)
         return RoundStats(self.n_rep, int(okh.sum()), int(newh.sum()),
-                          float(steps[okh].mean()) if okh.any() else float("nan"), time.time() - t0, move)
+                          float(steps[okh].mean()) if okh.any() else float("nan"), time.time() - t0, move,
+                          new_minima_rmsd=self._last_new_rmsd)
+
+    # ---------------------------------------------------------------- minima hopping
+    def minima_hopping(self, archive, n_hops, md_steps=1000, T=300.0, gamma=0.01, dt=0.5, log=None, keep=False):
+        """The paper's sampler on all n_rep replicas at once.  Hop 0 relaxes uniform
+        proposals; hop h >= 1 restores every replica to its last minimum, runs md_steps of
+        Langevin dynamics at T (friction gamma [1/fs], step dt [fs], Philox round h) in one
+        launch, relaxes with FIRE (max_steps moves, |F| < f_conv) in one launch and
+        deduplicates the converged minima by energy and by RMSD.  Converged replicas move
+        their base to the new minimum.  Returns per-hop dicts of counts and wall times; with
+        keep=True also each hop's starting positions, positions after the dynamics, relaxed
+        positions and status (host)."""
+        n = self.n_rep
+        say = log or (lambda m: None)
+        st = {"pos": torch.empty(3, self.plan.n_atoms, device="cuda"),
+              "vel": torch.zeros(3, self.plan.n_atoms, device="cuda"),
+              "fire_dt": torch.full((n,), 0.05, device="cuda"),
+              "fire_alpha": torch.full((n,), 0.1, device="cuda"),
+              "fire_npos": torch.zeros(n, dtype=torch.int32, device="cuda"),
+              "status": torch.zeros(n, dtype=torch.int32, device="cuda")}
+        base = {"pos": torch.empty_like(st["pos"]), "vel": torch.empty_like(st["vel"]),
+                "status": torch.empty_like(st["status"])}
+        all1 = torch.ones(n, dtype=torch.int32, device="cuda")
+        p_md = G.relax_params(G.MODE_LANGEVIN, md_steps, True, dt=dt, T=T, gamma=gamma, seed=self.seed)
+        p_fire = G.relax_params(G.MODE_FIRE, self.max_steps, True, f_conv=self.f_conv)
+        hops = []
+        for h in range(n_hops + 1):
+            t0 = time.time()
+            kept = {"base_in": D.unsoa(self.plan, base["pos"])} if keep and h > 0 else {}
+            if h == 0:
+                G.propose_uniform(n, self.T, self.seed, 0, H_LO, H_HI, self.dof)
+                G.pose_from_dof(self.topo, self.plan, self.dof, 7 + self.T, self.Lx, self.Ly, 0.0, st["pos"])
+            else:
+                G.refill(self.plan, all1, base["pos"], st)          # back to the last minimum, v = 0
+                p_md.round = h
+                G.relax_batch(self.grid.desc, self.topo, self.plan, p_md, st, self.out["E"], self.out["fnorm"],
+                              self.out["steps"])
+                if keep:
+                    kept["md_out"] = D.unsoa(self.plan, st["pos"])
+                G.refill(self.plan, all1, st["pos"], st)            # keep positions, reset FIRE state
+            G.relax_batch(self.grid.desc, self.topo, self.plan, p_fire, st, self.out["E"], self.out["fnorm"],
+                          self.out["steps"])
+            ok = ((st["status"] & G.REP_CONVERGED) != 0).to(torch.int32)
+            new_e, new_r = self._dedupe(archive, st["pos"], ok)
+            if keep:
+                kept.update(pos_out=D.unsoa(self.plan, st["pos"]), status=st["status"].cpu().numpy())
+            # converged replicas continue from the new minimum (hop 0: every replica)
+            G.refill(self.plan, all1 if h == 0 else ok, st["pos"], base)
+            torch.cuda.synchronize()
+            conv = int(ok.sum().item())
+            hops.append(dict(hop=h, converged=conv, new_minima=new_e, new_minima_rmsd=new_r,
+                             seconds=time.time() - t0, **kept))
+            say(f"hop {h}: converged {conv}/{n}, new {new_e} (energy) {new_r} (rmsd), {time.time() - t0:.2f} s")
+        return hops
 
     # ---------------------------------------------------------------- continuous flow
     def propose_uniform_rows(self, rnd):
@@ -160,7 +242,7 @@ class Sampler:
             mode.copy_(torch.from_numpy(np.where(active, 0, 2).astype(np.int32)))
             G.refill(self.plan, mode, st["pos"], st)
         prm = G.relax_params(G.MODE_FIRE, chunk, True, f_conv=self.f_conv)
-        conv_total, new_total, done_total, steps_conv, rec = 0, 0, 0, [], []
+        conv_total, new_total, new_rmsd_total, done_total, steps_conv, rec = 0, 0, 0, 0, [], []
         launches = 0
         while active.any():
             G.relax_batch(self.grid.desc, self.topo, self.plan, prm, st, self.out["E"], self.out["fnorm"],
@@ -173,9 +255,9 @@ class Sampler:
             if not done.any():
                 continue
             ok = torch.from_numpy(conv.astype(np.int32)).cuda()
-            G.dedupe_energy(self.out["E"], self.types, ok, 0.01, archive.capacity, archive.E, archive.types,
-                            archive.n, self.is_new)
-            new_total += int(self.is_new.sum().item())
+            ne, nr = self._dedupe(archive, st["pos"], ok)
+            new_total += ne
+            new_rmsd_total += nr
             conv_total += int(conv.sum()); done_total += int(done.sum())
             steps_conv += list(moves[conv])
             if record:
@@ -201,7 +283,8 @@ class Sampler:
             active[idx] = False
             active[take] = True
         torch.cuda.synchronize()
-        res = dict(proposals=done_total, converged=conv_total, new_minima=new_total, seconds=time.time() - t0,
+        res = dict(proposals=done_total, converged=conv_total, new_minima=new_total, new_minima_rmsd=new_rmsd_total,
+                   seconds=time.time() - t0,
                    launches=launches, mean_steps_converged=float(np.mean(steps_conv)) if steps_conv else float("nan"))
         if record:
             res["records"] = rec
@@ -317,4 +400,35 @@ def compare_learned_vs_uniform(grid, mol, collect_rounds=6, collect_rep=4096, tr
     res["training"] = dict(minima=m, distinct=arch.count(), steps=train_steps, loss_first=hist[0][1],
                            loss_last=hist[-1][1], collect_s=collect_s, train_s=train_s)
     res["gain_minima_per_s"] = res["learned"]["minima_per_s"] / max(res["uniform"]["minima_per_s"], 1e-12)
+    return res
+
+
+def compare_hopping_vs_uniform(grid, mol, n_rep=4096, n_hops=4, md_steps=1000, seed=S.SEED_PHILOX, log=None):
+    """Minima hopping against uniform proposal rounds with the same number of relaxations
+    (n_rep x (n_hops + 1)), each with a fresh archive: distinct minima by energy and by
+    RMSD, wall time (Langevin, relaxation and dedupe included) and minima per second."""
+    say = log or (lambda m: None)
+    res = {}
+    hp = Sampler(grid, mol, n_rep, seed=seed)
+    a = Archive(max_atoms=mol.n)
+    hops = hp.minima_hopping(a, n_hops, md_steps=md_steps, log=say)
+    secs = sum(h["seconds"] for h in hops)
+    res["hopping"] = dict(relaxations=n_rep * (n_hops + 1), converged=sum(h["converged"] for h in hops),
+                          distinct_minima=a.count(), distinct_minima_rmsd=a.count_rmsd(), seconds=secs,
+                          minima_per_s=a.count() / secs, minima_per_s_rmsd=a.count_rmsd() / secs, hops=hops)
+    un = Sampler(grid, mol, n_rep, seed=seed + 41)
+    a = Archive(max_atoms=mol.n)
+    secs, conv = 0.0, 0
+    for r in range(n_hops + 1):
+        rs = un.round_uniform(a, 2000 + r)
+        secs += rs.seconds; conv += rs.converged
+        say(f"uniform round {r}: converged {rs.converged}/{n_rep}, new {rs.new_minima} (energy) "
+            f"{rs.new_minima_rmsd} (rmsd), {rs.seconds:.2f} s")
+    res["uniform"] = dict(relaxations=n_rep * (n_hops + 1), converged=conv, distinct_minima=a.count(),
+                          distinct_minima_rmsd=a.count_rmsd(), seconds=secs, minima_per_s=a.count() / secs,
+                          minima_per_s_rmsd=a.count_rmsd() / secs)
+    for k in ("hopping", "uniform"):
+        r = res[k]
+        say(f"{k}: {r['distinct_minima']} (energy) / {r['distinct_minima_rmsd']} (rmsd) distinct minima from "
+            f"{r['relaxations']} relaxations ({r['converged']} converged) in {r['seconds']:.2f} s")
     return res

@@ -164,3 +164,37 @@ def test_langevin_harmonic_moments_at_large_batch():
         rl = vl[:, sel].mean() / (kT / (m * AMU))
         announce(f"  mass {m}: <z^2> ratio {rz:.4f}, <vz^2> ratio {rv:.4f}, <vxy^2> ratio {rl:.4f}")
         assert abs(rz - 1) < 0.02 and abs(rv - 1) < 0.02 and abs(rl - 1) < 0.02
+
+
+def test_minima_hopping_hops_follow_the_oracle(world):
+    """Two hops of the minima-hopping driver on 64 chain replicas (20 Langevin steps, then up
+    to 30 FIRE moves to |F| < 0.3 eV/A so that some replicas converge): for sampled replicas
+    the oracle's Langevin (replica id r, round h) and FIRE from the hop's starting positions
+    give the relaxed positions; replicas continue from their new minimum only if it
+    converged; the archive counts are the sums of the per-hop counts."""
+    from paper_2508_15522_amd import sampling as SM
+    w = world
+    announce("minima hopping driver")
+    mol = w["mols"][1]
+    sm = SM.Sampler(w["grid"], mol, 64, f_conv=0.3, max_steps=30, seed=4242)
+    arch = SM.Archive(max_atoms=mol.n, capacity=1000, rmsd_capacity=1000)
+    hops = sm.minima_hopping(arch, 2, md_steps=20, keep=True)
+    assert sum(h["new_minima"] for h in hops) == arch.count()
+    assert sum(h["new_minima_rmsd"] for h in hops) == arch.count_rmsd()
+    assert 0 < hops[0]["converged"] < 64
+    for h in (1, 2):
+        hp = hops[h]
+        for r in (0, 5, 31, 63):
+            L = O.langevin_batch(w["B"], w["geo"], [mol], [0], hp["base_in"][r], np.zeros((mol.n, 3)), 20, dt=0.5,
+                                 T=300.0, gamma=0.01, seed=4242, rnd=h, rep_id=[r])
+            dl = np.abs(hp["md_out"][r] - L["pos"]).max()
+            F = O.fire_batch(w["B"], w["geo"], [mol], [0], hp["md_out"][r], 30, f_conv=0.3)
+            dx = np.abs(hp["pos_out"][r] - F["pos"]).max()
+            announce(f"  hop {h} replica {r}: |dx| after dynamics {dl:.2e}, after relaxation {dx:.2e}, "
+                     f"status {hp['status'][r]} / {F['status'][0]}")
+            assert dl < 2e-4 and dx < 2e-4, (h, r, dl, dx)
+            assert hp["status"][r] == F["status"][0]
+        prev = hops[h - 1]
+        for r in range(64):
+            want = prev["pos_out"][r] if (h == 1 or prev["status"][r] & G.REP_CONVERGED) else prev["base_in"][r]
+            assert np.array_equal(hp["base_in"][r], want), (h, r)

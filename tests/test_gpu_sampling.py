@@ -1,5 +1,5 @@
 """GPU parity of the sampling rows: uniform proposals (Philox), pose construction, pose
-encoding/decoding, energy dedupe (a11, a13) and the proposer MLP (a11, a12).
+encoding/decoding, energy and RMSD dedupe (a11, a13) and the proposer MLP (a11, a12).
 
 Tolerances: Philox words are compared bit for bit; FP32 DOF/poses against the FP64 oracle
 within 1e-5 (angles, fractions) and 1e-4 A (poses); the MLP runs BF16 GEMMs with FP32
@@ -111,6 +111,93 @@ def test_dedupe_matches_oracle():
     assert np.array_equal(isn.cpu().numpy(), ref_new)
     assert an.item() == len(arch)
     assert np.array_equal(aE[:len(arch)].cpu().numpy(), np.array([a[0] for a in arch]))
+
+
+def _rmsd_candidates(mols, n, seed, Lx, Ly, n_base=25):
+    """Candidates around a few base poses per type: small per-atom noise (RMSD ~0.02 A to
+    their base), rigid shifts of 0.06 A and 0.12 A along x (a chain: neighbours 0.06 apart,
+    ends 0.12 apart) or 0.4 A, and random lattice translations."""
+    rng = np.random.default_rng(seed)
+    sub = S.rocksalt_slab(2, 3)
+    bases = [S.place_replicas(m, n_base, sub, 9100 + t) for t, m in enumerate(mols)]
+    types = rng.integers(0, len(mols), n)
+    pos = []
+    for t in types:
+        x = bases[t][rng.integers(0, n_base)].copy()
+        kind = rng.integers(0, 5)
+        if kind == 0:
+            x += rng.normal(0, 0.008, x.shape)
+        elif kind in (1, 2):
+            x[:, 0] += 0.06 * kind
+        elif kind == 3:
+            x[:, 1] += 0.4
+        x[:, :2] += [rng.integers(-2, 3) * Lx, rng.integers(-2, 3) * Ly]
+        pos.append(S.f32(x))
+    return types.astype(np.int32), pos
+
+
+def test_dedupe_rmsd_matches_oracle():
+    announce("dedupe rmsd")
+    mols = [S.mol_chain24(), S.mol_pah38(), S.mol_size(10, 1)]
+    Lx, Ly = 11.28, 11.28
+    topo = G.Topology(mols)
+    cap, max_atoms = 4000, 38
+    arch_pos = torch.zeros(cap, max_atoms, 3, device="cuda")
+    arch_cen = torch.zeros(cap, 3, dtype=torch.float64, device="cuda")
+    arch_type = torch.zeros(cap, dtype=torch.int32, device="cuda")
+    arch_n = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ref_arch = None
+    for call, seed in enumerate((31, 32)):
+        types, pos = _rmsd_candidates(mols, 400, seed, Lx, Ly)
+        ok = (np.random.default_rng(seed).random(len(types)) < 0.9).astype(np.int32)
+        if call == 0:
+            pos[7][3, 2] = np.nan
+        plan = G.Plan(topo, types)
+        dpos = D.soa(plan, pos)
+        isn = torch.empty(plan.n_rep, dtype=torch.int32, device="cuda")
+        G.dedupe_rmsd(plan, dpos, torch.from_numpy(ok).cuda(), 0.1, Lx, Ly, cap, max_atoms, arch_pos, arch_cen,
+                      arch_type, arch_n, isn)
+        torch.cuda.synchronize()
+        ref_new, ref_arch = OS.dedupe_rmsd(pos, types, ok, 0.1, Lx, Ly, ref_arch)
+        got = isn.cpu().numpy()
+        announce(f"  call {call}: {int(got.sum())} new of {len(types)} (oracle {int(ref_new.sum())}), "
+                 f"archive {arch_n.item()}")
+        assert np.array_equal(got, ref_new)
+    na = arch_n.item()
+    assert na == len(ref_arch)
+    ap, at, ac = arch_pos.cpu().numpy(), arch_type.cpu().numpy(), arch_cen.cpu().numpy()
+    for k, (x, t) in enumerate(ref_arch):
+        assert at[k] == t
+        assert np.array_equal(ap[k, :len(x)].astype(np.float64), x)
+        assert np.abs(ac[k] - x.mean(0)).max() < 1e-12
+    # every decision is robust: no accepted pair of one type lies within 1e-4 A of the threshold
+    d = [OS.rmsd_lattice(x, y, Lx, Ly) for i, (x, t) in enumerate(ref_arch) for (y, u) in ref_arch[:i] if t == u]
+    assert min(abs(np.array(d) - 0.1)) > 1e-4
+
+
+def test_dedupe_rmsd_capacity_and_arguments():
+    announce("dedupe rmsd capacity")
+    mols = [S.mol_chain24()]
+    topo = G.Topology(mols)
+    types, pos = _rmsd_candidates(mols, 50, 33, 11.28, 11.28)
+    plan = G.Plan(topo, types)
+    dpos = D.soa(plan, pos)
+    cap = 3
+    arch_pos = torch.zeros(cap, 24, 3, device="cuda")
+    arch_cen = torch.zeros(cap, 3, dtype=torch.float64, device="cuda")
+    arch_type = torch.zeros(cap, dtype=torch.int32, device="cuda")
+    arch_n = torch.zeros(1, dtype=torch.int32, device="cuda")
+    isn = torch.empty(plan.n_rep, dtype=torch.int32, device="cuda")
+    G.dedupe_rmsd(plan, dpos, None, 0.1, 11.28, 11.28, cap, 24, arch_pos, arch_cen, arch_type, arch_n, isn)
+    torch.cuda.synchronize()
+    ref_new, _ = OS.dedupe_rmsd(pos, types, None, 0.1, 11.28, 11.28)
+    got = isn.cpu().numpy()
+    first = np.where(ref_new)[0][:cap]
+    assert arch_n.item() == cap and np.array_equal(np.where(got)[0], first)
+    with pytest.raises(G.GffError):       # archive entries too small for the plan's molecules
+        G.dedupe_rmsd(plan, dpos, None, 0.1, 11.28, 11.28, cap, 23, arch_pos, arch_cen, arch_type, arch_n, isn)
+    with pytest.raises(G.GffError):
+        G.dedupe_rmsd(plan, dpos, None, -0.1, 11.28, 11.28, cap, 24, arch_pos, arch_cen, arch_type, arch_n, isn)
 
 
 def _bf16_bits(a):

@@ -423,6 +423,22 @@ def test_langevin_noise_keyed_by_replica_id_seed_and_round():
     assert np.abs(r3["pos"] - r1["pos"]).max() > 1e-4 and np.abs(r4["pos"] - r1["pos"]).max() > 1e-4
 
 
+def test_batch_wrappers_accept_strided_coordinates():
+    """Coordinates handed over as transposed views (as a [3][N] layout yields) give the same
+    trajectories as contiguous copies."""
+    spec = dict(nx=8, ny=8, nz=12, x0=0.0, y0=0.0, z0=1.0, dx=0.5, dy=0.5, dz=0.5)
+    B = O.fit_bspline(RNG.normal(size=(3, 8, 8, 12)) * 0.01)
+    mol = S.mol_chain24()
+    x = np.ascontiguousarray((mol.pos + [2.0, 2.0, 4.0]).T).T       # (n, 3) view of a (3, n) array
+    v = np.ascontiguousarray(S.mb_velocities(mol.mass, 1, 300.0, 7002)[0].T).T
+    assert not x.flags.c_contiguous
+    xc, vc = np.ascontiguousarray(x), np.ascontiguousarray(v)
+    for f in (lambda p, u: O.fire_batch(B, spec, [mol], [0], p, 20, vel=u),
+              lambda p, u: O.nve_batch(B, spec, [mol], [0], p, u, 20),
+              lambda p, u: O.langevin_batch(B, spec, [mol], [0], p, u, 20, gamma=0.05, rep_id=np.array([3, 9])[::2])):
+        assert np.array_equal(f(x, v)["pos"], f(xc, vc)["pos"])
+
+
 def test_langevin_harmonic_stationary_moments():
     """One-atom molecules (q = 1) in a Coulomb channel whose B-spline model is exactly
     k (z - zc)^2 and flat laterally.  For a quadratic potential BAOAB samples positions
