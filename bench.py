@@ -235,7 +235,9 @@ def main():
                                "gain": cmp["gain_minima_per_s"],
                                "flow_learned": cmp["learned"]["flow"]["minima_per_s"],
                                "flow_uniform": cmp["uniform"]["flow"]["minima_per_s"],
-                               "flow_gain": cmp["gain_minima_per_s_flow"], "detail": cmp,
+                               "flow_gain": cmp["gain_minima_per_s_flow"],
+                               "gain_rmsd": cmp["gain_minima_per_s_rmsd"],
+                               "flow_gain_rmsd": cmp["gain_minima_per_s_flow_rmsd"], "detail": cmp,
                                "workload": "chain24 FIRE to 1e-4 eV/A (max 5000 steps), distinct within 0.01 eV"}
     if args.hopping:
         from paper_2508_15522_amd import sampling as SM

@@ -371,7 +371,7 @@ def compare_learned_vs_uniform(grid, mol, collect_rounds=6, collect_rep=4096, tr
     ev = Sampler(grid, mol, eval_rep, seed=seed + 17)
     res = {}
     for name in ("uniform", "learned"):
-        a = Archive()
+        a = Archive(max_atoms=mol.n)
         secs, conv, props, steps, moves = 0.0, 0, 0, [], []
         for r in range(eval_rounds):
             rs = ev.round_uniform(a, 1000 + r) if name == "uniform" else ev.round_learned(a, mlp, 1000 + r)
@@ -380,26 +380,34 @@ def compare_learned_vs_uniform(grid, mol, collect_rounds=6, collect_rep=4096, tr
         n_min = a.count()
         res[name] = dict(distinct_minima=n_min, proposals=props, converged=conv, seconds=secs,
                          minima_per_s=n_min / secs, mean_fire_steps=float(np.nanmean(steps)),
-                         mean_rms_move=float(np.nanmean(moves)))
-        say(f"{name}: {n_min} distinct minima from {props} proposals ({conv} converged) in {secs:.2f} s, "
+                         mean_rms_move=float(np.nanmean(moves)), distinct_minima_rmsd=a.count_rmsd(),
+                         minima_per_s_rmsd=a.count_rmsd() / secs)
+        say(f"{name}: {n_min} distinct minima ({a.count_rmsd()} by RMSD) from {props} proposals ({conv} converged) "
+            f"in {secs:.2f} s, "
             f"mean FIRE steps {res[name]['mean_fire_steps']:.0f}, mean RMS move {res[name]['mean_rms_move']:.2f} A")
     # the same comparison in continuous flow (finished slots refilled between 250-step
     # launches), where a proposal costs the steps it needs rather than its launch's slowest
     for name in ("uniform", "learned"):
         fl = Sampler(grid, mol, eval_rep, seed=seed + 29)
         prop = fl.propose_uniform_rows if name == "uniform" else fl.propose_learned_rows(mlp)
-        a = Archive()
+        a = Archive(max_atoms=mol.n)
         r = fl.flow(a, eval_rounds * eval_rep, prop, chunk=250)
         res[name]["flow"] = dict(distinct_minima=r["new_minima"], proposals=r["proposals"], converged=r["converged"],
                                  seconds=r["seconds"], minima_per_s=r["new_minima"] / r["seconds"],
-                                 mean_fire_steps=r["mean_steps_converged"], launches=r["launches"])
-        say(f"{name} (flow): {r['new_minima']} distinct minima from {r['proposals']} proposals ({r['converged']} "
-            f"converged) in {r['seconds']:.2f} s")
+                                 mean_fire_steps=r["mean_steps_converged"], launches=r["launches"],
+                                 distinct_minima_rmsd=r["new_minima_rmsd"],
+                                 minima_per_s_rmsd=r["new_minima_rmsd"] / r["seconds"])
+        say(f"{name} (flow): {r['new_minima']} distinct minima ({r['new_minima_rmsd']} by RMSD) from "
+            f"{r['proposals']} proposals ({r['converged']} converged) in {r['seconds']:.2f} s")
     res["gain_minima_per_s_flow"] = (res["learned"]["flow"]["minima_per_s"] /
                                      max(res["uniform"]["flow"]["minima_per_s"], 1e-12))
     res["training"] = dict(minima=m, distinct=arch.count(), steps=train_steps, loss_first=hist[0][1],
                            loss_last=hist[-1][1], collect_s=collect_s, train_s=train_s)
     res["gain_minima_per_s"] = res["learned"]["minima_per_s"] / max(res["uniform"]["minima_per_s"], 1e-12)
+    res["gain_minima_per_s_rmsd"] = (res["learned"]["minima_per_s_rmsd"] /
+                                     max(res["uniform"]["minima_per_s_rmsd"], 1e-12))
+    res["gain_minima_per_s_flow_rmsd"] = (res["learned"]["flow"]["minima_per_s_rmsd"] /
+                                          max(res["uniform"]["flow"]["minima_per_s_rmsd"], 1e-12))
     return res
 
 
@@ -410,6 +418,7 @@ def compare_hopping_vs_uniform(grid, mol, n_rep=4096, n_hops=4, md_steps=1000, s
     say = log or (lambda m: None)
     res = {}
     hp = Sampler(grid, mol, n_rep, seed=seed)
+    hp.round_uniform(Archive(max_atoms=mol.n, capacity=1000, rmsd_capacity=1000), 999)     # warm-up, not counted
     a = Archive(max_atoms=mol.n)
     hops = hp.minima_hopping(a, n_hops, md_steps=md_steps, log=say)
     secs = sum(h["seconds"] for h in hops)
@@ -417,6 +426,7 @@ def compare_hopping_vs_uniform(grid, mol, n_rep=4096, n_hops=4, md_steps=1000, s
                           distinct_minima=a.count(), distinct_minima_rmsd=a.count_rmsd(), seconds=secs,
                           minima_per_s=a.count() / secs, minima_per_s_rmsd=a.count_rmsd() / secs, hops=hops)
     un = Sampler(grid, mol, n_rep, seed=seed + 41)
+    un.round_uniform(Archive(max_atoms=mol.n, capacity=1000, rmsd_capacity=1000), 1999)   # warm-up, not counted
     a = Archive(max_atoms=mol.n)
     secs, conv = 0.0, 0
     for r in range(n_hops + 1):
