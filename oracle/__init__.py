@@ -33,7 +33,7 @@ PINS = {
     "morse_direct": "single-atom analytic case, FD gradient, lattice symmetry (P6)",
     "coulomb_ewald2d": "eta independence, Fourier form above slab, corrugation decay (P7)",
     "intra": "FD gradient, zero net force/torque, rigid-motion invariance (P11)",
-    "fire_batch": "quadratic-bowl convergence (P10)",
+    "fire_batch": "quadratic-bowl convergence (P10); restraint: held atom, bond-length and inactive-restraint cases",
     "nve_batch": "dt^2 scaling of the energy fluctuation (P9)",
     "philox4x32_10": "published known-answer vectors",
     "pose": "torsion set to target, rigid-body invariants",
@@ -361,8 +361,10 @@ FIRE_DEFAULTS = dict(dt0=0.05, f_conv=1e-4, max_disp=0.1, finc=1.1, fdec=0.5, al
 
 
 def fire_batch(B, spec, mols, rep_type, pos, n_steps, vel=None, state=None, intra_on=True,
-               alpha=1.6, **kw):
-    """FIRE relaxation; returns dict with pos, vel, dt, alpha, npos, status, E, fnorm, steps."""
+               alpha=1.6, fixed_atom=None, fixed_pos=None, **kw):
+    """FIRE relaxation; returns dict with pos, vel, dt, alpha, npos, status, E, fnorm, steps.
+    fixed_atom [n_rep] (index in the molecule, -1 none) with fixed_pos [n_rep][3]: one
+    restrained atom per replica."""
     p = dict(FIRE_DEFAULTS)
     p.update(kw)
     tv, gv = TypesView(mols, alpha), GridView(B, spec)
@@ -381,7 +383,9 @@ def fire_batch(B, spec, mols, rep_type, pos, n_steps, vel=None, state=None, intr
     ip = lambda a: a.ctypes.data_as(C.POINTER(C.c_int))
     lib().orc_fire_batch(C.byref(gv.s), C.byref(tv.s), C.byref(prm), C.c_int(nr), _i(rep_type)[1],
                          _i(off)[1], _nullable(pos), _nullable(vel), _nullable(fdt), _nullable(fal),
-                         ip(fnp), ip(status), _nullable(E), _nullable(fn), ip(steps))
+                         ip(fnp), ip(status), _nullable(E), _nullable(fn), ip(steps),
+                         None if fixed_atom is None else _i(fixed_atom)[1],
+                         None if fixed_atom is None else _d(fixed_pos)[1])
     return dict(pos=pos, vel=vel, dt=fdt, alpha=fal, npos=fnp, status=status, E=E, fnorm=fn, steps=steps)
 
 

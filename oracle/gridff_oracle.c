@@ -567,11 +567,17 @@ typedef struct {
  * dx = v dt, each atom's step scaled down to |dx_i| <= max_disp; x <- x + dx.  After n_steps
  * moves the state is evaluated once more (and tested).  Non-finite replicas freeze (bit 4) and
  * report NaN; replicas converged on entry are evaluated once and not moved.
- * Not converged after n_steps with f_conv > 0: bit 8.  State arrays are in/out. */
+ * Not converged after n_steps with f_conv > 0: bit 8.  State arrays are in/out.
+ * Restraint (the manipulation scans of the paper's relaxed detachment and dragging: one atom
+ * held, the rest relaxed): if fixed_atom is given and 0 <= fixed_atom[r] < n, that atom is
+ * placed at fixed_pos[r] on entry, its velocity is zero and its force is replaced by zero
+ * (the restraint's reaction), so it never moves and takes no part in |F|, F.v or the mixing;
+ * the energy is the whole replica's. */
 void orc_fire_batch(const orc_grid *g, const orc_types *T, const orc_fire_params *prm, int n_rep,
                     const int *rep_type, const int *atom_off, double *pos, double *vel,
                     double *fdt, double *falpha, int *fnpos, int *status,
-                    double *E_rep, double *fnorm_rep, int *steps_rep)
+                    double *E_rep, double *fnorm_rep, int *steps_rep,
+                    const int *fixed_atom, const double *fixed_pos)
 {
     #pragma omp parallel for schedule(dynamic, 1)
     for (int r = 0; r < n_rep; ++r) {
@@ -586,8 +592,12 @@ void orc_fire_batch(const orc_grid *g, const orc_types *T, const orc_fire_params
         int st = status[r], steps = 0;
         double E = 0, fn = 0;
         if (st & 4) { E = NAN; fn = NAN; }
+        const int fa = (fixed_atom && fixed_atom[r] >= 0 && fixed_atom[r] < n) ? fixed_atom[r] : -1;
+        if (fa >= 0)
+            for (int c = 0; c < 3; ++c) { x[3*fa+c] = fixed_pos[3*r+c]; v[3*fa+c] = 0; }
         for (int it = 0; it <= prm->n_steps && !(st & 4); ++it) {
             st |= replica_force(g, &m, plq, prm->intra, ex, x, F, &E, NULL, Ft);
+            if (fa >= 0) F[3*fa] = F[3*fa+1] = F[3*fa+2] = 0;
             double ff = 0, fv = 0, vv = 0;
             for (int i = 0; i < 3 * n; ++i) { ff += F[i] * F[i]; fv += F[i] * v[i]; vv += v[i] * v[i]; }
             fn = sqrt(ff);

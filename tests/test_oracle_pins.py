@@ -319,6 +319,55 @@ def test_p10_fire_converges_on_quadratic_bowl():
     assert np.array_equal(out2["pos"], out["pos"]) and (out2["steps"] == 0).all()
 
 
+def _dimer():
+    m = _one_atom()
+    m.elem = ["C", "C"]; m.pos = np.zeros((2, 3)); m.q = np.zeros(2); m.eps = np.zeros(2); m.R = np.zeros(2)
+    m.mass = np.array([12.011, 12.011]); m.bonds = np.array([[0, 1]], np.int32)
+    m.bond_k = np.array([20.0]); m.bond_r0 = np.array([1.4])
+    return m
+
+
+def test_fire_restraint_holds_atom_and_relaxes_the_rest():
+    """A restrained atom never moves; its bonded partner relaxes along the bond to the rest
+    length (the bond force is radial and FIRE starts from rest, so the direction is kept);
+    replicas without a restraint are unaffected."""
+    spec = dict(nx=4, ny=4, nz=4, x0=0.0, y0=0.0, z0=-50.0, dx=1.0, dy=1.0, dz=1.0)
+    B = np.zeros((3, 4, 4, 4))
+    m = _dimer()
+    x0 = np.array([[0.3, 0.2, 0.1], [2.2, 0.6, -0.3], [0.0, 0.0, 0.0], [1.0, 0.9, 0.0]])
+    target = np.array([[0.0, 0.0, 0.0], [9.0, 9.0, 9.0]])
+    out = O.fire_batch(B, spec, [m], [0, 0], x0, 3000, f_conv=1e-8, intra_on=True,
+                       fixed_atom=np.array([0, -1]), fixed_pos=target)
+    assert (out["status"] & 1).all()
+    assert np.array_equal(out["pos"][0], target[0])
+    d = out["pos"][1] - out["pos"][0]
+    u = (x0[1] - target[0]) / np.linalg.norm(x0[1] - target[0])
+    assert abs(np.linalg.norm(d) - 1.4) < 1e-8 / 20
+    assert np.abs(d / np.linalg.norm(d) - u).max() < 1e-9
+    free = O.fire_batch(B, spec, [m], [0], x0[2:], 3000, f_conv=1e-8)
+    assert np.array_equal(out["pos"][2:], free["pos"])
+
+
+def test_fire_restraint_at_the_minimum_is_inactive():
+    """Holding one atom where the free relaxation put it leaves that minimum a minimum: a
+    perturbed start relaxes back to the same energy and geometry."""
+    spec = dict(nx=8, ny=8, nz=12, x0=0.0, y0=0.0, z0=1.0, dx=0.5, dy=0.5, dz=0.5)
+    B = O.fit_bspline(RNG.normal(size=(3, 8, 8, 12)) * 0.01)
+    mol = S.mol_chain24()
+    x0 = mol.pos + [2.0, 2.0, 4.0]
+    free = O.fire_batch(B, spec, [mol], [0], x0, 20000, f_conv=1e-7)
+    assert (free["status"] & 1).all()
+    xs = free["pos"]
+    j = 5
+    start = xs + np.random.default_rng(3).normal(0, 0.02, xs.shape)
+    held = O.fire_batch(B, spec, [mol], [0], start, 20000, f_conv=1e-7, fixed_atom=np.array([j]),
+                        fixed_pos=xs[j][None])
+    assert (held["status"] & 1).all()
+    assert np.array_equal(held["pos"][j], xs[j])
+    assert abs(held["E"][0] - free["E"][0]) < 1e-9
+    assert np.abs(held["pos"] - xs).max() < 1e-4
+
+
 def test_fire_resume_equals_continuous():
     sub_spec = dict(nx=8, ny=8, nz=12, x0=0.0, y0=0.0, z0=1.0, dx=0.5, dy=0.5, dz=0.5)
     B = O.fit_bspline(RNG.normal(size=(3, 8, 8, 12)) * [[[[0.01]]], [[[0.01]]], [[[0.01]]]])
