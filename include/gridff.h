@@ -224,6 +224,14 @@ typedef struct {
     float *d_fire_alpha;      /* [n_rep] FIRE mixing (initialise to alpha0) */
     int *d_fire_npos;         /* [n_rep] steps since P <= 0 (initialise to 0) */
     unsigned *d_status;       /* [n_rep] GFF_REP_* bits (initialise to 0) */
+    /* Restraint, FIRE only (the manipulation scans of Sections "Relaxed detachment" and
+     * "Dragging": one atom held, the rest relaxed); both NULL for none.  d_fixed_atom [n_rep]:
+     * index of the held atom in its molecule (outside [0, n): none); d_fixed_pos [n_rep][3]:
+     * where it is held.  On entry the atom is placed there with zero velocity; its force is
+     * replaced by zero, so it never moves and takes no part in |F|_2, P = F.v or the mixing;
+     * the energy is the whole replica's. */
+    const int *d_fixed_atom;
+    const float *d_fixed_pos;
 } gff_state;
 
 /* FIRE (Bitzek et al. 2006) per replica with unit masses, every step on the GPU:

@@ -59,6 +59,8 @@ struct KArgs {
     float dt, f_conv, max_disp, finc, fdec, a0, falpha_f, dtmax;
     float lg_c1, lg_c2, kT;             // Langevin: exp(-gamma dt), sqrt(1 - c1^2), k_B T
     unsigned seed_lo, seed_hi, round;   // Langevin: Philox key and fourth counter word
+    const int *fixed_atom;              // FIRE restraint: held atom per replica (nullable)
+    const float *fixed_pos;             // its position [n_rep][3]
     DirectView d;                       // all-atom comparison mode only
 };
 
@@ -542,6 +544,7 @@ k_replicas(KArgs A) {
         uint4 ex = make_uint4(0u, 0u, 0u, 0u);
         float khalf = 0.f;
         float fdt = 0.f, fal = 0.f; int fnp = 0; unsigned st = GFF_REP_NONFINITE;
+        bool held = false;                // FIRE restraint: this atom is held in place
         if (active) {
             rep = A.pack_reps[pinfo.z + lr];
             g = A.atom_off[rep] + at;
@@ -552,6 +555,11 @@ k_replicas(KArgs A) {
             khalf = A.t.khalf[abase + at];
             st = MODE == MODE_EVAL ? 0u : A.status[rep];
             if (MODE == MODE_FIRE) { fdt = A.fdt[rep]; fal = A.falpha[rep]; fnp = A.fnpos[rep]; }
+            if (MODE == MODE_FIRE && A.fixed_atom != nullptr && A.fixed_atom[rep] == at) {
+                held = true;
+                x = make_float3(A.fixed_pos[3 * rep], A.fixed_pos[3 * rep + 1], A.fixed_pos[3 * rep + 2]);
+                v = make_float3(0.f, 0.f, 0.f);
+            }
         }
         s_plq[tid] = me;
         s_nf[tid] = 0;
@@ -718,6 +726,7 @@ k_replicas(KArgs A) {
                 }
             }
             if (live) e_atom = e_grid + e_intra;
+            if (MODE == MODE_FIRE && held) F = make_float3(0.f, 0.f, 0.f);   // the restraint's reaction
 
             if (MODE == MODE_EVAL) break;
 
@@ -985,6 +994,8 @@ static gff_status relax_check(const gff_topology *topo, const gff_plan *plan, co
     if (p->mode == GFF_MODE_FIRE && (!state->d_fire_dt || !state->d_fire_alpha || !state->d_fire_npos))
         return GFF_EINVAL;
     if (p->mode == GFF_MODE_NVE && d_drift_rep && p->drift_every < 1) return GFF_EINVAL;
+    if ((state->d_fixed_atom != nullptr) != (state->d_fixed_pos != nullptr)) return GFF_EINVAL;
+    if (state->d_fixed_atom && p->mode != GFF_MODE_FIRE) return GFF_EUNSUPPORTED;
     if (p->mode == GFF_MODE_LANGEVIN &&
         (d_drift_rep || !(p->kT >= 0.f) || !(p->gamma >= 0.f) || !std::isfinite(p->kT) || !std::isfinite(p->gamma) ||
          !std::isfinite(p->dt)))
@@ -999,6 +1010,7 @@ static gff_status relax_common(int storage, KArgs &A, const gff_topology *topo, 
     A.pos = state->d_pos; A.vel = state->d_vel;
     A.fdt = state->d_fire_dt; A.falpha = state->d_fire_alpha; A.fnpos = state->d_fire_npos;
     A.status = state->d_status;
+    A.fixed_atom = state->d_fixed_atom; A.fixed_pos = state->d_fixed_pos;
     A.E_rep = d_E_rep; A.fnorm = d_fnorm_rep; A.steps = d_steps_rep;
     A.drift = p->mode == GFF_MODE_NVE ? d_drift_rep : nullptr;
     A.n_steps = p->n_steps; A.include_intra = p->include_intra;

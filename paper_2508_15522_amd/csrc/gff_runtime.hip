@@ -87,6 +87,8 @@ extern "C" gff_status gff_autotune(const gff_grid *grid, const gff_topology *top
     t.d_fire_alpha = (float *)p; p += rb;
     t.d_fire_npos = (int *)p; p += rb;
     t.d_status = (unsigned *)p; p += rb;
+    t.d_fixed_atom = state->d_fixed_atom;       // read only: shared with the caller
+    t.d_fixed_pos = state->d_fixed_pos;
     double *E = (double *)p; p += (size_t)n_rep * sizeof(double);
     double *drift = (double *)p; p += (size_t)n_rep * 6 * sizeof(double);
     float *fn = (float *)p; p += (size_t)n_rep * sizeof(float);

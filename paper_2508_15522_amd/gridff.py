@@ -67,7 +67,8 @@ class RelaxParams(C.Structure):
 
 class State(C.Structure):
     _fields_ = [("d_pos", C.c_void_p), ("d_vel", C.c_void_p), ("d_fire_dt", C.c_void_p),
-                ("d_fire_alpha", C.c_void_p), ("d_fire_npos", C.c_void_p), ("d_status", C.c_void_p)]
+                ("d_fire_alpha", C.c_void_p), ("d_fire_npos", C.c_void_p), ("d_status", C.c_void_p),
+                ("d_fixed_atom", C.c_void_p), ("d_fixed_pos", C.c_void_p)]
 
 
 EXPORTS = [
@@ -253,13 +254,16 @@ def relax_params(mode=MODE_FIRE, n_steps=1000, include_intra=True, dt=0.5, f_con
                        dtmax, nmin, drift_every, K_B * T, gamma, seed, rnd)
 
 
+def _state(st):
+    g = lambda k: st[k].data_ptr() if k in st and st[k] is not None else None
+    return State(g("pos"), g("vel"), g("fire_dt"), g("fire_alpha"), g("fire_npos"), g("status"), g("fixed_atom"),
+                 g("fixed_pos"))
+
+
 def relax_batch(grid_desc, topo, plan, params, st, d_E_rep, d_fnorm, d_steps, d_drift=None, stream=None):
-    """st: dict of torch tensors pos, vel, fire_dt, fire_alpha, fire_npos, status."""
-    state = State(st["pos"].data_ptr(), st["vel"].data_ptr(),
-                  st["fire_dt"].data_ptr() if "fire_dt" in st else None,
-                  st["fire_alpha"].data_ptr() if "fire_alpha" in st else None,
-                  st["fire_npos"].data_ptr() if "fire_npos" in st else None,
-                  st["status"].data_ptr())
+    """st: dict of torch tensors pos, vel, fire_dt, fire_alpha, fire_npos, status and, for a
+    restraint, fixed_atom (int32 [n_rep]) and fixed_pos (float32 [n_rep][3])."""
+    state = _state(st)
     check(lib().gff_relax_batch(C.byref(grid_desc), topo.handle, plan.handle, C.byref(params), C.byref(state),
                                 _ptr(d_E_rep), _ptr(d_fnorm), _ptr(d_steps), _ptr(d_drift), _stream(stream)))
 
@@ -293,11 +297,7 @@ def eval_forces_direct(direct, topo, plan, include_intra, d_pos, d_F, d_E_atom=N
 
 
 def relax_batch_direct(direct, topo, plan, params, st, d_E_rep, d_fnorm, d_steps, d_drift=None, stream=None):
-    state = State(st["pos"].data_ptr(), st["vel"].data_ptr(),
-                  st["fire_dt"].data_ptr() if "fire_dt" in st else None,
-                  st["fire_alpha"].data_ptr() if "fire_alpha" in st else None,
-                  st["fire_npos"].data_ptr() if "fire_npos" in st else None,
-                  st["status"].data_ptr())
+    state = _state(st)
     check(lib().gff_relax_batch_direct(direct.handle, topo.handle, plan.handle, C.byref(params), C.byref(state),
                                        _ptr(d_E_rep), _ptr(d_fnorm), _ptr(d_steps), _ptr(d_drift),
                                        _stream(stream)))
@@ -323,11 +323,7 @@ def propose_uniform(n_rep, n_tors, seed, rnd, h_lo, h_hi, d_dof, d_raw=None, str
 
 def refill(plan, d_mode, d_pos_src, st, dt0=0.05, alpha0=0.1, stream=None):
     """Replace (mode 1) or freeze (mode 2) replicas of a relaxation state between launches."""
-    state = State(st["pos"].data_ptr(), st["vel"].data_ptr(),
-                  st["fire_dt"].data_ptr() if "fire_dt" in st else None,
-                  st["fire_alpha"].data_ptr() if "fire_alpha" in st else None,
-                  st["fire_npos"].data_ptr() if "fire_npos" in st else None,
-                  st["status"].data_ptr())
+    state = _state(st)
     check(lib().gff_refill(plan.handle, _ptr(d_mode), _ptr(d_pos_src), C.c_float(dt0), C.c_float(alpha0),
                            C.byref(state), _stream(stream)))
 
@@ -433,10 +429,7 @@ class RelaxGraph:
     """A captured relaxation launch (fixed buffers); launch() re-runs it."""
 
     def __init__(self, grid_desc, topo, plan, params, st, d_E_rep, d_fnorm, d_steps, d_drift=None):
-        self.state = State(st["pos"].data_ptr(), st["vel"].data_ptr(),
-                           st["fire_dt"].data_ptr() if "fire_dt" in st else None,
-                           st["fire_alpha"].data_ptr() if "fire_alpha" in st else None,
-                           st["fire_npos"].data_ptr() if "fire_npos" in st else None, st["status"].data_ptr())
+        self.state = _state(st)
         self.keep = (grid_desc, topo, plan, params, st, d_E_rep, d_fnorm, d_steps, d_drift)
         self.handle = C.c_void_p()
         check(lib().gff_relax_graph_create(C.byref(grid_desc), topo.handle, plan.handle, C.byref(params),
@@ -455,10 +448,7 @@ class RelaxGraph:
 def autotune(grid_desc, topo, rep_type, params, st, stream=None):
     """Measured launch shape -> (Launch, replica-steps/s)."""
     rt = np.ascontiguousarray(rep_type, dtype=np.int32)
-    state = State(st["pos"].data_ptr(), st["vel"].data_ptr(),
-                  st["fire_dt"].data_ptr() if "fire_dt" in st else None,
-                  st["fire_alpha"].data_ptr() if "fire_alpha" in st else None,
-                  st["fire_npos"].data_ptr() if "fire_npos" in st else None, st["status"].data_ptr())
+    state = _state(st)
     best = Launch()
     rate = C.c_float()
     check(lib().gff_autotune(C.byref(grid_desc), topo.handle, C.c_int(len(rt)), rt.ctypes.data_as(C.c_void_p),
