@@ -101,6 +101,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--minima", action="store_true", help="learned vs uniform proposals: minima found per second")
+    ap.add_argument("--scans", action="store_true",
+                    help="batched restrained scans: relaxed detachment and drag of pah38, 4096 paths")
     ap.add_argument("--hopping", action="store_true",
                     help="minima hopping (Langevin + FIRE) vs uniform proposals: minima found per second")
     ap.add_argument("--extra", nargs="*", default=[], choices=["c1", "c3", "c5"],
@@ -248,6 +250,8 @@ def main():
         res["minima_hopping"]["workload"] = ("chain24, 4096 replicas: 1000 Langevin steps at 300 K (dt 0.5 fs, "
                                              "gamma 0.01/fs) then FIRE to 1e-4 eV/A (max 5000 steps), 4 hops "
                                              "after the initial relaxation; distinct within 0.01 eV / 0.1 A RMSD")
+    if args.scans:
+        res["restrained_scans"] = run_scans(grid if args.storage == "f32" else setup(G.STORE_F32), log)
     for extra in args.extra:
         res.setdefault("other_workloads", {})[extra] = run_workload(extra, log)
     for name in args.direct:
@@ -310,6 +314,46 @@ def run_workload(name, log):
         r["autotune_rate"] = tuned
     log(f"{name}: {r}")
     return r
+
+
+def run_scans(grid, log, n_paths=4096):
+    """Restrained scans of pah38 (one rim O atom held) on the small slab, every path a
+    replica: a relaxed detachment (held atom lifted from 1.3 to 20 A above the top plane in
+    0.1 A steps, FIRE to 1e-3 eV/A, at most 5000 moves per point) and a drag along the cell
+    diagonal at 3.3 A (0.1 A steps over one diagonal period, 5000 moves per point with a
+    force threshold of 0 so that every point takes all of them, the paper's timing
+    protocol).  Wall time of the whole scan (launches, refills, host loop)."""
+    import torch
+    from paper_2508_15522_amd import device as D, gridff as G, scans as SC, synth as S
+    mol = S.mol_pah38()
+    topo = G.Topology([mol])
+    plan = G.Plan(topo, np.zeros(n_paths, np.int32), block_threads=192)
+    sub = S.rocksalt_slab(2, 3)
+    start = list(S.f32(S.place_replicas(mol, n_paths, sub, S.SEED_PLACE * 7, h_range=(3.0, 3.5))))
+    held = np.full(n_paths, mol.elem.index("O"), np.int32)
+    out = {}
+    z = 1.3 + 0.1 * np.arange(188)
+    tg = SC.detachment_targets(start, held, z)
+    r = SC.restrained_scan(grid, topo, plan, start, held, tg, f_conv=1e-3, max_steps=5000, log=log)
+    moves = int(r["steps"].sum())
+    out["detachment"] = {"paths": n_paths, "points": len(z), "seconds": r["seconds"],
+                         "scan_points_per_s": n_paths * len(z) / r["seconds"], "replica_steps_per_s": moves / r["seconds"],
+                         "mean_moves_per_point": moves / (n_paths * len(z)),
+                         "converged_fraction": float(((r["status"] & G.REP_CONVERGED) != 0).mean())}
+    log(f"detachment scan: {out['detachment']}")
+    L = np.hypot(sub.Lx, sub.Ly) / 2                     # one period along the diagonal
+    npts = int(round(L / 0.1)) + 1
+    tg = SC.drag_targets(start, held, (1.0, 1.0), 0.1, npts, height=3.3)
+    r = SC.restrained_scan(grid, topo, plan, start, held, tg, f_conv=0.0, max_steps=5000, log=log)
+    moves = int(r["steps"].sum())
+    out["drag"] = {"paths": n_paths, "points": npts, "seconds": r["seconds"],
+                   "scan_points_per_s": n_paths * npts / r["seconds"], "replica_steps_per_s": moves / r["seconds"],
+                   "moves_per_point": moves / (n_paths * npts)}
+    log(f"drag scan: {out['drag']}")
+    out["workload"] = ("pah38 on the 2x2x3 slab (112x112x150 FP32 grid), 4096 paths, one rim O held: "
+                       "detachment 1.3-20 A (188 points, FIRE to 1e-3 eV/A, <= 5000 moves); drag along the "
+                       "diagonal at 3.3 A, 0.1 A steps, 5000 moves per point")
+    return out
 
 
 def run_direct(name, log):
