@@ -42,6 +42,7 @@ PINS = {
     "langevin_batch": "velocity Verlet at zero friction, exact BAOAB harmonic moments",
     "sampling.dedupe_energy": "hand-worked discovery-order cases",
     "sampling.rmsd_lattice": "lattice/continuous shift, rotation and permutation closed forms",
+    "trilinear_eval": "nodal values, exactness on multilinear fields, domain rules",
     "sampling.dedupe_rmsd": "hand-worked discovery-order chain, type, NaN and carried-archive cases",
 }
 
@@ -203,6 +204,36 @@ def bspline_eval(B, spec, pos, plq, chan=False):
                            bp, C.c_int(n), pp, qp, _nullable(E), _nullable(F),
                            fl.ctypes.data_as(C.POINTER(C.c_int)), _nullable(ch))
     return (E, F, fl, ch) if chan else (E, F, fl)
+
+
+def trilinear_nodes(B, spec):
+    """Nodal (E, Fx, Fy, Fz) per channel of the B-spline model B: [3][nx][ny][nz][4], the
+    table the trilinear scheme stores (energies and forces of the same model at the nodes)."""
+    nx, ny, nz = spec["nx"], spec["ny"], spec["nz"]
+    ii, jj, kk = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
+    pts = np.stack([spec["x0"] + ii * spec["dx"], spec["y0"] + jj * spec["dy"], spec["z0"] + kk * spec["dz"]],
+                   -1).reshape(-1, 3)
+    out = np.zeros((3, nx * ny * nz, 4))
+    for c in range(3):
+        plq = np.zeros((len(pts), 3)); plq[:, c] = 1.0
+        E, F, _ = bspline_eval(B, spec, pts, plq)
+        out[c, :, 0] = E; out[c, :, 1:] = F
+    return out.reshape(3, nx, ny, nz, 4)
+
+
+def trilinear_eval(N, spec, pos, plq):
+    """Trilinear interpolation of stored nodal (E, F) N[3][nx][ny][nz][4]: E (n,), F (n,3), flags."""
+    N, np_ = _d(N)
+    pos, pp = _d(pos)
+    plq, qp = _d(plq)
+    n = len(pos)
+    E, F, fl = np.zeros(n), np.zeros((n, 3)), np.zeros(n, np.int32)
+    lib().orc_trilinear_eval(C.c_int(spec["nx"]), C.c_int(spec["ny"]), C.c_int(spec["nz"]),
+                             C.c_double(spec["x0"]), C.c_double(spec["y0"]), C.c_double(spec["z0"]),
+                             C.c_double(spec["dx"]), C.c_double(spec["dy"]), C.c_double(spec["dz"]),
+                             np_, C.c_int(n), pp, qp, _nullable(E), _nullable(F),
+                             fl.ctypes.data_as(C.POINTER(C.c_int)))
+    return E, F, fl
 
 
 def mixing(eps, R, q, alpha=1.6):

@@ -469,6 +469,49 @@ double orc_intra(const orc_mol *m, const double *x, double *F, const unsigned ch
     return E;
 }
 
+/* Trilinear interpolation of stored nodal energies and forces, the earlier scheme the paper
+ * contrasts its B-splines with (Section "Interpolation": E, Fx, Fy, Fz stored and interpolated
+ * independently, so the force is not the gradient of the energy).  N[c][i][j][k][4] holds
+ * (E, Fx, Fy, Fz) of channel c at node (i, j, k).  Per point: u = (x - x0)/dx, i = floor(u)
+ * mod nx, t_x = u - floor(u) (same for y); w = (z - z0)/dz, below 0 evaluated at 0 with flag
+ * 2, above nz - 1 zero; k = min(floor(w), nz - 2), t_z = w - k.  Each of the 8 corners has
+ * weight prod (t or 1 - t); E = sum_c m_c E_c, F = sum_c m_c F_c with (m_c) = (P, L, Q). */
+void orc_trilinear_eval(int nx, int ny, int nz, double x0, double y0, double z0, double dx, double dy, double dz,
+                        const double *N, int n, const double *pos, const double *plq, double *E, double *F,
+                        int *flag)
+{
+    const size_t chan = (size_t)nx * ny * nz * 4;
+    #pragma omp parallel for schedule(static)
+    for (int p = 0; p < n; ++p) {
+        const double *r = pos + 3 * p, *m = plq + 3 * p;
+        int fl = 0;
+        double acc[4] = {0, 0, 0, 0};
+        if (!isfinite(r[0]) || !isfinite(r[1]) || !isfinite(r[2])) {
+            E[p] = NAN; F[3*p] = F[3*p+1] = F[3*p+2] = NAN; flag[p] = 4;
+            continue;
+        }
+        double u = (r[0] - x0) / dx, v = (r[1] - y0) / dy, w = (r[2] - z0) / dz;
+        if (w < 0) { w = 0; fl |= 2; }
+        if (w <= nz - 1) {
+            const double fu = floor(u), fv = floor(v);
+            double fw = floor(w);
+            if (fw > nz - 2) fw = nz - 2;
+            const double t[3] = {u - fu, v - fv, w - fw};
+            const long i0 = pmod((long)fu, nx), j0 = pmod((long)fv, ny), k0 = (long)fw;
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b)
+                    for (int c = 0; c < 2; ++c) {
+                        const double wt = (a ? t[0] : 1 - t[0]) * (b ? t[1] : 1 - t[1]) * (c ? t[2] : 1 - t[2]);
+                        const size_t node = ((size_t)pmod(i0 + a, nx) * ny + pmod(j0 + b, ny)) * nz + (k0 + c);
+                        for (int ch = 0; ch < 3; ++ch)
+                            for (int q = 0; q < 4; ++q) acc[q] += wt * m[ch] * N[ch * chan + 4 * node + q];
+                    }
+        }
+        E[p] = acc[0]; F[3*p] = acc[1]; F[3*p+1] = acc[2]; F[3*p+2] = acc[3];
+        flag[p] = fl;
+    }
+}
+
 /* ============================================================ whole-replica force */
 typedef struct {
     int nx, ny, nz; double x0, y0, z0, dx, dy, dz; const double *B;

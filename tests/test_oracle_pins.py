@@ -284,6 +284,67 @@ def test_intra_reference_geometry_bonded_terms_at_rest():
     assert abs(Ez) < 1e-9 and np.abs(Fz).max() < 1e-5
 
 
+# ------------------------------------------------------------------ trilinear E/F scheme
+def test_trilinear_reproduces_nodes_and_multilinear_fields():
+    """Trilinear interpolation returns the stored values at nodes and reproduces any field
+    that is linear in each coordinate separately (a + bx + cy + dz + exy + fyz + gxz + hxyz)
+    inside the lattice, for the energy and each force component independently."""
+    nx, ny, nz = 9, 8, 7
+    spec = dict(nx=nx, ny=ny, nz=nz, x0=0.5, y0=-0.3, z0=1.0, dx=0.3, dy=0.25, dz=0.2)
+    co = RNG.normal(size=(3, 4, 8))
+    ii, jj, kk = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
+    X = spec["x0"] + ii * spec["dx"]; Y = spec["y0"] + jj * spec["dy"]; Z = spec["z0"] + kk * spec["dz"]
+
+    def f(c, q, x, y, z):
+        a = co[c, q]
+        return a[0] + a[1] * x + a[2] * y + a[3] * z + a[4] * x * y + a[5] * y * z + a[6] * x * z + a[7] * x * y * z
+    N = np.zeros((3, nx, ny, nz, 4))
+    for c in range(3):
+        for q in range(4):
+            N[c, ..., q] = f(c, q, X, Y, Z)
+    plq = RNG.normal(size=(200, 3))
+    # interior points (away from the periodic wrap cell, where a non-periodic field jumps)
+    pts = np.stack([spec["x0"] + RNG.uniform(0, (nx - 1) * spec["dx"], 200),
+                    spec["y0"] + RNG.uniform(0, (ny - 1) * spec["dy"], 200),
+                    spec["z0"] + RNG.uniform(0, (nz - 1) * spec["dz"], 200)], 1)
+    E, F, fl = O.trilinear_eval(N, spec, pts, plq)
+    want = [sum(plq[:, c] * f(c, q, pts[:, 0], pts[:, 1], pts[:, 2]) for c in range(3)) for q in range(4)]
+    assert (fl == 0).all()
+    assert np.abs(E - want[0]).max() < 1e-12 and np.abs(F - np.stack(want[1:], 1)).max() < 1e-12
+    # at nodes: the stored values
+    idx = [(0, 0, 0), (3, 5, 5), (8, 7, 2)]
+    pn = np.array([[X[i], Y[i], Z[i]] for i in idx])
+    E, F, _ = O.trilinear_eval(N, spec, pn, np.tile([1.0, 0.0, 0.0], (3, 1)))
+    for r, i in enumerate(idx):
+        assert abs(E[r] - N[0][i][0]) < 1e-12 and np.abs(F[r] - N[0][i][1:]).max() < 1e-12
+    # domain: below z0 evaluated on the first plane and flagged; above the last plane zero
+    E1, _, f1 = O.trilinear_eval(N, spec, np.array([[0.7, 0.1, 0.5], [0.7, 0.1, 1.0]]), np.tile([1.0, 0, 0], (2, 1)))
+    assert f1[0] == 2 and f1[1] == 0 and E1[0] == E1[1]
+    E2, F2, f2 = O.trilinear_eval(N, spec, np.array([[0.7, 0.1, 2.21]]), np.array([[1.0, 1.0, 1.0]]))
+    assert E2[0] == 0 and (F2 == 0).all() and f2[0] == 0
+
+
+def test_trilinear_nodes_are_the_model_at_the_nodes():
+    """The stored table is the B-spline model's energy and force at each node, channel by
+    channel: between nodes the trilinear force then differs from minus the gradient of the
+    trilinear energy (the inconsistency the paper describes), while at nodes both agree with
+    the model."""
+    nx, ny, nz = 10, 10, 12
+    spec = dict(nx=nx, ny=ny, nz=nz, x0=0.0, y0=0.0, z0=1.0, dx=0.3, dy=0.3, dz=0.25)
+    B = O.fit_bspline(RNG.normal(size=(3, nx, ny, nz)))
+    N = O.trilinear_nodes(B, spec)
+    p = np.array([[0.9, 1.2, 1.0 + 5 * 0.25]])
+    for c in range(3):
+        m = np.zeros((1, 3)); m[0, c] = 1
+        E, F, _ = O.bspline_eval(B, spec, p, m)
+        assert abs(N[c, 3, 4, 5, 0] - E[0]) < 1e-12 and np.abs(N[c, 3, 4, 5, 1:] - F[0]).max() < 1e-12
+    q = np.array([[1.0, 1.3, 2.33]]); m = np.array([[0.3, -0.7, 1.1]]); h = 1e-6
+    _, Fq, _ = O.trilinear_eval(N, spec, q, m)
+    g = [(O.trilinear_eval(N, spec, q + h * e, m)[0][0] - O.trilinear_eval(N, spec, q - h * e, m)[0][0]) / (2 * h)
+         for e in np.eye(3)]
+    assert np.abs(Fq[0] + np.array(g)).max() > 1e-3
+
+
 # ------------------------------------------------------------------ P10: FIRE
 def _one_atom():
     return S.Molecule(name="atom", elem=["C"], pos=np.zeros((1, 3)), q=np.zeros(1), eps=np.array([0.0]),
