@@ -288,7 +288,7 @@ class _Grid(C.Structure):
     _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
                 ("x0", C.c_double), ("y0", C.c_double), ("z0", C.c_double),
                 ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
-                ("B", C.POINTER(C.c_double))]
+                ("B", C.POINTER(C.c_double)), ("N", C.POINTER(C.c_double))]
 
 
 class _Fire(C.Structure):
@@ -357,10 +357,14 @@ class TypesView:
 
 
 class GridView:
+    """B: B-spline coefficients [3][nx][ny][nz], or a trilinear nodal table [3][nx][ny][nz][4]
+    (trilinear_nodes), which the batch functions then interpolate instead."""
+
     def __init__(self, B, spec):
         self.B, bp = _d(B)
+        tri = self.B.ndim == 5
         self.s = _Grid(spec["nx"], spec["ny"], spec["nz"], spec["x0"], spec["y0"], spec["z0"],
-                       spec["dx"], spec["dy"], spec["dz"], bp)
+                       spec["dx"], spec["dy"], spec["dz"], None if tri else bp, bp if tri else None)
 
 
 def _batch_arrays(mols, rep_type):

@@ -515,10 +515,11 @@ void orc_trilinear_eval(int nx, int ny, int nz, double x0, double y0, double z0,
 /* ============================================================ whole-replica force */
 typedef struct {
     int nx, ny, nz; double x0, y0, z0, dx, dy, dz; const double *B;
+    const double *N;          /* if not NULL: trilinear nodal table [3][nx][ny][nz][4] instead of B */
 } orc_grid;
 
-/* Total energy and force of one replica: grid model (mixing with P_i, L_i, Q_i) plus the
- * intramolecular field if `intra`.  Returns status bits (2 out of domain, 4 non-finite). */
+/* Total energy and force of one replica: grid model (mixing with P_i, L_i, Q_i; B-spline,
+ * or the trilinear table when the grid carries one) plus the intramolecular field if `intra`.  Returns status bits (2 out of domain, 4 non-finite). */
 static int replica_force(const orc_grid *g, const orc_mol *m, const double *plq, int intra,
                          const unsigned char *ex, const double *x, double *F, double *E_out,
                          double *Eatom, double *Ftmp)
@@ -526,8 +527,12 @@ static int replica_force(const orc_grid *g, const orc_mol *m, const double *plq,
     int n = m->n, st = 0;
     int *fl = malloc(sizeof(int) * n);
     double *Ea = Eatom ? Eatom : malloc(sizeof(double) * n);
-    orc_bspline_eval(g->nx, g->ny, g->nz, g->x0, g->y0, g->z0, g->dx, g->dy, g->dz, g->B,
-                     n, x, plq, Ea, F, fl, NULL);
+    if (g->N)
+        orc_trilinear_eval(g->nx, g->ny, g->nz, g->x0, g->y0, g->z0, g->dx, g->dy, g->dz, g->N,
+                           n, x, plq, Ea, F, fl);
+    else
+        orc_bspline_eval(g->nx, g->ny, g->nz, g->x0, g->y0, g->z0, g->dx, g->dy, g->dz, g->B,
+                         n, x, plq, Ea, F, fl, NULL);
     double E = 0;
     for (int i = 0; i < n; ++i) { E += Ea[i]; st |= fl[i]; }
     if (intra) {

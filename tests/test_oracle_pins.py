@@ -343,6 +343,13 @@ def test_trilinear_nodes_are_the_model_at_the_nodes():
     g = [(O.trilinear_eval(N, spec, q + h * e, m)[0][0] - O.trilinear_eval(N, spec, q - h * e, m)[0][0]) / (2 * h)
          for e in np.eye(3)]
     assert np.abs(Fq[0] + np.array(g)).max() > 1e-3
+    # the replica functions take the table in place of the coefficients
+    mol = S.mol_chain24()
+    x = mol.pos * 0.2 + [1.5, 1.5, 2.5]
+    plq = O.mixing(mol.eps, mol.R, mol.q)
+    Fb, Er, Ea, st = O.eval_batch(N, spec, [mol], [0], x, intra_on=False)
+    Et, Ft, _ = O.trilinear_eval(N, spec, x, plq)
+    assert np.abs(Ea - Et).max() < 1e-14 and np.abs(Fb - Ft).max() < 1e-14
 
 
 # ------------------------------------------------------------------ P10: FIRE
