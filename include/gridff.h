@@ -52,7 +52,7 @@ typedef enum {
     GFF_ENOMEM = -5           /* allocation failed inside a create call */
 } gff_status;
 
-enum { GFF_STORE_F32 = 0, GFF_STORE_F16 = 1 };
+enum { GFF_STORE_F32 = 0, GFF_STORE_F16 = 1, GFF_STORE_TRILINEAR = 2 };
 
 /* per-replica status bits */
 enum {
@@ -120,6 +120,13 @@ gff_status gff_fit_bspline(const gff_grid_spec *spec, const double *d_V, double 
  * GFF_STORE_F32: float; GFF_STORE_F16: IEEE half of b / s_c (round to nearest even), with
  * per-channel scale s_c = 2^(ceil(log2 max|b_c|) - 15) written to d_scale[0..2]
  * (d_scale[3] = 0).  For F32, d_scale (if not NULL) receives 1,1,1,0.
+ * GFF_STORE_TRILINEAR, the earlier scheme the paper compares against (Section
+ * "Interpolation": energy and force stored per node and interpolated trilinearly, each on
+ * its own): tri[i][j][k][c] = float4 (E, dE/du, dE/dv, dE/dw) of channel c, the fitted
+ * model's value and gradient with respect to the node-index coordinates u = (x - x0)/dx,
+ * v, w at node (i, j, k), formed in FP64 from the coefficients (even-mirror rows at the z
+ * ends) and stored in FP32, 48 bytes per node (the evaluation scales the interpolated
+ * gradient by -1/dx, -1/dy, -1/dz into a force); d_scale as for F32.
  * d_coef: gff_grid_bytes(spec, storage) bytes. */
 size_t gff_grid_bytes(const gff_grid_spec *spec, int storage);
 gff_status gff_pack_grid(const gff_grid_spec *spec, const double *d_B, int storage,
@@ -129,9 +136,12 @@ gff_status gff_pack_grid(const gff_grid_spec *spec, const double *d_B, int stora
 
 /* A fitted, device-resident grid in the gff_pack_grid layout.  The lateral period is
  * nx*dx by ny*dy.  Coordinates below z0 are evaluated on the z0 plane (and flagged);
- * coordinates strictly above the last node z0 + (nz-1) dz contribute zero. */
+ * coordinates strictly above the last node z0 + (nz-1) dz contribute zero.  A
+ * GFF_STORE_TRILINEAR grid interpolates the stored nodal energy and force of each channel
+ * trilinearly in the cell, mixed with the atom's (P, L, Q); its force is therefore not the
+ * gradient of its energy. */
 typedef struct {
-    int storage;             /* GFF_STORE_F32 or GFF_STORE_F16 */
+    int storage;             /* GFF_STORE_F32, GFF_STORE_F16 or GFF_STORE_TRILINEAR */
     int nx, ny, nz;
     float x0, y0, z0, dx, dy, dz;
     const void *d_coef;

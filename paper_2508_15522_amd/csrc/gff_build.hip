@@ -270,6 +270,42 @@ __global__ void __launch_bounds__(256) k_pack(const double *B, int nx, int ny, i
     }
 }
 
+// Nodal value and index-space gradient of the fitted model for the trilinear scheme: per
+// node and channel E = sum b w_x w_y w_z and dE/du etc. over the 3x3x3 neighbourhood, with
+// the cubic B-spline's node weights (1/6, 2/3, 1/6) and derivative weights (-1/2, 0, 1/2);
+// x and y wrap, z rows beyond the ends mirror (node -1 -> 1, node nz -> nz-2).  FP64, stored
+// FP32.
+__global__ void __launch_bounds__(256) k_pack_tri(const double *B, int nx, int ny, int nz, float4 *out) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long)nx * ny * nz) return;
+    const int k = (int)(t % nz);
+    const long ij = t / nz;
+    const int j = (int)(ij % ny), i = (int)(ij / ny);
+    const double w[3] = {1.0 / 6.0, 2.0 / 3.0, 1.0 / 6.0}, d[3] = {-0.5, 0.0, 0.5};
+    const long plane = (long)nx * ny * nz;
+    double acc[3][4] = {};
+    for (int a = 0; a < 3; ++a) {
+        const int ii = (i + a - 1 + nx) % nx;
+        for (int b = 0; b < 3; ++b) {
+            const int jj = (j + b - 1 + ny) % ny;
+            for (int c = 0; c < 3; ++c) {
+                int kk = k + c - 1;
+                if (kk < 0) kk = -kk;
+                if (kk > nz - 1) kk = 2 * (nz - 1) - kk;
+                const long idx = ((long)ii * ny + jj) * nz + kk;
+                const double we = w[a] * w[b] * w[c];
+                const double gx = d[a] * w[b] * w[c], gy = w[a] * d[b] * w[c], gz = w[a] * w[b] * d[c];
+                for (int ch = 0; ch < 3; ++ch) {
+                    const double bb = B[ch * plane + idx];
+                    acc[ch][0] += we * bb; acc[ch][1] += gx * bb; acc[ch][2] += gy * bb; acc[ch][3] += gz * bb;
+                }
+            }
+        }
+    }
+    for (int ch = 0; ch < 3; ++ch)
+        out[3 * t + ch] = make_float4((float)acc[ch][0], (float)acc[ch][1], (float)acc[ch][2], (float)acc[ch][3]);
+}
+
 // ------------------------------------------------------------------ host helpers
 static bool spec_ok(const gff_grid_spec *s) {
     return s && s->nx >= 4 && s->ny >= 4 && s->nz >= 4 && s->dz > 0.0 &&
@@ -476,13 +512,15 @@ extern "C" size_t gff_grid_bytes(const gff_grid_spec *spec, int storage) {
     const size_t nodes = (size_t)spec->nx * spec->ny * (spec->nz + 3);
     if (storage == GFF_STORE_F32) return nodes * 4 * sizeof(float);
     if (storage == GFF_STORE_F16) return nodes * 4 * sizeof(uint16_t);
+    if (storage == GFF_STORE_TRILINEAR) return (size_t)spec->nx * spec->ny * spec->nz * 3 * sizeof(float4);
     return 0;
 }
 
 extern "C" gff_status gff_pack_grid(const gff_grid_spec *spec, const double *d_B, int storage, void *d_coef,
                                     float *d_scale, void *stream) {
     if (!spec_ok(spec) || !d_B || !d_coef) return GFF_EINVAL;
-    if (storage != GFF_STORE_F32 && storage != GFF_STORE_F16) return GFF_EUNSUPPORTED;
+    if (storage != GFF_STORE_F32 && storage != GFF_STORE_F16 && storage != GFF_STORE_TRILINEAR)
+        return GFF_EUNSUPPORTED;
     if (storage == GFF_STORE_F16 && !d_scale) return GFF_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     const long nodes = (long)spec->nx * spec->ny * (spec->nz + 3);
@@ -491,6 +529,11 @@ extern "C" gff_status gff_pack_grid(const gff_grid_spec *spec, const double *d_B
         if (d_scale) hipLaunchKernelGGL(k_scales_one, dim3(1), dim3(64), 0, s, d_scale);
         hipLaunchKernelGGL(k_pack<GFF_STORE_F32>, dim3(nb), dim3(256), 0, s, d_B, spec->nx, spec->ny, spec->nz,
                            (const float *)nullptr, d_coef);
+    } else if (storage == GFF_STORE_TRILINEAR) {
+        if (d_scale) hipLaunchKernelGGL(k_scales_one, dim3(1), dim3(64), 0, s, d_scale);
+        const long n3 = (long)spec->nx * spec->ny * spec->nz;
+        hipLaunchKernelGGL(k_pack_tri, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, s, d_B, spec->nx, spec->ny,
+                           spec->nz, static_cast<float4 *>(d_coef));
     } else {
         // the per-channel maxima are accumulated in the last 24 bytes of d_coef, which the
         // pack kernel overwrites afterwards (stream order: init, max, scales, pack)

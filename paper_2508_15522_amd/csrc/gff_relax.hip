@@ -20,7 +20,8 @@ namespace gff {
 
 enum { MODE_EVAL = 0, MODE_FIRE = 1, MODE_NVE = 2, MODE_LANGEVIN = 3 };
 // storage slot of the all-atom comparison mode (no grid: direct substrate sums)
-constexpr int STORE_DIRECT = 2;
+constexpr int STORE_DIRECT = 3;
+constexpr int STORE_TRI = GFF_STORE_TRILINEAR;
 
 struct DirectView {
     const float4 *xyza;        // substrate x, y, z, eps e^{2 alpha R}
@@ -182,6 +183,65 @@ __device__ __forceinline__ float grid_eval(const GridView &g, float x, float y, 
     }
     gx = Ex * g.idx; gy = Ey * g.idy; gz = Ez * g.idz;
     return E;
+}
+
+// ---- trilinear scheme (stored nodal value and index-space gradient per channel)
+struct TriKey {
+    int i, j, k;
+    float tx, ty, tz;
+    int state;                            // 0 in the grid, 1 above it (zero), 2 non-finite
+};
+
+// Cell and in-cell offsets with the domain rules of grid_eval; a point exactly on the last
+// plane uses the cell below it at offset 1.
+__device__ __forceinline__ TriKey tri_key(const GridView &g, float x, float y, float z, unsigned &fl) {
+    TriKey K{0, 0, 0, 0.f, 0.f, 0.f, 0};
+    if (!(__builtin_isfinite(x) && __builtin_isfinite(y) && __builtin_isfinite(z))) {
+        fl |= GFF_REP_NONFINITE;
+        K.state = 2;
+        return K;
+    }
+    const float qx = cell_split(x - g.x0, g.dx, g.idx, K.tx);
+    const float qy = cell_split(y - g.y0, g.dy, g.idy, K.ty);
+    float qz = cell_split(z - g.z0, g.dz, g.idz, K.tz);
+    if (qz < 0.f) { qz = 0.f; K.tz = 0.f; fl |= GFF_REP_OUT_OF_DOMAIN; }
+    if (qz > g.zmax || (qz == g.zmax && K.tz > 0.f)) { K.state = 1; return K; }
+    if (qz == g.zmax) { qz = g.zmax - 1.f; K.tz = 1.f; }
+    K.i = wrap_index(qx, g.nx); K.j = wrap_index(qy, g.ny); K.k = (int)qz;
+    return K;
+}
+
+__device__ __forceinline__ int tri_cell(const GridView &g, const TriKey &K) { return (K.i * g.ny + K.j) * g.nzp + K.k; }
+
+// The cell's 8 corners, each channel's (E, dE/du, dE/dv, dE/dw) mixed with (P, L, Q);
+// corner a*4 + b*2 + c is node (i+a, j+b, k+c).
+__device__ __forceinline__ void tri_load(const GridView &g, const TriKey &K, float P, float L, float Q, float4 q[8]) {
+    const float4 *T = reinterpret_cast<const float4 *>(g.coef);
+    const int i1 = K.i + 1 == g.nx ? 0 : K.i + 1, j1 = K.j + 1 == g.ny ? 0 : K.j + 1;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const size_t node = ((size_t)(a ? i1 : K.i) * g.ny + (b ? j1 : K.j)) * g.nzp + K.k + c;
+                const float4 c0 = T[3 * node], c1 = T[3 * node + 1], c2 = T[3 * node + 2];
+                q[4 * a + 2 * b + c] = make_float4(P * c0.x + L * c1.x + Q * c2.x, P * c0.y + L * c1.y + Q * c2.y,
+                                                   P * c0.z + L * c1.z + Q * c2.z, P * c0.w + L * c1.w + Q * c2.w);
+            }
+}
+
+// Trilinear weights on the 8 corners: energy and force (the stored gradient interpolated on
+// its own and scaled to a force).
+__device__ __forceinline__ float tri_interp(const GridView &g, const float4 q[8], const TriKey &K, float3 &F) {
+    float e = 0.f, gu = 0.f, gv = 0.f, gw = 0.f;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+        const float w = ((m & 4) ? K.tx : 1.f - K.tx) * ((m & 2) ? K.ty : 1.f - K.ty) * ((m & 1) ? K.tz : 1.f - K.tz);
+        e += w * q[m].x; gu += w * q[m].y; gv += w * q[m].z; gw += w * q[m].w;
+    }
+    F = make_float3(-gu * g.idx, -gv * g.idy, -gw * g.idz);
+    return e;
 }
 
 __device__ __forceinline__ float3 f3(const float4 &p) { return make_float3(p.x, p.y, p.z); }
@@ -529,7 +589,7 @@ k_replicas(KArgs A) {
     const int N = A.N;
     const int wl = tid & 63, wb = tid - wl, quad_s = wl & 3;
     GridView gv = A.g;
-    if constexpr (STORE != STORE_DIRECT) fetch_scales(gv);
+    if constexpr (STORE == GFF_STORE_F32 || STORE == GFF_STORE_F16) fetch_scales(gv);
 
     for (int pk = blockIdx.x; pk < A.n_packs; pk += gridDim.x) {
         const int4 pinfo = A.packs[pk];
@@ -582,6 +642,8 @@ k_replicas(KArgs A) {
         const bool reducer = rr < nrep;
         float cm[4][16];                        // cached pre-mixed stencil planes (CACHE)
         int cid[4] = {-1, -1, -1, -1};          // their stencil ids (-1: none)
+        float4 tq[8];                           // trilinear: the cell's pre-mixed corners
+        int tcid = -1;                          // their cell (CACHE; -1: none)
 
         const int total = (MODE == MODE_EVAL) ? 0 : A.n_steps;
         for (int it = 0; it <= total; ++it) {
@@ -620,6 +682,25 @@ k_replicas(KArgs A) {
                 } else {
                     e_grid = 0.f;
                     F = make_float3(0.f, 0.f, 0.f);
+                }
+            } else if constexpr (STORE == STORE_TRI) {
+                // per lane: the cell's 8 corners (kept across steps while the atom stays in
+                // the cell when CACHE), trilinear weights
+                e_grid = 0.f;
+                F = make_float3(0.f, 0.f, 0.f);
+                if (live) {
+                    unsigned fk = 0;
+                    const TriKey K = tri_key(gv, x.x, x.y, x.z, fk);
+                    fl |= fk;
+                    if (K.state == 2) {
+                        e_grid = __builtin_nanf("");
+                        F = make_float3(e_grid, e_grid, e_grid);
+                    } else if (K.state == 0) {
+                        const int cell = tri_cell(gv, K);
+                        if (!CACHE || cell != tcid) tri_load(gv, K, me.x, me.y, me.z, tq);
+                        tcid = cell;
+                        e_grid = tri_interp(gv, tq, K, F);
+                    }
                 }
             } else {
                 float4 t;
@@ -695,7 +776,7 @@ k_replicas(KArgs A) {
                         s_tres[2 * (lr * nt + q) + 1] = oB;
                     }
                     float fx = 0.f, fy = 0.f, fz = 0.f;
-                    if constexpr (CACHE) {
+                    if constexpr (CACHE && STORE != STORE_TRI) {
                         fx = pfx; fy = pfy; fz = pfz;
                         e_intra += 0.5f * pe;
                     } else {
@@ -868,19 +949,36 @@ __global__ void __launch_bounds__(256) k_points(GridView g, int n, const float *
                                                 float *F, float *E) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
-    fetch_scales(g);
     unsigned fl = 0;
-    float gx, gy, gz;
-    const float e = grid_eval<STORE>(g, pos[p], pos[p + n], pos[p + 2 * n], plq[p], plq[p + n], plq[p + 2 * n],
-                                     gx, gy, gz, fl);
-    F[p] = -gx; F[p + n] = -gy; F[p + 2 * n] = -gz;
-    if (E) E[p] = e;
+    if constexpr (STORE == STORE_TRI) {
+        const TriKey K = tri_key(g, pos[p], pos[p + n], pos[p + 2 * n], fl);
+        float e = 0.f;
+        float3 f = make_float3(0.f, 0.f, 0.f);
+        if (K.state == 2) {
+            e = __builtin_nanf("");
+            f = make_float3(e, e, e);
+        } else if (K.state == 0) {
+            float4 q[8];
+            tri_load(g, K, plq[p], plq[p + n], plq[p + 2 * n], q);
+            e = tri_interp(g, q, K, f);
+        }
+        F[p] = f.x; F[p + n] = f.y; F[p + 2 * n] = f.z;
+        if (E) E[p] = e;
+    } else {
+        fetch_scales(g);
+        float gx, gy, gz;
+        const float e = grid_eval<STORE>(g, pos[p], pos[p + n], pos[p + 2 * n], plq[p], plq[p + n],
+                                         plq[p + 2 * n], gx, gy, gz, fl);
+        F[p] = -gx; F[p + n] = -gy; F[p + 2 * n] = -gz;
+        if (E) E[p] = e;
+    }
 }
 
 // ------------------------------------------------------------------ host side
 static gff_status make_view(const gff_grid *gr, GridView &g) {
     if (!gr || !gr->d_coef) return GFF_EINVAL;
-    if (gr->storage != GFF_STORE_F32 && gr->storage != GFF_STORE_F16) return GFF_EUNSUPPORTED;
+    if (gr->storage != GFF_STORE_F32 && gr->storage != GFF_STORE_F16 && gr->storage != STORE_TRI)
+        return GFF_EUNSUPPORTED;
     if (gr->nx < 4 || gr->ny < 4 || gr->nz < 4) return GFF_EINVAL;
     if (!(gr->dx > 0.f && gr->dy > 0.f && gr->dz > 0.f)) return GFF_EINVAL;
     g.coef = gr->d_coef;
@@ -889,6 +987,14 @@ static gff_status make_view(const gff_grid *gr, GridView &g) {
     g.dx = gr->dx; g.dy = gr->dy; g.dz = gr->dz;
     g.zmax = (float)(gr->nz - 1);
     g.nx = gr->nx; g.ny = gr->ny; g.nzp = gr->nz + 3;
+    if (gr->storage == STORE_TRI) {      // unpadded nodes, plain global loads (64-bit addressing)
+        g.nzp = gr->nz;
+        if ((double)gr->nx * gr->ny * gr->nz >= 2147483647.0) return GFF_EUNSUPPORTED;   // 32-bit cell ids
+        g.bytes = 0;
+        g.s0 = g.s1 = g.s2 = 1.f;
+        g.scale = nullptr;
+        return GFF_OK;
+    }
     const double bytes = (double)gr->nx * gr->ny * (gr->nz + 3) * (gr->storage == GFF_STORE_F32 ? 16 : 8);
     if (bytes >= 2147483647.0) return GFF_EUNSUPPORTED;    // 32-bit buffer offsets
     g.bytes = (unsigned)bytes;
@@ -931,6 +1037,9 @@ static gff_status launch_mode(int storage, const gff_plan *plan, KArgs &A, hipSt
     const bool cache = can_cache && BT <= 512;
     if (storage == STORE_DIRECT) {
         launch_one<STORE_DIRECT, MODE, false>(grid, BT, lds, A, s);
+    } else if (storage == STORE_TRI) {
+        if (cache) launch_one<STORE_TRI, MODE, can_cache>(grid, BT, lds, A, s);
+        else launch_one<STORE_TRI, MODE, false>(grid, BT, lds, A, s);
     } else if (storage == GFF_STORE_F32) {
         if (cache) launch_one<GFF_STORE_F32, MODE, can_cache>(grid, BT, lds, A, s);
         else launch_one<GFF_STORE_F32, MODE, false>(grid, BT, lds, A, s);
@@ -951,6 +1060,9 @@ template <int MODE>
 static gff_status occupancy_mode(int storage, int BT, size_t lds, int *blocks) {
     constexpr bool can_cache = MODE != MODE_EVAL;
     const bool cache = can_cache && BT <= 512;
+    if (storage == STORE_TRI)
+        return cache ? occupancy_one<STORE_TRI, MODE, can_cache>(BT, lds, blocks)
+                     : occupancy_one<STORE_TRI, MODE, false>(BT, lds, blocks);
     if (storage == GFF_STORE_F32)
         return cache ? occupancy_one<GFF_STORE_F32, MODE, can_cache>(BT, lds, blocks)
                      : occupancy_one<GFF_STORE_F32, MODE, false>(BT, lds, blocks);
@@ -965,7 +1077,8 @@ using namespace gff;
 extern "C" gff_status gff_relax_occupancy(const gff_grid *grid, const gff_plan *plan, int mode, int *blocks_per_cu,
                                           size_t *lds_bytes_out) {
     if (!grid || !plan || !blocks_per_cu) return GFF_EINVAL;
-    if (grid->storage != GFF_STORE_F32 && grid->storage != GFF_STORE_F16) return GFF_EUNSUPPORTED;
+    if (grid->storage != GFF_STORE_F32 && grid->storage != GFF_STORE_F16 && grid->storage != STORE_TRI)
+        return GFF_EUNSUPPORTED;
     const int BT = plan->block_threads;
     const size_t lds = replica_lds_bytes(BT, plan->tres_max, plan->max_pack_reps, plan->topo_words);
     if (lds_bytes_out) *lds_bytes_out = lds;
@@ -1130,6 +1243,8 @@ extern "C" gff_status gff_interp_points(const gff_grid *grid, int n, const float
     const int blocks = (n + 255) / 256;
     if (grid->storage == GFF_STORE_F32)
         hipLaunchKernelGGL(k_points<GFF_STORE_F32>, dim3(blocks), dim3(256), 0, s, g, n, d_pos, d_plq, d_F, d_E);
+    else if (grid->storage == STORE_TRI)
+        hipLaunchKernelGGL(k_points<STORE_TRI>, dim3(blocks), dim3(256), 0, s, g, n, d_pos, d_plq, d_F, d_E);
     else
         hipLaunchKernelGGL(k_points<GFF_STORE_F16>, dim3(blocks), dim3(256), 0, s, g, n, d_pos, d_plq, d_F, d_E);
     return hip_status(hipGetLastError());

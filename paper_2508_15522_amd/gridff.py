@@ -14,7 +14,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgridff.so")
 
-STORE_F32, STORE_F16 = 0, 1
+STORE_F32, STORE_F16, STORE_TRILINEAR = 0, 1, 2
 MODE_FIRE, MODE_NVE, MODE_LANGEVIN = 0, 1, 2
 K_B = 8.617333262e-5                    # Boltzmann constant [eV/K]
 REP_CONVERGED, REP_OUT_OF_DOMAIN, REP_NONFINITE, REP_MAXSTEPS = 1, 2, 4, 8
