@@ -98,6 +98,8 @@ def main():
                     help="block threads (192: five 38-atom replicas fill 190 of 192 lanes; the fastest of a "
                          "64..448 sweep)")
     ap.add_argument("--compare-f16", action="store_true", help="also time the FP16-grid variant")
+    ap.add_argument("--compare-trilinear", action="store_true",
+                    help="also time the trilinear energy/force storage (the earlier scheme) and its NVE drift")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--minima", action="store_true", help="learned vs uniform proposals: minima found per second")
@@ -227,6 +229,16 @@ def main():
         res["f16_value"] = rs * args.steps / w16
         res["f16_kernel_avg_s"] = float(np.mean(p16))
         res["f16_vs_f32"] = res["f16_value"] / value
+    if args.compare_trilinear and args.storage == "f32":
+        gtri = setup(G.STORE_TRILINEAR)
+        wt, pt, _ = timed(gtri, args.steps, 1)
+        res["trilinear_value"] = rs * args.steps / wt
+        res["trilinear_kernel_avg_s"] = float(np.mean(pt))
+        res["trilinear_vs_bspline"] = res["trilinear_value"] / value
+        drift_t = float(out["drift"].cpu().numpy()[:, 2].max())
+        res["trilinear_max_abs_drift_eV"] = drift_t
+        log(f"trilinear storage: {res['trilinear_value']:.3e} replica-steps/s "
+            f"({res['trilinear_vs_bspline']:.2f}x the B-spline), drift {drift_t}")
     if args.minima:
         from paper_2508_15522_amd import sampling as SM
         log("learned vs uniform proposals (minima found per second)")
