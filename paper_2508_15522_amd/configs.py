@@ -23,15 +23,22 @@ class GridCfg:
     dz: float = 0.1
     alpha: float = synth.ALPHA
     rcut: float = 17.0
+    vacancy: tuple = ()        # (i, j, plane) sites removed from the slab
 
     def substrate(self):
-        return synth.rocksalt_slab(self.n_cells, self.n_planes)
+        return synth.rocksalt_slab(self.n_cells, self.n_planes, vacancy=list(self.vacancy))
 
 
 # 2x2 conventional cells, 3 atomic planes (48 atoms), 112 x 112 x 150 nodes
 GRID_SMALL = GridCfg(2, 3, 112, 112, 150)
 # 8x8 conventional cells, 12 atomic planes (3072 atoms), 452 x 452 x 200 nodes
 GRID_LARGE = GridCfg(8, 12, 452, 452, 200)
+# a neutral point defect in a large supercell (the paper's dragging-over-a-defect case):
+# 20x20 conventional cells, 3 planes, one adjacent cation-anion pair removed from the top
+# plane at the cell centre (4798 atoms); 1128 x 1128 x 80 nodes (112.8 x 112.8 x 7.9 A,
+# 1.69 GB in FP32), and the same supercell without the defect
+GRID_DEFECT = GridCfg(20, 3, 1128, 1128, 80, vacancy=((20, 20, 0), (21, 20, 0)))
+GRID_DEFECT_PRISTINE = GridCfg(20, 3, 1128, 1128, 80)
 
 
 @dataclass(frozen=True)
