@@ -338,7 +338,8 @@ def run_scans(grid, log, n_paths=4096):
     0.1 A steps, FIRE to 1e-3 eV/A, at most 5000 moves per point) and a drag along the cell
     diagonal at 3.3 A (0.1 A steps over one diagonal period, 5000 moves per point with a
     force threshold of 0 so that every point takes all of them, the paper's timing
-    protocol).  Wall time of the whole scan (launches, refills, host loop)."""
+    protocol).  Each scan is one fused launch (gff_relax_scan); the detachment is also run
+    point by point (one launch per point) for comparison.  Wall time of the whole scan."""
     import torch
     from paper_2508_15522_amd import device as D, gridff as G, scans as SC, synth as S
     mol = S.mol_pah38()
@@ -350,17 +351,18 @@ def run_scans(grid, log, n_paths=4096):
     out = {}
     z = 1.3 + 0.1 * np.arange(188)
     tg = SC.detachment_targets(start, held, z)
-    r = SC.restrained_scan(grid, topo, plan, start, held, tg, f_conv=1e-3, max_steps=5000, log=log)
-    moves = int(r["steps"].sum())
-    out["detachment"] = {"paths": n_paths, "points": len(z), "seconds": r["seconds"],
-                         "scan_points_per_s": n_paths * len(z) / r["seconds"], "replica_steps_per_s": moves / r["seconds"],
-                         "mean_moves_per_point": moves / (n_paths * len(z)),
-                         "converged_fraction": float(((r["status"] & G.REP_CONVERGED) != 0).mean())}
-    log(f"detachment scan: {out['detachment']}")
+    for name, fn in (("detachment", SC.restrained_scan_fused), ("detachment_point_by_point", SC.restrained_scan)):
+        r = fn(grid, topo, plan, start, held, tg, f_conv=1e-3, max_steps=5000)
+        moves = int(r["steps"].sum())
+        out[name] = {"paths": n_paths, "points": len(z), "seconds": r["seconds"],
+                     "scan_points_per_s": n_paths * len(z) / r["seconds"], "replica_steps_per_s": moves / r["seconds"],
+                     "mean_moves_per_point": moves / (n_paths * len(z)),
+                     "converged_fraction": float(((r["status"] & G.REP_CONVERGED) != 0).mean())}
+        log(f"{name} scan: {out[name]}")
     L = np.hypot(sub.Lx, sub.Ly) / 2                     # one period along the diagonal
     npts = int(round(L / 0.1)) + 1
     tg = SC.drag_targets(start, held, (1.0, 1.0), 0.1, npts, height=3.3)
-    r = SC.restrained_scan(grid, topo, plan, start, held, tg, f_conv=0.0, max_steps=5000, log=log)
+    r = SC.restrained_scan_fused(grid, topo, plan, start, held, tg, f_conv=0.0, max_steps=5000)
     moves = int(r["steps"].sum())
     out["drag"] = {"paths": n_paths, "points": npts, "seconds": r["seconds"],
                    "scan_points_per_s": n_paths * npts / r["seconds"], "replica_steps_per_s": moves / r["seconds"],
@@ -409,7 +411,7 @@ def run_defect(log, n_paths=512, n_points=200):
         grid = D.build_physical_grid(sub, spec, G.STORE_F32)
         torch.cuda.synchronize()
         bsec = time.time() - t0
-        r = SC.restrained_scan(grid, topo, plan, start, held, tg, f_conv=1e-3, max_steps=2000)
+        r = SC.restrained_scan_fused(grid, topo, plan, start, held, tg, f_conv=1e-3, max_steps=2000)
         E[name] = r["E"]
         moves = int(r["steps"].sum())
         out[name] = {"substrate_atoms": sub.n, "grid": f"{spec.nx}x{spec.ny}x{spec.nz}x3 f32",

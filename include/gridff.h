@@ -276,6 +276,27 @@ gff_status gff_relax_batch(const gff_grid *grid, const gff_topology *topo, const
                            double *d_E_rep, float *d_fnorm_rep, int *d_steps_rep,
                            double *d_drift_rep, void *stream);
 
+/* A whole restrained scan in one launch (Sections "Relaxed detachment" and "Dragging": the
+ * held atom moved point by point, the rest relaxed at each point, continuing from the
+ * previous point).  FIRE only (params->mode == GFF_MODE_FIRE; params->n_steps is ignored);
+ * state->d_fixed_atom names each replica's held atom (state->d_fixed_pos is not used).  Per
+ * replica r the held atom is placed at d_path[r][p] (float [n_rep][n_points][3]) for
+ * p = 0 .. n_points-1; at each point FIRE runs until |F|_2 < f_conv or moves_per_point moves,
+ * then the point's energy (FP32 sum over the replica's atoms), move count, status
+ * (GFF_REP_CONVERGED or GFF_REP_MAXSTEPS) and optionally all positions are recorded and FIRE
+ * restarts for the next point (velocities 0, dt = dt0, alpha = fire_alpha0, count 0).  Each
+ * replica advances on its own, so a launch costs the slowest replica's total moves rather
+ * than the sum over points of each point's slowest replica.  The trajectory of every replica
+ * is that of one gff_relax_batch launch per point with a gff_refill restart in between.
+ * Outputs: d_E_points [n_rep][n_points] (FP64 holding the FP32 sums), d_steps_points and
+ * d_status_points [n_rep][n_points] (nullable), d_pos_points [n_points][3][N] (nullable),
+ * and as gff_relax_batch the final state, d_E_rep, d_fnorm_rep, d_steps_rep (total moves). */
+gff_status gff_relax_scan(const gff_grid *grid, const gff_topology *topo, const gff_plan *plan,
+                          const gff_relax_params *params, const gff_state *state, const float *d_path, int n_points,
+                          int moves_per_point, float dt0, double *d_E_points, int *d_steps_points,
+                          unsigned *d_status_points, float *d_pos_points, double *d_E_rep, float *d_fnorm_rep,
+                          int *d_steps_rep, void *stream);
+
 /* ------------------------------------------------------------------ all-atom comparison mode */
 
 /* The all-atom molecule-substrate evaluation that the paper compares GridFF with (Section

@@ -62,6 +62,12 @@ struct KArgs {
     unsigned seed_lo, seed_hi, round;   // Langevin: Philox key and fourth counter word
     const int *fixed_atom;              // FIRE restraint: held atom per replica (nullable)
     const float *fixed_pos;             // its position [n_rep][3]
+    // FIRE scan (nullable path): the held atom visits path[rep][p] for p = 0 .. n_points-1,
+    // each point relaxed to f_conv or mpp moves, then FIRE restarts (dt0, alpha0) at the next
+    const float *path;
+    int n_points, mpp;
+    float dt0;
+    double *E_pts; int *steps_pts; unsigned *st_pts; float *pos_pts;
     DirectView d;                       // all-atom comparison mode only
 };
 
@@ -617,7 +623,8 @@ k_replicas(KArgs A) {
             if (MODE == MODE_FIRE) { fdt = A.fdt[rep]; fal = A.falpha[rep]; fnp = A.fnpos[rep]; }
             if (MODE == MODE_FIRE && A.fixed_atom != nullptr && A.fixed_atom[rep] == at) {
                 held = true;
-                x = make_float3(A.fixed_pos[3 * rep], A.fixed_pos[3 * rep + 1], A.fixed_pos[3 * rep + 2]);
+                const float *tp = A.path ? A.path + 3 * (size_t)rep * A.n_points : A.fixed_pos + 3 * rep;
+                x = make_float3(tp[0], tp[1], tp[2]);
                 v = make_float3(0.f, 0.f, 0.f);
             }
         }
@@ -633,6 +640,7 @@ k_replicas(KArgs A) {
         float3 F = make_float3(0.f, 0.f, 0.f);
         float e_atom = 0.f, e_grid = 0.f, fnorm = 0.f;
         int steps = 0;
+        int pt = 0, spt = 0;             // scan: current point, moves made at it
         const bool entered_conv = (st & GFF_REP_CONVERGED) != 0;
         bool live = active && !(st & GFF_REP_NONFINITE);
         // per-replica sums: a quad of reducer lanes per replica (lane q adds atoms q, q+4, ...,
@@ -812,30 +820,57 @@ k_replicas(KArgs A) {
             if (MODE == MODE_EVAL) break;
 
             if (MODE == MODE_FIRE) {
-                s_red[tid] = make_float4(dot(F, F), dot(F, v), dot(v, v), 0.f);
+                const bool scan = A.path != nullptr;
+                s_red[tid] = make_float4(dot(F, F), dot(F, v), dot(v, v), scan ? e_atom : 0.f);
                 lds_sync();                                      // C: partials visible
                 if (reducer) {                                   // reducer lanes of replica rr
-                    float ff = 0.f, fv = 0.f, vv = 0.f;
+                    float ff = 0.f, fv = 0.f, vv = 0.f, ee = 0.f;
 #pragma unroll 4
                     for (int j = rq; j < n; j += RL) {
                         const float4 r = s_red[rr * n + j];
-                        ff += r.x; fv += r.y; vv += r.z;
+                        ff += r.x; fv += r.y; vv += r.z; ee += r.w;
                     }
-                    if (RL == 4) { ff = quad_sum(ff); fv = quad_sum(fv); vv = quad_sum(vv); }
-                    if (rq == 0) s_sum[rr] = make_float4(ff, fv, vv, 0.f);
+                    if (RL == 4) { ff = quad_sum(ff); fv = quad_sum(fv); vv = quad_sum(vv); ee = quad_sum(ee); }
+                    if (rq == 0) s_sum[rr] = make_float4(ff, fv, vv, ee);
                 }
                 lds_sync();                                      // D: sums visible
                 if (live) {
                     const float4 sm = s_sum[lr];
                     const float ff = sm.x, fv = sm.y, vv = sm.z;
                     fnorm = sqrtf(ff);
+                    const bool conv = fnorm < A.f_conv;
                     if (!__builtin_isfinite(ff) || !__builtin_isfinite(fv) || !__builtin_isfinite(vv)) {
                         st |= GFF_REP_NONFINITE; live = false;
                     } else if (entered_conv) {
                         live = false;
-                    } else if (fnorm < A.f_conv) {
+                    } else if (scan && (conv || spt >= A.mpp)) {
+                        // the point is done: record it, then restart FIRE at the next point
+                        const size_t o = (size_t)rep * A.n_points + pt;
+                        if (at == 0) {
+                            A.E_pts[o] = (double)sm.w;
+                            if (A.steps_pts) A.steps_pts[o] = spt;
+                            if (A.st_pts) A.st_pts[o] = conv ? GFF_REP_CONVERGED : GFF_REP_MAXSTEPS;
+                        }
+                        if (A.pos_pts) {
+                            const size_t N3 = 3 * (size_t)N;
+                            A.pos_pts[pt * N3 + g] = x.x; A.pos_pts[pt * N3 + g + N] = x.y;
+                            A.pos_pts[pt * N3 + g + 2 * N] = x.z;
+                        }
+                        ++pt; spt = 0;
+                        if (pt == A.n_points) {
+                            if (conv) st |= GFF_REP_CONVERGED;
+                            live = false;
+                        } else {
+                            v = make_float3(0.f, 0.f, 0.f);
+                            fdt = A.dt0; fal = A.a0; fnp = 0;
+                            if (held) {
+                                const float *tp = A.path + 3 * ((size_t)rep * A.n_points + pt);
+                                x = make_float3(tp[0], tp[1], tp[2]);
+                            }
+                        }
+                    } else if (!scan && conv) {
                         st |= GFF_REP_CONVERGED; live = false;
-                    } else if (it < total) {
+                    } else if (scan || it < total) {
                         float a = fal, dt = fdt;
                         const float vn = sqrtf(vv);
                         const float mix = a * vn / fnorm;
@@ -853,7 +888,7 @@ k_replicas(KArgs A) {
                         if (l2 > A.max_disp * A.max_disp) d = (A.max_disp * __builtin_amdgcn_rsqf(l2)) * d;
                         x = x + d;
                         fdt = dt; fal = a;
-                        steps++;
+                        steps++; spt++;
                     } else {
                         live = false;
                     }
@@ -1138,6 +1173,31 @@ static gff_status relax_common(int storage, KArgs &A, const gff_topology *topo, 
     if (p->mode == GFF_MODE_FIRE) return launch_mode<MODE_FIRE>(storage, plan, A, s);
     if (p->mode == GFF_MODE_LANGEVIN) return launch_mode<MODE_LANGEVIN>(storage, plan, A, s);
     return launch_mode<MODE_NVE>(storage, plan, A, s);
+}
+
+extern "C" gff_status gff_relax_scan(const gff_grid *grid, const gff_topology *topo, const gff_plan *plan,
+                                     const gff_relax_params *p, const gff_state *state, const float *d_path,
+                                     int n_points, int moves_per_point, float dt0, double *d_E_points,
+                                     int *d_steps_points, unsigned *d_status_points, float *d_pos_points,
+                                     double *d_E_rep, float *d_fnorm_rep, int *d_steps_rep, void *stream) {
+    if (!p || p->mode != GFF_MODE_FIRE || !d_path || n_points < 1 || moves_per_point < 0 || !d_E_points ||
+        !(dt0 > 0.f))
+        return GFF_EINVAL;
+    if ((long)n_points * ((long)moves_per_point + 1) >= 2147483647L) return GFF_EINVAL;
+    if (!state || !state->d_fixed_atom) return GFF_EINVAL;       // the scanned atom
+    gff_relax_params q = *p;
+    q.n_steps = n_points * (moves_per_point + 1);
+    gff_state t = *state;
+    t.d_fixed_pos = d_path;                                     // satisfies the restraint check
+    gff_status rc = relax_check(topo, plan, &q, &t, nullptr);
+    if (rc != GFF_OK) return rc;
+    KArgs A;
+    std::memset(&A, 0, sizeof(A));
+    if ((rc = make_view(grid, A.g)) != GFF_OK) return rc;
+    A.path = d_path; A.n_points = n_points; A.mpp = moves_per_point; A.dt0 = dt0;
+    A.E_pts = d_E_points; A.steps_pts = d_steps_points; A.st_pts = d_status_points; A.pos_pts = d_pos_points;
+    return relax_common(grid->storage, A, topo, plan, &q, &t, d_E_rep, d_fnorm_rep, d_steps_rep, nullptr,
+                        (hipStream_t)stream);
 }
 
 static gff_status direct_view(const gff_direct *d, const gff_topology *topo, DirectView &v) {

@@ -268,6 +268,19 @@ def relax_batch(grid_desc, topo, plan, params, st, d_E_rep, d_fnorm, d_steps, d_
                                 _ptr(d_E_rep), _ptr(d_fnorm), _ptr(d_steps), _ptr(d_drift), _stream(stream)))
 
 
+EXPORTS += ["gff_relax_scan"]
+
+
+def relax_scan(grid_desc, topo, plan, params, st, d_path, n_points, moves_per_point, dt0, d_E_points,
+               d_steps_points=None, d_status_points=None, d_pos_points=None, d_E_rep=None, d_fnorm=None, d_steps=None,
+               stream=None):
+    """A whole restrained scan in one FIRE launch; st as for relax_batch with fixed_atom."""
+    check(lib().gff_relax_scan(C.byref(grid_desc), topo.handle, plan.handle, C.byref(params), C.byref(_state(st)),
+                               _ptr(d_path), C.c_int(n_points), C.c_int(moves_per_point), C.c_float(dt0),
+                               _ptr(d_E_points), _ptr(d_steps_points), _ptr(d_status_points), _ptr(d_pos_points),
+                               _ptr(d_E_rep), _ptr(d_fnorm), _ptr(d_steps), _stream(stream)))
+
+
 # ------------------------------------------------------------------ all-atom comparison mode
 EXPORTS += ["gff_direct_create", "gff_direct_destroy", "gff_eval_forces_direct", "gff_relax_batch_direct"]
 

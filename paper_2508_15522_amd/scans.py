@@ -10,6 +10,8 @@ a time.  Here every scan point (rigid scans) or every path (restrained scans) is
   held atom of every path is placed at its k-th target and the rest of the molecule relaxes
   with FIRE from the configuration of point k-1 (the continuation the paper's scans use),
   all paths in one launch per point.
+* restrained_scan_fused: the same scans in one launch, each path advancing to its next point
+  as soon as the current one is relaxed.
 """
 from __future__ import annotations
 
@@ -35,6 +37,34 @@ def rigid_scan(grid, topo, mol_type, base_pos, offsets, include_intra=False, blo
     G.eval_forces(grid.desc, topo, plan, include_intra, pos, F, None, E, st)
     torch.cuda.synchronize()
     return E.cpu().numpy(), st.cpu().numpy()
+
+
+def restrained_scan_fused(grid, topo, plan, start_pos, held_atom, targets, f_conv=1e-3, max_steps=5000,
+                          keep_pos=False, dt0=0.05):
+    """The same scan as restrained_scan in a single launch (gff_relax_scan): every replica
+    advances to its next point as soon as the current one is relaxed.  Same returns, with the
+    per-point energies as FP32 sums."""
+    n = plan.n_rep
+    targets = np.asarray(targets, np.float32)
+    n_pts = targets.shape[1]
+    st = D.fire_state(plan, start_pos, dt0=dt0)
+    st["fixed_atom"] = torch.from_numpy(np.ascontiguousarray(held_atom, np.int32)).cuda()
+    path = torch.from_numpy(np.ascontiguousarray(targets)).cuda()                      # [n_rep][n_points][3]
+    E = torch.empty(n, n_pts, dtype=torch.float64, device="cuda")
+    steps = torch.empty(n, n_pts, dtype=torch.int32, device="cuda")
+    status = torch.empty(n, n_pts, dtype=torch.int32, device="cuda")
+    pos = torch.empty(n_pts, 3, plan.n_atoms, device="cuda") if keep_pos else None
+    out = D.outputs(plan)
+    prm = G.relax_params(G.MODE_FIRE, 0, True, f_conv=f_conv)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    G.relax_scan(grid.desc, topo, plan, prm, st, path, n_pts, max_steps, dt0, E, steps, status, pos, out["E"],
+                 out["fnorm"], out["steps"])
+    torch.cuda.synchronize()
+    res = dict(E=E.cpu().numpy(), steps=steps.cpu().numpy(), status=status.cpu().numpy(), seconds=time.time() - t0)
+    if keep_pos:
+        res["pos"] = [pos[k] for k in range(n_pts)]
+    return res
 
 
 def restrained_scan(grid, topo, plan, start_pos, held_atom, targets, f_conv=1e-3, max_steps=5000, keep_pos=False,

@@ -115,3 +115,38 @@ def test_restrained_scan_follows_oracle(world):
         xr = D.unsoa(plan, res["pos"][k])
         for r in range(n):
             assert np.array_equal(xr[r][5].astype(np.float32), tg[r, k].astype(np.float32))
+
+
+def test_fused_scan_equals_point_by_point_launches(world):
+    """gff_relax_scan (every replica advancing to its next point on its own inside one
+    launch) against one launch per point with a FIRE restart in between: bit-identical
+    positions after every point, identical move counts and flags, energies equal to the
+    FP32 summation order (the fused scan sums each point's energy in FP32)."""
+    w = world
+    announce("fused scan vs point-by-point launches")
+    rng = np.random.default_rng(21)
+    rep_type = rng.integers(0, len(w["mols"]), 36)
+    plan = G.Plan(w["topo"], rep_type, block_threads=256)
+    # starts near minima (600 free FIRE moves), so that the points relax in tens of moves
+    st = D.fire_state(plan, _positions(w, rep_type, 6700))
+    out = D.outputs(plan)
+    G.relax_batch(w["grid"].desc, w["topo"], plan, G.relax_params(G.MODE_FIRE, 600, True, f_conv=1e-3), st,
+                  out["E"], out["fnorm"], out["steps"])
+    pos = D.unsoa(plan, st["pos"])
+    nat = np.array([w["mols"][t].n for t in rep_type])
+    held = rng.integers(0, nat).astype(np.int32)
+    lift = np.array([0.0, 0.15, 0.3, 0.45, 0.6])
+    tg = S.f32(np.array([[pos[r][held[r]] + [0.05 * k, 0.0, dz] for k, dz in enumerate(lift)]
+                         for r in range(len(rep_type))]))
+    a = SC.restrained_scan(w["grid"], w["topo"], plan, pos, held, tg, f_conv=5e-2, max_steps=60, keep_pos=True)
+    b = SC.restrained_scan_fused(w["grid"], w["topo"], plan, pos, held, tg, f_conv=5e-2, max_steps=60,
+                                 keep_pos=True)
+    conv = (a["status"] & G.REP_CONVERGED) != 0
+    announce(f"  converged points {int(conv.sum())}/{conv.size}, moves per point {a['steps'].min()}..{a['steps'].max()}; "
+             f"wall {a['seconds']:.3f} s point by point, {b['seconds']:.3f} s fused")
+    assert 0 < conv.sum() < conv.size                    # replicas advance at different moves
+    assert np.array_equal(a["steps"], b["steps"])
+    assert np.array_equal(a["status"] & (G.REP_CONVERGED | G.REP_MAXSTEPS), b["status"])
+    for k in range(len(lift)):
+        assert torch.equal(a["pos"][k], b["pos"][k]), k
+    assert (np.abs(a["E"] - b["E"]) < 2e-5 * nat[:, None] + 1e-6 * np.abs(a["E"])).all()
