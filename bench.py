@@ -40,10 +40,10 @@ COUNTER_SCALE = {"fetch": 2.0, "write": 1.0}
 MEASURED_TRAFFIC = {
     ("f32", 16384, 5000, 192): {
         "sources": {"paper_2508_15522_amd/csrc/gff_relax.hip":
-                    "be6bc648aecc09ae081e909e30fa0d199ffcb5cc5a0508dc945c93eaab9aa3f4",
+                    "dbf5c9473d39d40af71b5502b2d8b731e98a2e406f7ddf493044987ca2b82111",
                     "paper_2508_15522_amd/csrc/gff_internal.hpp":
-                    "0f1b5c8a61f7e25dc89b990b2e2dc102cab89a75d27295dcb91d10cc002b91f4"},
-        "fetch_kib": 292215755.75, "write_kib": 11601174.0,
+                    "56468c79b1c704b1db9f8607714a5d167a4691f89ff6d5a71d11baaf78e37ac9"},
+        "fetch_kib": 291617255.5625, "write_kib": 11595372.625,
         "valu_insts": 204741970915.0,          # SQ_INSTS_VALU (wave instructions) of the launch
     },
 }
