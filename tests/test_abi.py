@@ -98,3 +98,20 @@ def test_struct_layouts_match_the_header(tmp_path):
         assert int(got[c]) == C.sizeof(py), c
         for f in py._fields_:
             assert int(got[f"{c}.{f[0]}"]) == getattr(py, f[0]).offset, (c, f[0])
+
+
+def test_scan_target_helpers():
+    """Host helpers that lay out scan targets (input preparation, no device)."""
+    from paper_2508_15522_amd import scans as SC
+    start = [np.array([[0.0, 0.0, 3.0], [1.0, 2.0, 3.5]]), np.array([[5.0, 5.0, 4.0], [6.0, 7.0, 4.2]])]
+    held = np.array([1, 0])
+    t = SC.detachment_targets(start, held, np.array([1.3, 1.4, 1.5]))
+    assert t.shape == (2, 3, 3)
+    assert np.allclose(t[0, :, :2], [1.0, 2.0]) and np.allclose(t[1, :, :2], [5.0, 5.0])
+    assert np.allclose(t[:, :, 2], [1.3, 1.4, 1.5])
+    d = SC.drag_targets(start, held, (1.0, 1.0), 0.1, 4, height=3.3)
+    step = 0.1 / np.sqrt(2.0)
+    assert np.allclose(d[0, 3], [1.0 + 3 * step, 2.0 + 3 * step, 3.3])
+    assert np.allclose(d[1, 0], [5.0, 5.0, 3.3])
+    d2 = SC.drag_targets(start, held, (0.0, 2.0), 0.5, 2)
+    assert np.allclose(d2[1, 1], [5.0, 5.5, 4.0])

@@ -111,3 +111,26 @@ def test_direct_rejects_mismatched_alpha(world):
     F = torch.empty_like(pos)
     with pytest.raises(G.GffError):
         G.eval_forces_direct(d2, topo, plan, False, pos, F)
+
+
+def test_direct_langevin_without_friction_is_velocity_verlet(world):
+    """The all-atom mode's Langevin integrator at zero friction reduces to its velocity
+    Verlet (the O step is the identity), up to the rounding of two half drifts."""
+    sub, mols, topo, direct = world
+    announce("all-atom Langevin at zero friction")
+    rep_type = np.full(24, 1)
+    plan = G.Plan(topo, rep_type, block_threads=192)
+    pos = _batch(sub, mols, rep_type, 1300)
+    vel = list(S.mb_velocities(mols[1].mass, len(rep_type), 300.0, S.SEED_NVE + 3))
+    res = []
+    for mode, kw in ((G.MODE_NVE, {}), (G.MODE_LANGEVIN, dict(gamma=0.0, seed=5))):
+        st = D.fire_state(plan, pos, vel_per_rep=vel)
+        out = D.outputs(plan)
+        G.relax_batch_direct(direct, topo, plan, G.relax_params(mode, 60, True, dt=0.5, **kw), st, out["E"],
+                             out["fnorm"], out["steps"])
+        torch.cuda.synchronize()
+        res.append((st["pos"].cpu().numpy(), out["E"].cpu().numpy()))
+    dx = np.abs(res[0][0] - res[1][0]).max()
+    announce(f"  max |dx| NVE vs Langevin(gamma=0) = {dx:.2e} A")
+    assert dx < 1e-4
+    assert np.abs(res[0][1] - res[1][1]).max() < 1e-3

@@ -150,3 +150,24 @@ def test_fused_scan_equals_point_by_point_launches(world):
     for k in range(len(lift)):
         assert torch.equal(a["pos"][k], b["pos"][k]), k
     assert (np.abs(a["E"] - b["E"]) < 2e-5 * nat[:, None] + 1e-6 * np.abs(a["E"])).all()
+
+
+def test_relax_scan_rejects_invalid_arguments(world):
+    w = world
+    plan = G.Plan(w["topo"], np.array([1, 1]))
+    pos = _positions(w, [1, 1], 6900)
+    st = D.fire_state(plan, pos)
+    path = torch.zeros(2, 3, 3, device="cuda")
+    E = torch.empty(2, 3, dtype=torch.float64, device="cuda")
+    fire = G.relax_params(G.MODE_FIRE, 0, True, f_conv=1e-3)
+    with pytest.raises(G.GffError):          # no held atom
+        G.relax_scan(w["grid"].desc, w["topo"], plan, fire, st, path, 3, 10, 0.05, E)
+    st["fixed_atom"] = torch.zeros(2, dtype=torch.int32, device="cuda")
+    for bad in (dict(n_points=0), dict(mpp=-1), dict(dt0=0.0)):
+        a = dict(n_points=3, mpp=10, dt0=0.05); a.update(bad)
+        with pytest.raises(G.GffError):
+            G.relax_scan(w["grid"].desc, w["topo"], plan, fire, st, path, a["n_points"], a["mpp"], a["dt0"], E)
+    with pytest.raises(G.GffError):          # FIRE only
+        G.relax_scan(w["grid"].desc, w["topo"], plan, G.relax_params(G.MODE_NVE, 0, True), st, path, 3, 10, 0.05, E)
+    with pytest.raises(G.GffError):          # the per-point energies are required
+        G.relax_scan(w["grid"].desc, w["topo"], plan, fire, st, path, 3, 10, 0.05, None)
