@@ -290,7 +290,10 @@ gff_status gff_relax_batch(const gff_grid *grid, const gff_topology *topo, const
  * is that of one gff_relax_batch launch per point with a gff_refill restart in between.
  * Outputs: d_E_points [n_rep][n_points] (FP64 holding the FP32 sums), d_steps_points and
  * d_status_points [n_rep][n_points] (nullable), d_pos_points [n_points][3][N] (nullable),
- * and as gff_relax_batch the final state, d_E_rep, d_fnorm_rep, d_steps_rep (total moves). */
+ * and as gff_relax_batch the final state, d_E_rep, d_fnorm_rep, d_steps_rep (total moves).
+ * A replica that enters with GFF_REP_CONVERGED or GFF_REP_NONFINITE set, or becomes
+ * non-finite during the scan, is not scanned further: its remaining per-point entries are
+ * left unwritten (initialise the status with 0 to scan every replica). */
 gff_status gff_relax_scan(const gff_grid *grid, const gff_topology *topo, const gff_plan *plan,
                           const gff_relax_params *params, const gff_state *state, const float *d_path, int n_points,
                           int moves_per_point, float dt0, double *d_E_points, int *d_steps_points,
