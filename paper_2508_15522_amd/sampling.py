@@ -305,7 +305,7 @@ def train_imle(mlp, targets, ntors, types, steps, batch=1024, K=64, lr=1e-3, see
     batches draw minima with probabilities proportional to `weights` (host, default uniform)."""
     m = targets.shape[0]
     rng = np.random.default_rng(seed)
-    p = None if weights is None else np.asarray(weights, np.float64) / np.sum(weights)
+    cdf = None if weights is None else np.cumsum(np.asarray(weights, np.float64))
     cand_noise = torch.empty(batch * K, 64, device="cuda")
     cand_out = torch.empty(batch * K, 41, device="cuda")
     best = torch.empty(batch, dtype=torch.int32, device="cuda")
@@ -314,7 +314,11 @@ def train_imle(mlp, targets, ntors, types, steps, batch=1024, K=64, lr=1e-3, see
     loss = torch.empty(batch, device="cuda")
     hist = []
     for s in range(steps):
-        idx = torch.from_numpy(rng.integers(0, m, batch) if p is None else rng.choice(m, batch, p=p)).cuda()
+        if cdf is None:
+            pick = rng.integers(0, m, batch)
+        else:
+            pick = np.minimum(np.searchsorted(cdf, rng.random(batch) * cdf[-1], side="right"), m - 1)
+        idx = torch.from_numpy(pick).cuda()
         tg = targets.index_select(0, idx).contiguous()
         nt = ntors.index_select(0, idx).contiguous()
         ty = types.index_select(0, idx).contiguous()
@@ -332,26 +336,33 @@ def train_imle(mlp, targets, ntors, types, steps, batch=1024, K=64, lr=1e-3, see
     return hist
 
 
-def compare_learned_vs_uniform(grid, mol, collect_rounds=6, collect_rep=4096, train_steps=400, eval_rounds=6,
-                               eval_rep=1024, seed=S.SEED_PHILOX, log=None):
-    """Collect minima with uniform proposals, train the proposer on every converged minimum
-    (the relaxed poses the method generated), each distinct minimum weighted equally, then
-    run equal numbers of proposals with each method against fresh archives.  Returns a dict
-    of counts, wall times, minima/s, mean FIRE steps and mean RMS relaxation move per
-    converged minimum."""
+def compare_learned_vs_uniform(grid, mol, collect_minima=50_000, collect_rep=4096, train_steps=400, eval_rounds=6,
+                               eval_rep=1024, seed=S.SEED_PHILOX, log=None, max_collect_rounds=4000,
+                               weight_power=1.0):
+    """Collect at least collect_minima converged minima with rounds of uniform proposals,
+    train the proposer on every converged minimum (the relaxed poses the method generated),
+    a minimum of an energy class with c members weighted c^-weight_power (1: every distinct
+    minimum the same total weight, 0: every minimum the same weight), then run equal numbers
+    of proposals with each
+    method against fresh archives.  Returns a dict of counts, wall times, minima/s, mean FIRE
+    steps and mean RMS relaxation move per converged minimum."""
     say = log or (lambda m: None)
     col = Sampler(grid, mol, collect_rep, seed=seed)
-    arch = Archive()
+    arch = Archive(max_atoms=mol.n)
     targets, energies = [], []
     t0 = time.time()
-    for r in range(collect_rounds):
+    got, r = 0, 0
+    while got < collect_minima and r < max_collect_rounds:
         rs = col.round_uniform(arch, r, keep_new=True)
         pos, newh, okh, E = rs.new_pos[0]
         if okh.any():
             targets.append(col.encode_minima(pos, okh))
             energies.append(E[okh])
-        say(f"collect round {r}: converged {rs.converged}/{rs.proposals}, new {rs.new_minima}, "
-            f"mean steps {rs.fire_steps_converged:.0f}, {rs.seconds:.2f} s")
+        got += rs.converged
+        if r % 25 == 0:
+            say(f"collect round {r}: converged {rs.converged}/{rs.proposals}, new {rs.new_minima}, "
+                f"mean steps {rs.fire_steps_converged:.0f}, {rs.seconds:.2f} s; {got} minima so far")
+        r += 1
     collect_s = time.time() - t0
     tg = torch.cat(targets, 0).contiguous()
     m = tg.shape[0]
@@ -361,8 +372,14 @@ def compare_learned_vs_uniform(grid, mol, collect_rounds=6, collect_rep=4096, tr
     # over its converged members: frequent basins do not crowd out rare ones
     E = np.concatenate(energies)
     aE = arch.E[:arch.count()].cpu().numpy()
-    cl = np.abs(E[:, None] - aE[None, :]).argmin(1)
-    w = 1.0 / np.bincount(cl, minlength=len(aE))[cl]
+    order = np.argsort(aE)
+    sE = aE[order]
+    if len(sE) == 1:
+        cl = np.zeros(len(E), np.int64)
+    else:                                                            # nearest archived energy
+        hi = np.clip(np.searchsorted(sE, E), 1, len(sE) - 1)
+        cl = order[np.where(np.abs(E - sE[hi - 1]) <= np.abs(E - sE[hi]), hi - 1, hi)]
+    w = np.bincount(cl, minlength=len(aE))[cl].astype(np.float64) ** -weight_power
     mlp = G.MLP(1, S.mlp_init_params(1))
     t0 = time.time()
     hist = train_imle(mlp, tg, ntors, types, train_steps, batch=min(1024, max(64, m)), log=say, weights=w)
@@ -402,7 +419,7 @@ def compare_learned_vs_uniform(grid, mol, collect_rounds=6, collect_rep=4096, tr
     res["gain_minima_per_s_flow"] = (res["learned"]["flow"]["minima_per_s"] /
                                      max(res["uniform"]["flow"]["minima_per_s"], 1e-12))
     res["training"] = dict(minima=m, distinct=arch.count(), steps=train_steps, loss_first=hist[0][1],
-                           loss_last=hist[-1][1], collect_s=collect_s, train_s=train_s)
+                           loss_last=hist[-1][1], collect_s=collect_s, train_s=train_s, collect_rounds=r)
     res["gain_minima_per_s"] = res["learned"]["minima_per_s"] / max(res["uniform"]["minima_per_s"], 1e-12)
     res["gain_minima_per_s_rmsd"] = (res["learned"]["minima_per_s_rmsd"] /
                                      max(res["uniform"]["minima_per_s_rmsd"], 1e-12))

@@ -21,7 +21,7 @@ def test_learned_proposals_land_near_minima():
     D.require_gpu()
     cfg = configs.GRID_SMALL
     grid = D.build_physical_grid(cfg.substrate(), D.spec_for(cfg))
-    res = SM.compare_learned_vs_uniform(grid, S.mol_chain24(), collect_rounds=4, collect_rep=2048,
+    res = SM.compare_learned_vs_uniform(grid, S.mol_chain24(), collect_minima=6000, collect_rep=2048,
                                         train_steps=300, eval_rounds=3, eval_rep=1024, log=announce)
     announce(f"  result: {res}")
     tr = res["training"]
