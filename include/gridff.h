@@ -421,11 +421,14 @@ gff_status gff_dedupe_energy(int n_new, const double *d_E, const int *d_type, co
  * centroid d_arch_cen [k][3] (FP64, the mean of its atoms in order), type d_arch_type [k];
  * *d_arch_n (device int) entries are in use, new minima are appended up to `capacity`.
  * d_is_new [n_rep] receives 1 for the new minima.  max_atoms must cover every type in the
- * plan (<= 128).  Two kernels: all candidates against the prior archive in parallel, then
- * one workgroup walks the survivors in order. */
+ * plan (<= 128).  d_work: gff_dedupe_rmsd_workspace_bytes(n_rep) bytes of device scratch.
+ * Four kernels: every candidate against the prior archive, every candidate against the
+ * earlier candidates, one workgroup over the candidates in order (comparing only those that
+ * match an earlier candidate), and the flags. */
+size_t gff_dedupe_rmsd_workspace_bytes(int n_rep);
 gff_status gff_dedupe_rmsd(const gff_plan *plan, const float *d_pos, const int *d_ok, float tol, float Lx, float Ly,
                            int capacity, int max_atoms, float *d_arch_pos, double *d_arch_cen, int *d_arch_type,
-                           int *d_arch_n, int *d_is_new, void *stream);
+                           int *d_arch_n, int *d_is_new, void *d_work, size_t work_bytes, void *stream);
 
 /* ------------------------------------------------------------------ learned proposer */
 

@@ -161,6 +161,13 @@ __global__ void __launch_bounds__(1024) k_dedupe(int n_new, const double *E, con
 // difference, so the best t is the lattice vector nearest m.  The sum of squares runs in
 // FP64 over the atoms in order and stops once it exceeds n tol^2: its terms are
 // non-negative, so stopping never changes the decision.
+//
+// Three passes keep the order-dependent part small.  (1) one block per candidate: its
+// centroid, and whether it matches a minimum archived before the call; (2) one block per
+// surviving candidate: whether any earlier survivor of its type matches it; (3) one
+// workgroup walks the survivors in order: one with no earlier matching survivor is new
+// without further comparison, the others are compared with the minima accepted so far in
+// the call.
 struct RmsdArgs {
     const int *rep_type, *atom_off, *ok;
     const float *pos;                    // [3][N]
@@ -168,102 +175,152 @@ struct RmsdArgs {
     double Lx, Ly, tol2;
     float *arch_pos;                     // [capacity][max_atoms][3]
     double *arch_cen;                    // [capacity][3]
-    int *arch_type, *arch_n, *is_new;
+    int *arch_type, *arch_n, *is_new;    // is_new: 1 survivor of pass 1, 3 with an earlier matching survivor
+    double4 *cen;                        // [n_rep] candidate centroids (w: 1 if finite)
 };
 
-// Candidate c's atoms into LDS (x, y, z per atom); returns whether all are finite.
-__device__ bool stage_candidate(const RmsdArgs &A, int c, float *s_x, double *s_c) {
+// Candidate c's atoms into LDS (x, y, z per atom).
+__device__ void stage_candidate(const RmsdArgs &A, int c, float *s_x) {
     const int g0 = A.atom_off[c], n = A.atom_off[c + 1] - g0;
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
         s_x[3 * i] = A.pos[g0 + i]; s_x[3 * i + 1] = A.pos[g0 + i + A.N]; s_x[3 * i + 2] = A.pos[g0 + i + 2 * A.N];
     }
-    __syncthreads();
-    bool fin = true;
-    if (threadIdx.x == 0) {             // centroid in FP64, atoms in order
-        double sx = 0.0, sy = 0.0, sz = 0.0;
-        for (int i = 0; i < n; ++i) {
-            const float x = s_x[3 * i], y = s_x[3 * i + 1], z = s_x[3 * i + 2];
-            fin = fin && __builtin_isfinite(x) && __builtin_isfinite(y) && __builtin_isfinite(z);
-            sx += x; sy += y; sz += z;
-        }
-        s_c[0] = sx / n; s_c[1] = sy / n; s_c[2] = sz / n;
-    }
-    return fin;
 }
 
-__device__ bool same_minimum(const RmsdArgs &A, const float *s_x, const double *s_c, int n, int k) {
-    const double *ac = A.arch_cen + 3 * (size_t)k;
-    const double tx = rint((s_c[0] - ac[0]) / A.Lx) * A.Lx, ty = rint((s_c[1] - ac[1]) / A.Ly) * A.Ly;
-    const float *ap = A.arch_pos + (size_t)k * 3 * A.max_atoms;
+// Lattice-translated RMSD test of the staged candidate (atoms s_x, centroid c) against an
+// entry given by its atoms (x, y, z at stride sx within an atom, sa between atoms) and
+// centroid e.
+__device__ __forceinline__ bool same_minimum(const RmsdArgs &A, const float *s_x, double cx, double cy, int n,
+                                             const float *ex, const float *ey, const float *ez, long sa, double ecx,
+                                             double ecy) {
+    const double tx = rint((cx - ecx) / A.Lx) * A.Lx, ty = rint((cy - ecy) / A.Ly) * A.Ly;
     const double lim = n * A.tol2;
     double s = 0.0;
     for (int i = 0; i < n; ++i) {
-        const double dx = (double)s_x[3 * i] - (double)ap[3 * i] - tx;
-        const double dy = (double)s_x[3 * i + 1] - (double)ap[3 * i + 1] - ty;
-        const double dz = (double)s_x[3 * i + 2] - (double)ap[3 * i + 2];
+        const double dx = (double)s_x[3 * i] - (double)ex[i * sa] - tx;
+        const double dy = (double)s_x[3 * i + 1] - (double)ey[i * sa] - ty;
+        const double dz = (double)s_x[3 * i + 2] - (double)ez[i * sa];
         s += dx * dx + dy * dy + dz * dz;
         if (s > lim) return false;
     }
     return true;
 }
 
-// Pass 1, one block per candidate: is_new[c] = 1 when candidate c (ok, finite) matches no
-// minimum archived before this call.
+__device__ __forceinline__ bool same_as_archived(const RmsdArgs &A, const float *s_x, double4 c, int n, int k) {
+    const float *ap = A.arch_pos + (size_t)k * 3 * A.max_atoms;
+    const double *ac = A.arch_cen + 3 * (size_t)k;
+    return same_minimum(A, s_x, c.x, c.y, n, ap, ap + 1, ap + 2, 3, ac[0], ac[1]);
+}
+
+// Pass 1, one block per candidate: centroid (FP64, atoms in order) and the match against
+// the minima archived before the call.  is_new[c] = 1 for a candidate (ok, finite) that
+// matches none of them, 0 otherwise.
 __global__ void __launch_bounds__(256) k_rmsd_archive(RmsdArgs A) {
     __shared__ float s_x[3 * kMaxAtoms];
-    __shared__ double s_c[3];
+    __shared__ double4 s_c;
     __shared__ int s_state;              // 0 candidate, no match yet; 1 match; 2 not a candidate
     const int c = blockIdx.x;
-    const bool fin = stage_candidate(A, c, s_x, s_c);
-    if (threadIdx.x == 0) s_state = (fin && (A.ok == nullptr || A.ok[c] != 0)) ? 0 : 2;
+    const int n = A.atom_off[c + 1] - A.atom_off[c], t = A.rep_type[c];
+    stage_candidate(A, c, s_x);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        bool fin = true;
+        double sx = 0.0, sy = 0.0, sz = 0.0;
+        for (int i = 0; i < n; ++i) {
+            const float x = s_x[3 * i], y = s_x[3 * i + 1], z = s_x[3 * i + 2];
+            fin = fin && __builtin_isfinite(x) && __builtin_isfinite(y) && __builtin_isfinite(z);
+            sx += x; sy += y; sz += z;
+        }
+        s_c = make_double4(sx / n, sy / n, sz / n, fin ? 1.0 : 0.0);
+        A.cen[c] = s_c;
+        s_state = (fin && (A.ok == nullptr || A.ok[c] != 0)) ? 0 : 2;
+    }
     __syncthreads();
     if (s_state == 0) {
-        const int n = A.atom_off[c + 1] - A.atom_off[c], t = A.rep_type[c];
+        const double4 cc = s_c;
         const int na = min(*A.arch_n, A.capacity);
         volatile int *vs = &s_state;
         for (int k = threadIdx.x; k < na && *vs == 0; k += blockDim.x)
-            if (A.arch_type[k] == t && same_minimum(A, s_x, s_c, n, k)) *vs = 1;
+            if (A.arch_type[k] == t && same_as_archived(A, s_x, cc, n, k)) *vs = 1;
     }
     __syncthreads();
     if (threadIdx.x == 0) A.is_new[c] = s_state == 0;
 }
 
-// Pass 2, one workgroup: the surviving candidates in order against the minima accepted
-// earlier in this call; the new ones are appended.
+// Pass 2, one block per survivor c: does an earlier survivor of the same type match it?
+// Then is_new[c] = 3.  Only bit 1 is written here, and only by the block of c, so the
+// survivor bit read by the other blocks does not change.
+__global__ void __launch_bounds__(256) k_rmsd_pairs(RmsdArgs A) {
+    __shared__ float s_x[3 * kMaxAtoms];
+    __shared__ int s_hit;
+    const int c = blockIdx.x;
+    if ((A.is_new[c] & 1) == 0) return;                 // uniform across the block
+    const int n = A.atom_off[c + 1] - A.atom_off[c], t = A.rep_type[c];
+    stage_candidate(A, c, s_x);
+    if (threadIdx.x == 0) s_hit = 0;
+    __syncthreads();
+    const double4 cc = A.cen[c];
+    volatile int *vh = &s_hit;
+    for (int j = threadIdx.x; j < c && *vh == 0; j += blockDim.x) {
+        if ((A.is_new[j] & 1) == 0 || A.rep_type[j] != t) continue;
+        const double4 cj = A.cen[j];
+        const int g0 = A.atom_off[j];
+        if (same_minimum(A, s_x, cc.x, cc.y, n, A.pos + g0, A.pos + g0 + A.N, A.pos + g0 + 2 * A.N, 1, cj.x, cj.y))
+            *vh = 1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && s_hit) A.is_new[c] = 3;
+}
+
+// Pass 3, one workgroup: the survivors in order.  A survivor without an earlier matching
+// survivor (is_new 1) is new; one with (3) is compared with the minima accepted so far in
+// this call.  New minima are appended while the archive has room.  The decision goes to
+// cen[c].w (is_new stays as the passes left it while the workgroup reads it).
 __global__ void __launch_bounds__(1024) k_rmsd_batch(RmsdArgs A) {
     __shared__ float s_x[3 * kMaxAtoms];
-    __shared__ double s_c[3];
-    __shared__ int s_n, s_hit;
-    if (threadIdx.x == 0) s_n = min(*A.arch_n, A.capacity);
-    __syncthreads();
-    const int na0 = s_n;
+    __shared__ int s_hit;
+    const int na0 = min(*A.arch_n, A.capacity);
+    int na = na0;                                      // identical in every thread
     for (int c = 0; c < A.n_rep; ++c) {
-        if (A.is_new[c] == 0) continue;                // uniform across the block
-        stage_candidate(A, c, s_x, s_c);
-        if (threadIdx.x == 0) s_hit = 0;
-        __syncthreads();
-        const int n = A.atom_off[c + 1] - A.atom_off[c], t = A.rep_type[c], na = s_n;
-        for (int k = na0 + threadIdx.x; k < na; k += blockDim.x)
-            if (A.arch_type[k] == t && same_minimum(A, s_x, s_c, n, k)) s_hit = 1;
-        __syncthreads();
-        const bool fresh = !s_hit && na < A.capacity;
+        const int state = A.is_new[c];                // uniform: not written in this pass
+        if (state == 0) continue;
+        const int n = A.atom_off[c + 1] - A.atom_off[c], t = A.rep_type[c];
+        const double4 cc = A.cen[c];
+        bool fresh = na < A.capacity;
+        if (state == 3 && fresh && na > na0) {
+            __syncthreads();                           // earlier appends and s_x reads are done
+            stage_candidate(A, c, s_x);
+            if (threadIdx.x == 0) s_hit = 0;
+            __syncthreads();
+            for (int k = na0 + threadIdx.x; k < na; k += blockDim.x)
+                if (A.arch_type[k] == t && same_as_archived(A, s_x, cc, n, k)) s_hit = 1;
+            __syncthreads();
+            fresh = s_hit == 0;
+        }
         if (fresh) {
+            const int g0 = A.atom_off[c];
             float *ap = A.arch_pos + (size_t)na * 3 * A.max_atoms;
-            for (int i = threadIdx.x; i < 3 * n; i += blockDim.x) ap[i] = s_x[i];
+            for (int i = threadIdx.x; i < 3 * n; i += blockDim.x) {
+                const int a = i / 3, d = i - 3 * a;
+                ap[i] = A.pos[g0 + a + d * A.N];
+            }
             if (threadIdx.x == 0) {
-                A.arch_cen[3 * (size_t)na] = s_c[0]; A.arch_cen[3 * (size_t)na + 1] = s_c[1];
-                A.arch_cen[3 * (size_t)na + 2] = s_c[2];
+                A.arch_cen[3 * (size_t)na] = cc.x; A.arch_cen[3 * (size_t)na + 1] = cc.y;
+                A.arch_cen[3 * (size_t)na + 2] = cc.z;
                 A.arch_type[na] = t;
             }
+            ++na;
         }
-        __syncthreads();                               // every thread has read s_n and s_x
-        if (threadIdx.x == 0) {
-            A.is_new[c] = fresh;
-            if (fresh) s_n = na + 1;
-        }
-        __syncthreads();
+        if (threadIdx.x == 0) A.cen[c].w = fresh ? 1.0 : 0.0;
     }
-    if (threadIdx.x == 0) *A.arch_n = s_n;
+    if (threadIdx.x == 0) *A.arch_n = na;
+}
+
+// is_new[c] = 1 for the survivors pass 3 accepted, 0 otherwise.
+__global__ void __launch_bounds__(256) k_rmsd_final(RmsdArgs A) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= A.n_rep) return;
+    A.is_new[c] = (A.is_new[c] != 0 && A.cen[c].w != 0.0) ? 1 : 0;
 }
 
 // ---------------------------------------------------------------- pose -> encoding
@@ -414,19 +471,26 @@ extern "C" gff_status gff_dedupe_energy(int n_new, const double *d_E, const int 
     return hip_status(hipGetLastError());
 }
 
+extern "C" size_t gff_dedupe_rmsd_workspace_bytes(int n_rep) { return n_rep > 0 ? (size_t)n_rep * sizeof(double4) : 0; }
+
 extern "C" gff_status gff_dedupe_rmsd(const gff_plan *plan, const float *d_pos, const int *d_ok, float tol, float Lx,
                                       float Ly, int capacity, int max_atoms, float *d_arch_pos, double *d_arch_cen,
-                                      int *d_arch_type, int *d_arch_n, int *d_is_new, void *stream) {
+                                      int *d_arch_type, int *d_arch_n, int *d_is_new, void *d_work, size_t work_bytes,
+                                      void *stream) {
     if (!plan || !(tol >= 0.f) || !std::isfinite(tol) || !(Lx > 0.f) || !(Ly > 0.f) || capacity < 0) return GFF_EINVAL;
     if (max_atoms < plan->max_n || max_atoms > kMaxAtoms) return GFF_EINVAL;
     if (!d_arch_pos || !d_arch_cen || !d_arch_type || !d_arch_n) return GFF_EINVAL;
     if (plan->n_rep == 0) return GFF_OK;
     if (!d_pos || !d_is_new) return GFF_EINVAL;
+    if (!d_work || work_bytes < gff_dedupe_rmsd_workspace_bytes(plan->n_rep)) return GFF_EWORKSPACE;
     RmsdArgs A{plan->d_rep_type, plan->d_atom_off, d_ok, d_pos, plan->n_atoms, plan->n_rep, capacity, max_atoms,
                (double)Lx, (double)Ly, (double)tol * (double)tol, d_arch_pos, d_arch_cen, d_arch_type, d_arch_n,
-               d_is_new};
-    hipLaunchKernelGGL(k_rmsd_archive, dim3(plan->n_rep), dim3(256), 0, (hipStream_t)stream, A);
-    hipLaunchKernelGGL(k_rmsd_batch, dim3(1), dim3(1024), 0, (hipStream_t)stream, A);
+               d_is_new, static_cast<double4 *>(d_work)};
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_rmsd_archive, dim3(plan->n_rep), dim3(256), 0, s, A);
+    hipLaunchKernelGGL(k_rmsd_pairs, dim3(plan->n_rep), dim3(256), 0, s, A);
+    hipLaunchKernelGGL(k_rmsd_batch, dim3(1), dim3(1024), 0, s, A);
+    hipLaunchKernelGGL(k_rmsd_final, dim3((plan->n_rep + 255) / 256), dim3(256), 0, s, A);
     return hip_status(hipGetLastError());
 }
 

@@ -88,7 +88,8 @@ def lib():
             raise GffError(f"{LIB_PATH} is missing: build it with paper_2508_15522_amd.build.build()")
         L = C.CDLL(LIB_PATH)
         L.gff_status_string.restype = C.c_char_p
-        for n in ("gff_build_grid_workspace_bytes", "gff_fit_workspace_bytes", "gff_grid_bytes"):
+        for n in ("gff_build_grid_workspace_bytes", "gff_fit_workspace_bytes", "gff_grid_bytes",
+                  "gff_dedupe_rmsd_workspace_bytes"):
             getattr(L, n).restype = C.c_size_t
         for n in ("gff_build_grid", "gff_fit_bspline", "gff_pack_grid", "gff_topology_create", "gff_plan_create",
                   "gff_plan_atom_offsets", "gff_eval_forces", "gff_interp_points", "gff_relax_batch",
@@ -321,7 +322,7 @@ EXPORTS += ["gff_propose_uniform", "gff_pose_from_dof", "gff_encode_pose", "gff_
             "gff_mlp_n_params", "gff_mlp_create", "gff_mlp_destroy", "gff_mlp_get_params", "gff_mlp_workspace_bytes",
             "gff_mlp_forward", "gff_mlp_train_step", "gff_imle_select", "gff_normal_philox", "gff_gemm_bf16",
             "gff_gather_rows", "gff_relax_graph_create", "gff_graph_launch", "gff_graph_destroy", "gff_autotune",
-            "gff_refill", "gff_dedupe_rmsd"]
+            "gff_refill", "gff_dedupe_rmsd", "gff_dedupe_rmsd_workspace_bytes"]
 N_ENC = 41
 
 
@@ -362,11 +363,23 @@ def dedupe_energy(d_E, d_type, d_ok, tol, capacity, d_arch_E, d_arch_type, d_arc
                                   _ptr(d_is_new), _stream(stream)))
 
 
+def dedupe_rmsd_workspace_bytes(n_rep):
+    return lib().gff_dedupe_rmsd_workspace_bytes(C.c_int(n_rep))
+
+
 def dedupe_rmsd(plan, d_pos, d_ok, tol, Lx, Ly, capacity, max_atoms, d_arch_pos, d_arch_cen, d_arch_type, d_arch_n,
-                d_is_new, stream=None):
+                d_is_new, d_work=None, stream=None):
+    """d_work: device scratch of dedupe_rmsd_workspace_bytes(plan.n_rep) bytes (allocated
+    here when not given)."""
+    nb = dedupe_rmsd_workspace_bytes(plan.n_rep)
+    if d_work is None and nb > 0:
+        import torch
+        d_work = torch.empty(nb, dtype=torch.uint8, device=d_is_new.device)
     check(lib().gff_dedupe_rmsd(plan.handle, _ptr(d_pos), _ptr(d_ok), C.c_float(tol), C.c_float(Lx), C.c_float(Ly),
                                 C.c_int(capacity), C.c_int(max_atoms), _ptr(d_arch_pos), _ptr(d_arch_cen),
-                                _ptr(d_arch_type), _ptr(d_arch_n), _ptr(d_is_new), _stream(stream)))
+                                _ptr(d_arch_type), _ptr(d_arch_n), _ptr(d_is_new), _ptr(d_work),
+                                C.c_size_t(0 if d_work is None else d_work.numel() * d_work.element_size()),
+                                _stream(stream)))
 
 
 def normal_philox(n, seed, rnd, d_out, stream=None):

@@ -82,6 +82,7 @@ class Sampler:
         self.ntors = torch.full((n_rep,), self.T, dtype=torch.int32, device="cuda")
         self.is_new = torch.empty(n_rep, dtype=torch.int32, device="cuda")
         self.is_new_rmsd = torch.empty(n_rep, dtype=torch.int32, device="cuda")
+        self.rmsd_work = torch.empty(max(G.dedupe_rmsd_workspace_bytes(n_rep), 1), dtype=torch.uint8, device="cuda")
         self.out = D.outputs(self.plan)
 
     def _dedupe(self, archive, pos, ok):
@@ -90,7 +91,7 @@ class Sampler:
         G.dedupe_energy(self.out["E"], self.types, ok, E_TOL, archive.capacity, archive.E, archive.types, archive.n,
                         self.is_new)
         G.dedupe_rmsd(self.plan, pos, ok, RMSD_TOL, self.Lx, self.Ly, archive.rmsd_capacity, archive.max_atoms,
-                      archive.pos, archive.cen, archive.rtypes, archive.rn, self.is_new_rmsd)
+                      archive.pos, archive.cen, archive.rtypes, archive.rn, self.is_new_rmsd, self.rmsd_work)
         return int(self.is_new.sum().item()), int(self.is_new_rmsd.sum().item())
 
     def _relax_and_dedupe(self, archive, keep_new):

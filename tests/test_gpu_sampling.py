@@ -198,6 +198,9 @@ def test_dedupe_rmsd_capacity_and_arguments():
         G.dedupe_rmsd(plan, dpos, None, 0.1, 11.28, 11.28, cap, 23, arch_pos, arch_cen, arch_type, arch_n, isn)
     with pytest.raises(G.GffError):
         G.dedupe_rmsd(plan, dpos, None, -0.1, 11.28, 11.28, cap, 24, arch_pos, arch_cen, arch_type, arch_n, isn)
+    small = torch.empty(G.dedupe_rmsd_workspace_bytes(plan.n_rep) - 8, dtype=torch.uint8, device="cuda")
+    with pytest.raises(G.GffError):       # workspace below the query
+        G.dedupe_rmsd(plan, dpos, None, 0.1, 11.28, 11.28, cap, 24, arch_pos, arch_cen, arch_type, arch_n, isn, small)
 
 
 def _bf16_bits(a):
