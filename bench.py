@@ -98,6 +98,8 @@ def main():
                     help="block threads (192: five 38-atom replicas fill 190 of 192 lanes; the fastest of a "
                          "64..448 sweep)")
     ap.add_argument("--compare-f16", action="store_true", help="also time the FP16-grid variant")
+    ap.add_argument("--compare-langevin", action="store_true",
+                    help="also time the same replicas under Langevin dynamics (BAOAB, 300 K, gamma 0.01/fs)")
     ap.add_argument("--compare-trilinear", action="store_true",
                     help="also time the trilinear energy/force storage (the earlier scheme) and its NVE drift")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -234,6 +236,25 @@ def main():
         res["f16_value"] = rs * args.steps / w16
         res["f16_kernel_avg_s"] = float(np.mean(p16))
         res["f16_vs_f32"] = res["f16_value"] / value
+    if args.compare_langevin:
+        lprm = G.relax_params(G.MODE_LANGEVIN, args.md_steps, True, dt=0.5, T=300.0, gamma=0.01, seed=S.SEED_PHILOX)
+        lts = []
+        for k in range(args.steps + 1):
+            stl = fresh_state()
+            lprm.round = k
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            G.relax_batch(grid.desc, topo, plan, lprm, stl, out["E"], out["fnorm"], out["steps"], None, stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            if k > 0:                                    # the first launch is a warm-up
+                lts.append(e0.elapsed_time(e1) / 1e3)
+        res["langevin_kernel_avg_s"] = float(np.mean(lts))
+        res["langevin_value"] = rs / res["langevin_kernel_avg_s"]
+        res["langevin_vs_nve_kernel"] = kern_avg / res["langevin_kernel_avg_s"]
+        log(f"Langevin: {res['langevin_value']:.3e} replica-steps/s by kernel time "
+            f"({res['langevin_vs_nve_kernel']:.3f}x the NVE kernel time ratio)")
     if args.compare_trilinear and args.storage == "f32":
         gtri = setup(G.STORE_TRILINEAR)
         wt, pt, _ = timed(gtri, args.steps, 1)
