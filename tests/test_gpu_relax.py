@@ -185,3 +185,42 @@ def test_nve_short_run_parity_and_drift(world):
     assert (out["steps"].cpu().numpy() == n).all()
     # FP32 forces with FP64 accounting: the energy error stays far below the thermal scale
     assert dr[:, 2].max() < 5e-3
+
+
+def test_fire_teacher_forced_steps_and_final_certificate(world):
+    """Long runs cannot be compared step for step (FP32 and FP64 trajectories separate), so
+    (i) teacher forcing: the GPU state after 1500 moves (positions, velocities, FIRE dt,
+    alpha, count, flags) is handed to the oracle, and both sides take 5 more moves from it;
+    (ii) a final-state certificate: the oracle's FP64 |F|_2 and energy at the GPU's final
+    positions agree with the convergence the GPU reported."""
+    w = world
+    announce("fire teacher forcing + certificate")
+    rep_type = np.repeat(np.arange(len(w["mols"])), 4)
+    plan = G.Plan(w["topo"], rep_type, block_threads=256)
+    pos = _positions(w, rep_type, 1700)
+    st, out = _fire(w, plan, pos, 1500, f_conv=1e-3)
+    x = np.concatenate(D.unsoa(plan, st["pos"]))
+    v = np.concatenate(D.unsoa(plan, st["vel"]))
+    state = dict(dt=st["fire_dt"].cpu().numpy().astype(np.float64), alpha=st["fire_alpha"].cpu().numpy().astype(np.float64),
+                 npos=st["fire_npos"].cpu().numpy(), status=st["status"].cpu().numpy())
+    nat = np.array([w["mols"][t].n for t in rep_type])
+    # (ii) certificate at the GPU's final positions
+    Fo, Eo, _, _ = O.eval_batch(w["B"], w["geo"], w["mols"], rep_type, x)
+    off = np.concatenate([[0], np.cumsum(nat)])
+    fo = np.array([np.linalg.norm(Fo[off[r]:off[r + 1]]) for r in range(len(rep_type))])
+    conv = (state["status"] & G.REP_CONVERGED) != 0
+    announce(f"  converged {conv.sum()}/{len(conv)}; oracle |F| at converged GPU states max "
+             f"{fo[conv].max() if conv.any() else 0:.2e}")
+    assert conv.any()
+    assert (fo[conv] < 1e-3 + 2e-4).all()
+    assert (np.abs(out["E"].cpu().numpy() - Eo) < 2e-5 * nat + 1e-6 * np.abs(Eo)).all()
+    # (i) five more moves from the GPU's state on both sides (converged replicas stay put)
+    st2, out2 = _fire(w, plan, None, 5, f_conv=1e-3, st=st)
+    ref = O.fire_batch(w["B"], w["geo"], w["mols"], rep_type, x, 5, vel=v, state=state, f_conv=1e-3)
+    x2 = np.concatenate(D.unsoa(plan, st2["pos"]))
+    dx = np.abs(x2 - ref["pos"]).max()
+    announce(f"  teacher-forced 5 moves: max |dx| = {dx:.2e} A")
+    assert dx < 2e-5
+    assert np.array_equal(out2["steps"].cpu().numpy(), ref["steps"])
+    assert np.array_equal(st2["status"].cpu().numpy(), ref["status"])
+    assert np.abs(st2["fire_dt"].cpu().numpy() - ref["dt"]).max() < 1e-6
