@@ -123,7 +123,7 @@ def main():
                     help="run a 1 GiB device copy first (reference for HBM counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py: runs on one GPU only (asked for --gpus {args.gpus}); "
               "replicas are independent, so more GPUs would each run their own share", file=sys.stderr)
         sys.exit(2)
 
