@@ -403,7 +403,9 @@ gff_status gff_decode_dof(int n, const float *d_enc, int n_tors, float h_lo, flo
  * d_ok nullable) is new when its energy differs by more than tol from every archived minimum
  * of the same type, including candidates accepted earlier in the batch.  New minima are
  * appended to the archive (d_arch_E, d_arch_type, count *d_arch_n, at most `capacity`);
- * d_is_new[c] = 1 for them.  Sequential in c by definition; one workgroup. */
+ * d_is_new[c] = 1 for them.  Sequential in c by definition: three kernels (candidates
+ * against the prior archive, candidates against each other, then one workgroup in order
+ * over those that an earlier candidate lies within tol of). */
 gff_status gff_dedupe_energy(int n_new, const double *d_E, const int *d_type, const int *d_ok, double tol,
                              int capacity, double *d_arch_E, int *d_arch_type, int *d_arch_n, int *d_is_new,
                              void *stream);
@@ -424,7 +426,7 @@ gff_status gff_dedupe_energy(int n_new, const double *d_E, const int *d_type, co
  * plan (<= 128).  d_work: gff_dedupe_rmsd_workspace_bytes(n_rep) bytes of device scratch.
  * Four kernels: every candidate against the prior archive, every candidate against the
  * earlier candidates, one workgroup over the candidates in order (comparing only those that
- * match an earlier candidate), and the flags. */
+ * match an earlier candidate), and the appends and flags. */
 size_t gff_dedupe_rmsd_workspace_bytes(int n_rep);
 gff_status gff_dedupe_rmsd(const gff_plan *plan, const float *d_pos, const int *d_ok, float tol, float Lx, float Ly,
                            int capacity, int max_atoms, float *d_arch_pos, double *d_arch_cen, int *d_arch_type,

@@ -117,40 +117,90 @@ __global__ void __launch_bounds__(128) k_pose(DevTopo t, const int *rep_type, co
 
 // ---------------------------------------------------------------- deduplication
 // Distinct minima in discovery order (energy criterion): candidate c of type t (with
-// ok[c] != 0) is new if |E_c - E_k| > tol for every archived minimum k of type t,
-// including those accepted earlier in the same batch.  One workgroup walks the candidates
-// in order; its threads scan the archive in parallel.  Appends to the archive.
-__global__ void __launch_bounds__(1024) k_dedupe(int n_new, const double *E, const int *type, const int *ok,
-                                                 double tol, int capacity, double *arch_E, int *arch_type,
-                                                 int *arch_n, int *is_new) {
-    __shared__ int s_match;
-    __shared__ int s_n;
-    if (threadIdx.x == 0) s_n = *arch_n;
+// ok[c] != 0 and a finite energy) is new if |E_c - E_k| > tol for every archived minimum k
+// of type t, including those accepted earlier in the same batch.  Three passes: every
+// candidate against the archive as it was (is_new 1 for the survivors), every survivor
+// against the earlier survivors (is_new 3 when one of its type lies within tol), then one
+// workgroup in order: a survivor without such an earlier survivor is new outright, the
+// others are compared with the minima accepted so far in the call.  Appends to the archive.
+__global__ void __launch_bounds__(256) k_dedupe_archive(int n_new, const double *E, const int *type, const int *ok,
+                                                        double tol, int capacity, const double *arch_E,
+                                                        const int *arch_type, const int *arch_n, int *is_new) {
+    __shared__ int s_state;              // 0 candidate, no match yet; 1 match or not a candidate
+    const int c = blockIdx.x;
+    const double e = E[c];
+    const int t = type[c];
+    if (threadIdx.x == 0) s_state = ((ok == nullptr || ok[c] != 0) && fabs(e) < 1e300) ? 0 : 1;
     __syncthreads();
-    for (int c = 0; c < n_new; ++c) {
-        const bool cand = ok == nullptr || ok[c] != 0;
-        if (!cand) {
-            if (threadIdx.x == 0) is_new[c] = 0;
-            continue;                                   // uniform across the block
+    if (s_state == 0) {
+        const int na = min(*arch_n, capacity);
+        volatile int *vs = &s_state;
+        for (int k = threadIdx.x; k < na && *vs == 0; k += blockDim.x)
+            if (arch_type[k] == t && fabs(arch_E[k] - e) <= tol) *vs = 1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) is_new[c] = s_state == 0;
+}
+
+__global__ void __launch_bounds__(256) k_dedupe_pairs(const double *E, const int *type, double tol, int *is_new) {
+    __shared__ int s_hit;
+    const int c = blockIdx.x;
+    if ((is_new[c] & 1) == 0) return;                  // uniform; bit 0 is never cleared here
+    const double e = E[c];
+    const int t = type[c];
+    if (threadIdx.x == 0) s_hit = 0;
+    __syncthreads();
+    volatile int *vh = &s_hit;
+    for (int j = threadIdx.x; j < c && *vh == 0; j += blockDim.x)
+        if ((is_new[j] & 1) && type[j] == t && fabs(E[j] - e) <= tol) *vh = 1;
+    __syncthreads();
+    if (threadIdx.x == 0 && s_hit) is_new[c] = 3;
+}
+
+constexpr int kDedupeChunk = 2048;
+
+__global__ void __launch_bounds__(1024) k_dedupe_batch(int n_new, const double *E, const int *type, double tol,
+                                                       int capacity, double *arch_E, int *arch_type, int *arch_n,
+                                                       int *is_new) {
+    __shared__ int s_state[kDedupeChunk];
+    __shared__ double s_e[kDedupeChunk];
+    __shared__ int s_t[kDedupeChunk];
+    __shared__ int s_fresh[kDedupeChunk];
+    __shared__ int s_hit;
+    const int na0 = min(*arch_n, capacity);
+    int na = na0;                                      // identical in every thread
+    for (int c0 = 0; c0 < n_new; c0 += kDedupeChunk) {
+        const int m = min(kDedupeChunk, n_new - c0);
+        for (int i = threadIdx.x; i < m; i += blockDim.x) {
+            s_state[i] = is_new[c0 + i]; s_e[i] = E[c0 + i]; s_t[i] = type[c0 + i];
         }
-        const double e = E[c];
-        const int t = type[c];
-        if (threadIdx.x == 0) s_match = !(fabs(e) < 1e300);   // non-finite energies never count
         __syncthreads();
-        const int na = s_n;
-        bool m = false;
-        for (int k = threadIdx.x; k < na; k += blockDim.x)
-            if (arch_type[k] == t && fabs(arch_E[k] - e) <= tol) m = true;
-        if (m) s_match = 1;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            const int fresh = !s_match && na < capacity;
-            is_new[c] = fresh;
-            if (fresh) { arch_E[na] = e; arch_type[na] = t; s_n = na + 1; }
+        for (int i = 0; i < m; ++i) {
+            const int state = s_state[i];
+            if (state == 0) { if (threadIdx.x == 0) s_fresh[i] = 0; continue; }
+            const double e = s_e[i];
+            const int t = s_t[i];
+            bool fresh = na < capacity;
+            if (state == 3 && fresh && na > na0) {
+                __syncthreads();                       // the appends so far are visible
+                if (threadIdx.x == 0) s_hit = 0;
+                __syncthreads();
+                for (int k = na0 + threadIdx.x; k < na; k += blockDim.x)
+                    if (arch_type[k] == t && fabs(arch_E[k] - e) <= tol) s_hit = 1;
+                __syncthreads();
+                fresh = s_hit == 0;
+            }
+            if (threadIdx.x == 0) {
+                s_fresh[i] = fresh;
+                if (fresh) { arch_E[na] = e; arch_type[na] = t; }
+            }
+            if (fresh) ++na;
         }
+        __syncthreads();
+        for (int i = threadIdx.x; i < m; i += blockDim.x) is_new[c0 + i] = s_fresh[i];
         __syncthreads();
     }
-    if (threadIdx.x == 0) *arch_n = s_n;
+    if (threadIdx.x == 0) *arch_n = na;
 }
 
 // ---------------------------------------------------------------- RMSD deduplication
@@ -176,7 +226,8 @@ struct RmsdArgs {
     float *arch_pos;                     // [capacity][max_atoms][3]
     double *arch_cen;                    // [capacity][3]
     int *arch_type, *arch_n, *is_new;    // is_new: 1 survivor of pass 1, 3 with an earlier matching survivor
-    double4 *cen;                        // [n_rep] candidate centroids (w: 1 if finite)
+    double4 *cen;                        // [n_rep] candidate centroids (w: pass 3's decision)
+    int *acc;                            // [n_rep] candidates accepted in the call, in order
 };
 
 // Candidate c's atoms into LDS (x, y, z per atom).
@@ -272,55 +323,83 @@ __global__ void __launch_bounds__(256) k_rmsd_pairs(RmsdArgs A) {
     if (threadIdx.x == 0 && s_hit) A.is_new[c] = 3;
 }
 
-// Pass 3, one workgroup: the survivors in order.  A survivor without an earlier matching
-// survivor (is_new 1) is new; one with (3) is compared with the minima accepted so far in
-// this call.  New minima are appended while the archive has room.  The decision goes to
-// cen[c].w (is_new stays as the passes left it while the workgroup reads it).
+// Pass 3, one workgroup: the survivors in order, their data staged in LDS a chunk at a
+// time.  A survivor without an earlier matching survivor (is_new 1) is new; one with (3) is
+// compared with the candidates accepted so far in the call (their own coordinates; the
+// archive copies are written afterwards).  The decision goes to cen[c].w as the archive
+// slot + 1, or 0 (is_new stays as the passes left it while the workgroup reads it).
+constexpr int kRmsdChunk = 1024;
+
 __global__ void __launch_bounds__(1024) k_rmsd_batch(RmsdArgs A) {
     __shared__ float s_x[3 * kMaxAtoms];
+    __shared__ int s_state[kRmsdChunk], s_type[kRmsdChunk], s_n[kRmsdChunk];
+    __shared__ double s_cx[kRmsdChunk], s_cy[kRmsdChunk];
     __shared__ int s_hit;
     const int na0 = min(*A.arch_n, A.capacity);
     int na = na0;                                      // identical in every thread
-    for (int c = 0; c < A.n_rep; ++c) {
-        const int state = A.is_new[c];                // uniform: not written in this pass
-        if (state == 0) continue;
-        const int n = A.atom_off[c + 1] - A.atom_off[c], t = A.rep_type[c];
-        const double4 cc = A.cen[c];
-        bool fresh = na < A.capacity;
-        if (state == 3 && fresh && na > na0) {
-            __syncthreads();                           // earlier appends and s_x reads are done
-            stage_candidate(A, c, s_x);
-            if (threadIdx.x == 0) s_hit = 0;
-            __syncthreads();
-            for (int k = na0 + threadIdx.x; k < na; k += blockDim.x)
-                if (A.arch_type[k] == t && same_as_archived(A, s_x, cc, n, k)) s_hit = 1;
-            __syncthreads();
-            fresh = s_hit == 0;
+    for (int c0 = 0; c0 < A.n_rep; c0 += kRmsdChunk) {
+        const int m = min(kRmsdChunk, A.n_rep - c0);
+        __syncthreads();                               // the previous chunk's LDS reads are done
+        for (int i = threadIdx.x; i < m; i += blockDim.x) {
+            const int c = c0 + i;
+            s_state[i] = A.is_new[c]; s_type[i] = A.rep_type[c];
+            s_n[i] = A.atom_off[c + 1] - A.atom_off[c];
+            const double4 cc = A.cen[c];
+            s_cx[i] = cc.x; s_cy[i] = cc.y;
         }
-        if (fresh) {
-            const int g0 = A.atom_off[c];
-            float *ap = A.arch_pos + (size_t)na * 3 * A.max_atoms;
-            for (int i = threadIdx.x; i < 3 * n; i += blockDim.x) {
-                const int a = i / 3, d = i - 3 * a;
-                ap[i] = A.pos[g0 + a + d * A.N];
+        __syncthreads();
+        for (int i = 0; i < m; ++i) {
+            const int state = s_state[i];
+            if (state == 0) continue;
+            const int c = c0 + i, n = s_n[i], t = s_type[i];
+            bool fresh = na < A.capacity;
+            if (state == 3 && fresh && na > na0) {
+                __syncthreads();                       // accepted list and s_x reads are done
+                stage_candidate(A, c, s_x);
+                if (threadIdx.x == 0) s_hit = 0;
+                __syncthreads();
+                const double cx = s_cx[i], cy = s_cy[i];
+                for (int k = threadIdx.x; k < na - na0; k += blockDim.x) {
+                    const int j = A.acc[k];
+                    if (A.rep_type[j] != t) continue;
+                    const double4 cj = A.cen[j];
+                    const int g0 = A.atom_off[j];
+                    if (same_minimum(A, s_x, cx, cy, n, A.pos + g0, A.pos + g0 + A.N, A.pos + g0 + 2 * A.N, 1,
+                                     cj.x, cj.y))
+                        s_hit = 1;
+                }
+                __syncthreads();
+                fresh = s_hit == 0;
             }
             if (threadIdx.x == 0) {
-                A.arch_cen[3 * (size_t)na] = cc.x; A.arch_cen[3 * (size_t)na + 1] = cc.y;
-                A.arch_cen[3 * (size_t)na + 2] = cc.z;
-                A.arch_type[na] = t;
+                A.cen[c].w = fresh ? (double)(na + 1) : 0.0;
+                if (fresh) A.acc[na - na0] = c;
             }
-            ++na;
+            if (fresh) ++na;
         }
-        if (threadIdx.x == 0) A.cen[c].w = fresh ? 1.0 : 0.0;
     }
     if (threadIdx.x == 0) *A.arch_n = na;
 }
 
-// is_new[c] = 1 for the survivors pass 3 accepted, 0 otherwise.
-__global__ void __launch_bounds__(256) k_rmsd_final(RmsdArgs A) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= A.n_rep) return;
-    A.is_new[c] = (A.is_new[c] != 0 && A.cen[c].w != 0.0) ? 1 : 0;
+// Appends the accepted candidates to their archive slots and writes is_new.
+__global__ void __launch_bounds__(128) k_rmsd_final(RmsdArgs A) {
+    const int c = blockIdx.x;
+    const double4 cc = A.cen[c];
+    const bool acc = A.is_new[c] != 0 && cc.w > 0.0;
+    if (threadIdx.x == 0) A.is_new[c] = acc ? 1 : 0;
+    if (!acc) return;
+    const int slot = (int)cc.w - 1;
+    const int g0 = A.atom_off[c], n = A.atom_off[c + 1] - g0;
+    float *ap = A.arch_pos + (size_t)slot * 3 * A.max_atoms;
+    for (int i = threadIdx.x; i < 3 * n; i += blockDim.x) {
+        const int a = i / 3, d = i - 3 * a;
+        ap[i] = A.pos[g0 + a + d * A.N];
+    }
+    if (threadIdx.x == 0) {
+        A.arch_cen[3 * (size_t)slot] = cc.x; A.arch_cen[3 * (size_t)slot + 1] = cc.y;
+        A.arch_cen[3 * (size_t)slot + 2] = cc.z;
+        A.arch_type[slot] = A.rep_type[c];
+    }
 }
 
 // ---------------------------------------------------------------- pose -> encoding
@@ -466,12 +545,19 @@ extern "C" gff_status gff_dedupe_energy(int n_new, const double *d_E, const int 
     if (n_new < 0 || capacity < 0 || !(tol >= 0.0)) return GFF_EINVAL;
     if (n_new > 0 && (!d_E || !d_type || !d_is_new)) return GFF_EINVAL;
     if (!d_arch_E || !d_arch_type || !d_arch_n) return GFF_EINVAL;
-    hipLaunchKernelGGL(k_dedupe, dim3(1), dim3(1024), 0, (hipStream_t)stream, n_new, d_E, d_type, d_ok, tol, capacity,
-                       d_arch_E, d_arch_type, d_arch_n, d_is_new);
+    if (n_new == 0) return GFF_OK;
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_dedupe_archive, dim3(n_new), dim3(256), 0, s, n_new, d_E, d_type, d_ok, tol, capacity,
+                       (const double *)d_arch_E, (const int *)d_arch_type, (const int *)d_arch_n, d_is_new);
+    hipLaunchKernelGGL(k_dedupe_pairs, dim3(n_new), dim3(256), 0, s, d_E, d_type, tol, d_is_new);
+    hipLaunchKernelGGL(k_dedupe_batch, dim3(1), dim3(1024), 0, s, n_new, d_E, d_type, tol, capacity, d_arch_E,
+                       d_arch_type, d_arch_n, d_is_new);
     return hip_status(hipGetLastError());
 }
 
-extern "C" size_t gff_dedupe_rmsd_workspace_bytes(int n_rep) { return n_rep > 0 ? (size_t)n_rep * sizeof(double4) : 0; }
+extern "C" size_t gff_dedupe_rmsd_workspace_bytes(int n_rep) {
+    return n_rep > 0 ? (size_t)n_rep * (sizeof(double4) + sizeof(int)) : 0;
+}
 
 extern "C" gff_status gff_dedupe_rmsd(const gff_plan *plan, const float *d_pos, const int *d_ok, float tol, float Lx,
                                       float Ly, int capacity, int max_atoms, float *d_arch_pos, double *d_arch_cen,
@@ -485,12 +571,13 @@ extern "C" gff_status gff_dedupe_rmsd(const gff_plan *plan, const float *d_pos, 
     if (!d_work || work_bytes < gff_dedupe_rmsd_workspace_bytes(plan->n_rep)) return GFF_EWORKSPACE;
     RmsdArgs A{plan->d_rep_type, plan->d_atom_off, d_ok, d_pos, plan->n_atoms, plan->n_rep, capacity, max_atoms,
                (double)Lx, (double)Ly, (double)tol * (double)tol, d_arch_pos, d_arch_cen, d_arch_type, d_arch_n,
-               d_is_new, static_cast<double4 *>(d_work)};
+               d_is_new, static_cast<double4 *>(d_work),
+               reinterpret_cast<int *>(static_cast<char *>(d_work) + (size_t)plan->n_rep * sizeof(double4))};
     hipStream_t s = (hipStream_t)stream;
     hipLaunchKernelGGL(k_rmsd_archive, dim3(plan->n_rep), dim3(256), 0, s, A);
     hipLaunchKernelGGL(k_rmsd_pairs, dim3(plan->n_rep), dim3(256), 0, s, A);
     hipLaunchKernelGGL(k_rmsd_batch, dim3(1), dim3(1024), 0, s, A);
-    hipLaunchKernelGGL(k_rmsd_final, dim3((plan->n_rep + 255) / 256), dim3(256), 0, s, A);
+    hipLaunchKernelGGL(k_rmsd_final, dim3(plan->n_rep), dim3(128), 0, s, A);
     return hip_status(hipGetLastError());
 }
 
