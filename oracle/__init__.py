@@ -37,7 +37,8 @@ PINS = {
     "nve_batch": "dt^2 scaling of the energy fluctuation (P9)",
     "philox4x32_10": "published known-answer vectors",
     "pose": "torsion set to target, rigid-body invariants",
-    "mlp": "FD gradient check (P12)",
+    "mlp": "FD gradient check (P12); one-path forward closed form; Adam constant-gradient closed form; "
+           "IMLE selection brute-force cases",
     "direct_images": "Morse image sums, 2D Ewald convergence, FD gradient",
     "langevin_batch": "velocity Verlet at zero friction, exact BAOAB harmonic moments",
     "sampling.dedupe_energy": "hand-worked discovery-order cases",

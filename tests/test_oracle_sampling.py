@@ -157,3 +157,64 @@ def test_normal_philox_moments():
     z = OS.normal_philox(40000, 9, 2)
     assert abs(z.mean()) < 0.02 and abs(z.std() - 1) < 0.02
     assert abs((z ** 4).mean() - 3) < 0.1
+
+
+def test_mlp_forward_path_closed_form():
+    """One live path through the four layers (input 0 -> unit 0 -> unit 0 -> unit 0 -> output
+    3, weights exactly representable in BF16, everything else zero): the output is the
+    composition silu(silu(silu(s x0 + b1) + b2) + b3) w4 + b4 of the scalar SiLU x/(1+e^-x);
+    with all weights zero the output is the last bias."""
+    n_types = 2
+    sizes = [(OS.DIMS[l + 1], OS.DIMS[l]) for l in range(4)]
+    n = sum(a * b + a for a, b in sizes) + n_types * 32
+    p = np.zeros(n)
+    o = 0
+    Ws, bs = [], []
+    for a, b in sizes:
+        Ws.append(o); o += a * b
+        bs.append(o); o += a
+    s, b1, b2, b3, w4, b4 = 1.5, 0.25, -0.5, 0.75, -2.0, 0.125
+    p[Ws[0] + 0 * 96 + 0] = s
+    p[bs[0] + 0] = b1
+    p[Ws[1] + 0] = 1.0; p[bs[1] + 0] = b2
+    p[Ws[2] + 0] = 1.0; p[bs[2] + 0] = b3
+    p[Ws[3] + 3 * 256 + 0] = w4; p[bs[3] + 3] = b4
+    noise = np.array([[0.7] + [0.3] * 63, [-1.9] + [5.0] * 63])
+    Y, _ = OS.forward(p, n_types, noise, np.array([0, 1]))
+    f = lambda z: z / (1.0 + np.exp(-z))
+    for r in range(2):
+        want = f(f(f(s * noise[r, 0] + b1) + b2) + b3) * w4 + b4
+        assert abs(Y[r, 3] - want) < 1e-14
+        others = np.delete(Y[r], 3)
+        assert np.abs(others).max() == 0.0
+    q = np.zeros(n); q[bs[3]:bs[3] + 41] = np.arange(41) * 0.5
+    Y0, _ = OS.forward(q, n_types, noise, np.array([1, 0]))
+    assert np.array_equal(Y0, np.tile(np.arange(41) * 0.5, (2, 1)))
+
+
+def test_adam_constant_gradient_closed_form():
+    """With a constant gradient the bias-corrected moments are exact (m_hat = g,
+    v_hat = g^2) at every step, so each Adam step moves a parameter by lr g / (|g| + eps)."""
+    g = np.array([0.3, -2.0, 1e-3, 0.0])
+    p0 = np.array([1.0, -1.0, 0.5, 2.0])
+    p, m, v = p0.copy(), np.zeros(4), np.zeros(4)
+    lr = 1e-2
+    for step in range(1, 51):
+        p, m, v = OS.adam(p, g, m, v, step, lr)
+        assert np.allclose(p, p0 - step * lr * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-13)
+
+
+def test_imle_select_brute_force_cases():
+    """The nearest candidate under the encoding distance: an exact copy of the target wins;
+    the quaternion block is compared up to sign (q and -q are one rotation); angle pairs
+    beyond the molecule's torsion count are ignored; ties go to the lowest index."""
+    rng = np.random.default_rng(2)
+    t = rng.normal(size=(3, 41))
+    cand = rng.normal(size=(3, 5, 41)) * 3.0
+    cand[0, 3] = t[0]                                    # exact copy
+    flip = t[1].copy(); flip[5:9] *= -1; cand[1, 2] = flip     # quaternion sign flipped
+    junk = t[2].copy(); junk[9 + 2 * 2:] += 50.0         # differs only beyond 2 torsions
+    cand[2, 1] = junk; cand[2, 4] = junk                 # tie: lowest index
+    best, d = OS.imle_select(cand, t, np.array([16, 16, 2]))
+    assert list(best) == [3, 2, 1]
+    assert d[0] == 0.0 and d[1] < 1e-24 and d[2] == 0.0
