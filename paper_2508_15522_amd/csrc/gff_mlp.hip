@@ -116,19 +116,30 @@ __device__ __forceinline__ float enc_dist(const float *y, const float *t, int T,
     return d;
 }
 
-// IMLE: for each target the nearest of its K candidate outputs (ties: lowest k).
-__global__ void k_imle_select(int n, int K, const float *cand, const float *target, const int *ntors, int *best,
-                              float *bestd) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int bk = 0;
+// IMLE: for each target the nearest of its K candidate outputs (ties: lowest k).  One
+// wavefront per target: lane l scores candidates l, l + 64, ..., then a butterfly keeps the
+// smaller distance, the lower index on ties (non-finite distances never win).
+__global__ void __launch_bounds__(256) k_imle_select(int n, int K, const float *cand, const float *target,
+                                                     const int *ntors, int *best, float *bestd) {
+    const int lane = threadIdx.x & 63;
+    const int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (i >= n) return;                                 // uniform across the wavefront
+    int bk = 0x7fffffff;
     float bd = 3.4e38f;
-    for (int k = 0; k < K; ++k) {
+    for (int k = lane; k < K; k += 64) {
         const float d = enc_dist(cand + ((long)i * K + k) * kOut, target + (long)i * kOut, ntors[i], nullptr);
         if (d < bd) { bd = d; bk = k; }
     }
-    best[i] = bk;
-    if (bestd) bestd[i] = bd;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        const float od = __shfl_xor(bd, o, 64);
+        const int ok = __shfl_xor(bk, o, 64);
+        if (od < bd || (od == bd && ok < bk)) { bd = od; bk = ok; }
+    }
+    if (lane == 0) {
+        best[i] = bk == 0x7fffffff ? 0 : bk;
+        if (bestd) bestd[i] = bd;
+    }
 }
 
 // dY = (2 / B) (Y - s t) on unmasked entries (s = quaternion sign of the nearer target);
@@ -162,23 +173,40 @@ __global__ void k_silu_back(long n, const float *dH, const float *Z, float *dZ, 
 }
 
 // column sums (bias gradients) in a fixed order: one thread per column
-__global__ void k_colsum(int B, int N, const float *X, long ld, float *out) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= N) return;
+// Column sums of a [B][N] matrix: one block per 64 columns, 16 row groups of 64 lanes each
+// (rows g, g + 16, ...), then the 16 partial sums of a column in a fixed order.
+__global__ void __launch_bounds__(1024) k_colsum(int B, int N, const float *X, long ld, float *out) {
+    __shared__ float s_p[16][64];
+    const int cx = threadIdx.x & 63, ry = threadIdx.x >> 6;
+    const int c = blockIdx.x * 64 + cx;
     float s = 0.f;
-    for (int b = 0; b < B; ++b) s += X[(long)b * ld + c];
-    out[c] = s;
+    if (c < N)
+        for (int b = ry; b < B; b += 16) s += X[(long)b * ld + c];
+    s_p[ry][cx] = s;
+    __syncthreads();
+    if (ry == 0 && c < N) {
+        float t = 0.f;
+        for (int g = 0; g < 16; ++g) t += s_p[g][cx];
+        out[c] = t;
+    }
 }
 
-// embedding gradient: per type, sum over samples of dX0[:, 64:96] (fixed order)
-__global__ void k_emb_grad(int B, int n_types, const int *type, const float *dX0, float *gemb) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_types * kEmb) return;
-    const int t = i / kEmb, c = i % kEmb;
+// embedding gradient: per type, sum over samples of dX0[:, 64:96]; one block per type,
+// 32 row groups of 32 lanes (rows g, g + 32, ...), partial sums combined in a fixed order
+__global__ void __launch_bounds__(1024) k_emb_grad(int B, int n_types, const int *type, const float *dX0,
+                                                   float *gemb) {
+    __shared__ float s_p[32][kEmb];
+    const int t = blockIdx.x, c = threadIdx.x % kEmb, ry = threadIdx.x / kEmb;
     float s = 0.f;
-    for (int b = 0; b < B; ++b)
+    for (int b = ry; b < B; b += 32)
         if (type[b] == t) s += dX0[(long)b * kIn + kNoise + c];
-    gemb[i] = s;
+    s_p[ry][c] = s;
+    __syncthreads();
+    if (ry == 0) {
+        float u = 0.f;
+        for (int g = 0; g < 32; ++g) u += s_p[g][c];
+        gemb[t * kEmb + c] = u;
+    }
 }
 
 __global__ void k_adam(long n, float *p, const float *g, float *m, float *v, float lr, float b1, float b2, float eps,
@@ -374,7 +402,7 @@ extern "C" gff_status gff_mlp_train_step(gff_mlp *m, int batch, const float *d_n
     float *g = m->d_g;
     gemm(s, kOut, kWidth, B, k.dYb, 1, kOut, k.H[2], kWidth, 1, nullptr, 0, g + m->off_W[3], kWidth, nullptr, 0,
          nullptr, 0);
-    hipLaunchKernelGGL(k_colsum, dim3(1), dim3(64), 0, s, B, kOut, k.dY, (long)kOut, g + m->off_b[3]);
+    hipLaunchKernelGGL(k_colsum, dim3(1), dim3(1024), 0, s, B, kOut, k.dY, (long)kOut, g + m->off_b[3]);
     gemm(s, B, kWidth, kOut, k.dYb, kOut, 1, m->d_pb + m->off_W[3], kWidth, 1, nullptr, 0, k.dH, kWidth, nullptr, 0,
          nullptr, 0);
     for (int l = 2; l >= 0; --l) {
@@ -384,13 +412,14 @@ extern "C" gff_status gff_mlp_train_step(gff_mlp *m, int batch, const float *d_n
         const unsigned short *Xin = l == 0 ? k.X0 : k.H[l - 1];
         // dW_l = dZ^T X_in  [dout x din]
         gemm(s, dout, din, B, k.dZb, 1, dout, Xin, din, 1, nullptr, 0, g + m->off_W[l], din, nullptr, 0, nullptr, 0);
-        hipLaunchKernelGGL(k_colsum, dim3(blocks(dout, 64)), dim3(64), 0, s, B, dout, k.dZ, (long)dout, g + m->off_b[l]);
+        hipLaunchKernelGGL(k_colsum, dim3(blocks(dout, 64)), dim3(1024), 0, s, B, dout, k.dZ, (long)dout,
+                           g + m->off_b[l]);
         // dX_in = dZ W_l [B x din]
         float *dX = l == 0 ? k.dX0 : k.dH;
         gemm(s, B, din, dout, k.dZb, dout, 1, m->d_pb + m->off_W[l], din, 1, nullptr, 0, dX, din, nullptr, 0, nullptr,
              0);
     }
-    hipLaunchKernelGGL(k_emb_grad, dim3(blocks(m->n_types * kEmb, 64)), dim3(64), 0, s, B, m->n_types, d_type, k.dX0,
+    hipLaunchKernelGGL(k_emb_grad, dim3(m->n_types), dim3(1024), 0, s, B, m->n_types, d_type, k.dX0,
                        g + m->off_emb);
     if (lr > 0.f) {
         m->step += 1;
@@ -408,7 +437,7 @@ extern "C" gff_status gff_imle_select(int n, int K, const float *d_cand_out, con
                                       int *d_best, float *d_best_dist, void *stream) {
     if (n < 0 || K < 1 || (n > 0 && (!d_cand_out || !d_target || !d_ntors || !d_best))) return GFF_EINVAL;
     if (n == 0) return GFF_OK;
-    hipLaunchKernelGGL(k_imle_select, dim3(blocks(n, 256)), dim3(256), 0, (hipStream_t)stream, n, K, d_cand_out,
+    hipLaunchKernelGGL(k_imle_select, dim3(blocks(n, 4)), dim3(256), 0, (hipStream_t)stream, n, K, d_cand_out,
                        d_target, d_ntors, d_best, d_best_dist);
     return hip_status(hipGetLastError());
 }
