@@ -471,6 +471,18 @@ gff_status gff_normal_philox(long n, uint64_t seed, uint32_t round, float *d_out
 gff_status gff_gather_rows(int n, int len, const float *d_src, int K, const int *d_idx, float *d_dst, void *stream);
 /* C [M][N] (FP32) = A [M][K] B [K][N] (BF16, row-major) on the MFMA tile used by the MLP */
 gff_status gff_gemm_bf16(int M, int N, int K, const void *d_A, const void *d_B, float *d_C, void *stream);
+/* The same tile with element strides: C[m*ldc + n] = sum_k A[m*sam + k*sak] B[k*sbk + n*sbn]
+ * (BF16 inputs as raw 16-bit words, FP32 output; strides >= 1, ldc >= N).  Operands
+ * contiguous along k or along their row index are read with 16-byte loads when 16-byte
+ * aligned.  With d_work (at least gff_gemm_bf16_workspace_bytes(), device memory owned by the
+ * caller, overwritten) a product of fewer than 64 output tiles of 64 x 64 and K >= 128 splits
+ * K over blocks, the FP32 partial sums added in slice order by a second kernel; d_work NULL:
+ * one pass over K.  Results are deterministic either way.  GFF_EWORKSPACE when work_bytes is
+ * too small; asynchronous on `stream`. */
+size_t gff_gemm_bf16_workspace_bytes(void);
+gff_status gff_gemm_bf16_strided(int M, int N, int K, const void *d_A, long sam, long sak, const void *d_B,
+                                 long sbk, long sbn, float *d_C, long ldc, void *d_work, size_t work_bytes,
+                                 void *stream);
 
 #ifdef __cplusplus
 }

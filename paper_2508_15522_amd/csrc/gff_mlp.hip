@@ -6,8 +6,13 @@
 // GEMM: C[M x N] = A[M x K] B[K x N], A and B in BF16 read through arbitrary element strides
 // (so transposed operands need no copies), tiles of 64 x 64 per 256-thread block staged
 // through LDS, each wave owning a 32 x 32 sub-tile of 2 x 2 v_mfma_f32_16x16x32_bf16.
-// Every output element is reduced over K in one fixed order: results are deterministic.
+// Operands contiguous along k or along their row index are staged with 16-byte loads, the
+// next k-slice's loads in flight during the current slice's MFMAs.  Products with few
+// output tiles and a long K (the weight gradients) split K over blocks into FP32 partials
+// that a second kernel sums in split order.  Every output element is reduced in one fixed
+// order: results are deterministic.
 #include "gff_internal.hpp"
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -38,26 +43,87 @@ struct GemmArgs {
     float *Cpre; long ldp;                       // FP32 pre-activation copy, or null
     unsigned short *Cb; long ldb;                // BF16 output (after activation), or null
     int accumulate;                              // C += result (FP32 output only)
+    int modeA, modeB;                            // staging layout of each operand (StageMode)
+    int kchunk;                                  // K range of one blockIdx.z (a multiple of 32)
+    float *part;                                 // split K: partial sums [gridDim.z][M][N]; null: none
 };
+
+// How a thread stages its 8 elements of a 64-row x 32-k operand slice.  K_*: 8 consecutive k
+// of one row (thread t: row t/4, k 8(t%4)..+7); R_*: 8 consecutive rows at one k (thread t:
+// k t/8, rows 8(t%8)..+7).  *_VEC: one 16-byte load where the 8 elements are in range.
+enum StageMode { K_ELEM = 0, K_VEC = 1, R_VEC = 2, R_ELEM = 3 };
+
+// Load this thread's 8 elements of X(row, k) = X[row*srow + k*sk], rows [r0, r0+64) of R,
+// k [k0, k0+32) of those below kend; zero outside.
+__device__ __forceinline__ uint4 stage_load(const unsigned short *X, long srow, long sk, int mode, int R, int r0,
+                                            int k0, int kend, int tid) {
+    const bool kmaj = mode == K_ELEM || mode == K_VEC;
+    const int r = r0 + (kmaj ? tid >> 2 : 8 * (tid & 7));
+    const int k = k0 + (kmaj ? 8 * (tid & 3) : tid >> 3);
+    const long base = (long)r * srow + (long)k * sk;
+    if (mode == K_VEC && r < R && k + 8 <= kend) return *reinterpret_cast<const uint4 *>(X + base);
+    if (mode == R_VEC && r + 8 <= R && k < kend) return *reinterpret_cast<const uint4 *>(X + base);
+    unsigned short e[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int ri = kmaj ? r : r + i, ki = kmaj ? k + i : k;
+        e[i] = (ri < R && ki < kend) ? X[(long)ri * srow + (long)ki * sk] : (unsigned short)0;
+    }
+    uint4 v;
+    v.x = e[0] | ((unsigned)e[1] << 16); v.y = e[2] | ((unsigned)e[3] << 16);
+    v.z = e[4] | ((unsigned)e[5] << 16); v.w = e[6] | ((unsigned)e[7] << 16);
+    return v;
+}
+
+// Store the thread's 8 elements into the [row][k] LDS slice.
+__device__ __forceinline__ void stage_store(unsigned short (*S)[40], int mode, int tid, uint4 v) {
+    if (mode == K_ELEM || mode == K_VEC) {
+        *reinterpret_cast<uint4 *>(&S[tid >> 2][8 * (tid & 3)]) = v;
+    } else {
+        const int k = tid >> 3, r = 8 * (tid & 7);
+        const unsigned w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            S[r + 2 * i][k] = (unsigned short)(w[i] & 0xffffu);
+            S[r + 2 * i + 1][k] = (unsigned short)(w[i] >> 16);
+        }
+    }
+}
+
+// Bias, activation and the stores of one output element.
+__device__ __forceinline__ void gemm_epilogue(const GemmArgs &g, int m, int n, float z) {
+    if (g.bias) z += g.bias[n];
+    if (g.Cpre) g.Cpre[m * g.ldp + n] = z;
+    const float y = g.act == 1 ? z / (1.f + __expf(-z)) : z;
+    if (g.C) {
+        if (g.accumulate) g.C[m * g.ldc + n] += y;
+        else g.C[m * g.ldc + n] = y;
+    }
+    if (g.Cb) g.Cb[m * g.ldb + n] = f2bf(y);
+}
 
 __global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
     __shared__ __align__(16) unsigned short sA[64][40];   // [m][k], row padded against bank conflicts
     __shared__ __align__(16) unsigned short sB[64][40];   // [n][k]
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+    // tiles that share rows of A go to one XCD (workgroups are dealt to the 8 XCDs in turn)
+    const int nt = gridDim.x * gridDim.y, lin = blockIdx.y * gridDim.x + blockIdx.x, per = nt >> 3;
+    const int tix = lin < 8 * per ? (lin & 7) * per + (lin >> 3) : lin;
+    const int m0 = (tix / gridDim.x) * 64, n0 = (tix % gridDim.x) * 64;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    const int kb = blockIdx.z * g.kchunk, ke = min(g.K, kb + g.kchunk);
     f32x4 acc[2][2];
     for (int i = 0; i < 2; ++i) for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < g.K; k0 += 32) {
-        // stage 64 x 32 of A and 32 x 64 of B (zero outside the matrices)
-        for (int e = tid; e < 64 * 32; e += 256) {
-            const int r = e >> 5, c = e & 31;
-            const int m = m0 + r, k = k0 + c;
-            sA[r][c] = (m < g.M && k < g.K) ? g.A[m * g.sam + k * g.sak] : (unsigned short)0;
-            const int n = n0 + r;
-            sB[r][c] = (n < g.N && k < g.K) ? g.B[k * g.sbk + n * g.sbn] : (unsigned short)0;
-        }
+    uint4 va = stage_load(g.A, g.sam, g.sak, g.modeA, g.M, m0, kb, ke, tid);
+    uint4 vb = stage_load(g.B, g.sbn, g.sbk, g.modeB, g.N, n0, kb, ke, tid);
+    for (int k0 = kb; k0 < ke; k0 += 32) {
+        stage_store(sA, g.modeA, tid, va);
+        stage_store(sB, g.modeB, tid, vb);
         __syncthreads();
+        if (k0 + 32 < ke) {                         // next slice in flight during the MFMAs
+            va = stage_load(g.A, g.sam, g.sak, g.modeA, g.M, m0, k0 + 32, ke, tid);
+            vb = stage_load(g.B, g.sbn, g.sbk, g.modeB, g.N, n0, k0 + 32, ke, tid);
+        }
         const int row = lane & 15, kq = (lane >> 4) * 8;
         bf16x8 a[2], b[2];
         for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const bf16x8 *>(&sA[wm + 16 * i + row][kq]);
@@ -68,22 +134,26 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
         __syncthreads();
     }
     // D layout: lane holds rows 4*(lane/16) + r, column lane % 16 of each 16 x 16 tile
+    float *part = g.part ? g.part + (size_t)blockIdx.z * g.M * g.N : nullptr;
     for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j)
             for (int r = 0; r < 4; ++r) {
                 const int m = m0 + wm + 16 * i + 4 * (lane >> 4) + r;
                 const int n = n0 + wn + 16 * j + (lane & 15);
                 if (m >= g.M || n >= g.N) continue;
-                float z = acc[i][j][r];
-                if (g.bias) z += g.bias[n];
-                if (g.Cpre) g.Cpre[m * g.ldp + n] = z;
-                const float y = g.act == 1 ? z / (1.f + __expf(-z)) : z;
-                if (g.C) {
-                    if (g.accumulate) g.C[m * g.ldc + n] += y;
-                    else g.C[m * g.ldc + n] = y;
-                }
-                if (g.Cb) g.Cb[m * g.ldb + n] = f2bf(y);
+                if (part) part[(size_t)m * g.N + n] = acc[i][j][r];
+                else gemm_epilogue(g, m, n, acc[i][j][r]);
             }
+}
+
+// Split K: the partial sums of the gridDim.z slices added in slice order, then the epilogue.
+__global__ void k_splitk_sum(GemmArgs g, int splits) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long mn = (long)g.M * g.N;
+    if (i >= mn) return;
+    float z = 0.f;
+    for (int s = 0; s < splits; ++s) z += g.part[s * mn + i];
+    gemm_epilogue(g, (int)(i / g.N), (int)(i % g.N), z);
 }
 
 __global__ void k_to_bf16(const float *x, unsigned short *y, long n) {
@@ -240,11 +310,34 @@ __global__ void k_normal(long n, uint32_t k0, uint32_t k1, uint32_t round, float
 
 static unsigned blocks(long n, int t) { return (unsigned)((n + t - 1) / t); }
 
+constexpr int kSplitMax = 16;                 // split-K slices at most
+constexpr size_t kPartFloats = (size_t)kSplitMax * kWidth * kWidth;   // partials of the largest weight gradient
+
+static int stage_mode(const unsigned short *X, long srow, long sk) {
+    const bool al = ((uintptr_t)X & 15) == 0;
+    if (sk == 1) return al && srow % 8 == 0 ? K_VEC : K_ELEM;
+    if (srow == 1) return al && sk % 8 == 0 ? R_VEC : R_ELEM;
+    return K_ELEM;
+}
+
+// part: FP32 scratch for split-K partial sums (kPartFloats), or null for no split.
 static void gemm(hipStream_t s, int M, int N, int K, const unsigned short *A, long sam, long sak,
                  const unsigned short *B, long sbk, long sbn, const float *bias, int act, float *C, long ldc,
-                 float *Cpre, long ldp, unsigned short *Cb, long ldb, int accumulate = 0) {
-    GemmArgs g{M, N, K, A, sam, sak, B, sbk, sbn, bias, act, C, ldc, Cpre, ldp, Cb, ldb, accumulate};
-    hipLaunchKernelGGL(k_gemm_bf16, dim3((N + 63) / 64, (M + 63) / 64), dim3(256), 0, s, g);
+                 float *Cpre, long ldp, unsigned short *Cb, long ldb, int accumulate = 0, float *part = nullptr) {
+    const int gx = (N + 63) / 64, gy = (M + 63) / 64;
+    int splits = 1;
+    if (part && gx * gy < 64 && K >= 128) {
+        splits = std::min(kSplitMax, std::min(K / 64, (512 + gx * gy - 1) / (gx * gy)));
+        if ((size_t)splits * M * N > kPartFloats) splits = 1;
+    }
+    const int kchunk = splits > 1 ? ((K + splits - 1) / splits + 31) / 32 * 32 : std::max(K, 32);
+    splits = (K + kchunk - 1) / kchunk;
+    if (splits < 1) splits = 1;
+    GemmArgs g{M, N, K, A, sam, sak, B, sbk, sbn, bias, act, C, ldc, Cpre, ldp, Cb, ldb, accumulate,
+               stage_mode(A, sam, sak), stage_mode(B, sbn, sbk), kchunk, splits > 1 ? part : nullptr};
+    hipLaunchKernelGGL(k_gemm_bf16, dim3(gx, gy, splits), dim3(256), 0, s, g);
+    if (splits > 1)
+        hipLaunchKernelGGL(k_splitk_sum, dim3(blocks((long)M * N, 256)), dim3(256), 0, s, g, splits);
 }
 
 }  // namespace gff
@@ -327,18 +420,19 @@ extern "C" gff_status gff_mlp_get_params(const gff_mlp *m, float *params_h, floa
 
 // workspace: X0 (bf16 B x 96), H1..H3 (bf16 B x 256 each), Z1..Z3 (f32 B x 256 each),
 // then for the backward pass dY (f32 B x 41), dYb (bf16), dH / dZ (f32 B x 256), dZb (bf16),
-// dX0 (f32 B x 96), loss (f32 B)
+// dX0 (f32 B x 96), loss (f32 B), split-K partial sums of the weight gradients
 static size_t a256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 extern "C" size_t gff_mlp_workspace_bytes(int batch) {
     const size_t B = (size_t)(batch > 0 ? batch : 0);
     return a256(B * kIn * 2) + 3 * a256(B * kWidth * 2) + 3 * a256(B * kWidth * 4) + a256(B * kOut * 4) +
-           a256(B * kOut * 2) + 2 * a256(B * kWidth * 4) + a256(B * kWidth * 2) + a256(B * kIn * 4) + a256(B * 4);
+           a256(B * kOut * 2) + 2 * a256(B * kWidth * 4) + a256(B * kWidth * 2) + a256(B * kIn * 4) + a256(B * 4) +
+           a256(kPartFloats * 4);
 }
 
 struct MlpWork {
     unsigned short *X0, *H[3];
-    float *Z[3], *dY; unsigned short *dYb; float *dH, *dZ; unsigned short *dZb; float *dX0, *loss;
+    float *Z[3], *dY; unsigned short *dYb; float *dH, *dZ; unsigned short *dZb; float *dX0, *loss, *part;
 };
 
 static MlpWork carve(void *w, int batch) {
@@ -354,18 +448,21 @@ static MlpWork carve(void *w, int batch) {
     k.dZ = (float *)p; p += a256(B * kWidth * 4);
     k.dZb = (unsigned short *)p; p += a256(B * kWidth * 2);
     k.dX0 = (float *)p; p += a256(B * kIn * 4);
-    k.loss = (float *)p;
+    k.loss = (float *)p; p += a256(B * 4);
+    k.part = (float *)p;
     return k;
 }
 
-static void forward(gff_mlp *m, hipStream_t s, int B, const float *noise, const int *type, float *out, MlpWork &k) {
+// keep_pre: store the pre-activations Z (the backward pass needs them; inference does not)
+static void forward(gff_mlp *m, hipStream_t s, int B, const float *noise, const int *type, float *out, MlpWork &k,
+                    bool keep_pre) {
     hipLaunchKernelGGL(k_input, dim3(blocks((long)B * kIn, 256)), dim3(256), 0, s, B, noise, type,
                        m->d_p + m->off_emb, k.X0);
     const unsigned short *X = k.X0;
     for (int l = 0; l < 3; ++l) {
         const int din = kDims[l], dout = kDims[l + 1];
-        gemm(s, B, dout, din, X, din, 1, m->d_pb + m->off_W[l], 1, din, m->d_p + m->off_b[l], 1, nullptr, 0, k.Z[l],
-             dout, k.H[l], dout);
+        gemm(s, B, dout, din, X, din, 1, m->d_pb + m->off_W[l], 1, din, m->d_p + m->off_b[l], 1, nullptr, 0,
+             keep_pre ? k.Z[l] : nullptr, dout, k.H[l], dout);
         X = k.H[l];
     }
     gemm(s, B, kOut, kWidth, X, kWidth, 1, m->d_pb + m->off_W[3], 1, kWidth, m->d_p + m->off_b[3], 0, out, kOut,
@@ -378,7 +475,7 @@ extern "C" gff_status gff_mlp_forward(gff_mlp *m, int batch, const float *d_nois
     if (batch == 0) return GFF_OK;
     if (!d_work || work_bytes < gff_mlp_workspace_bytes(batch)) return GFF_EWORKSPACE;
     MlpWork k = carve(d_work, batch);
-    forward(m, (hipStream_t)stream, batch, d_noise, d_type, d_out, k);
+    forward(m, (hipStream_t)stream, batch, d_noise, d_type, d_out, k, false);
     return hip_status(hipGetLastError());
 }
 
@@ -394,14 +491,14 @@ extern "C" gff_status gff_mlp_train_step(gff_mlp *m, int batch, const float *d_n
     hipStream_t s = (hipStream_t)stream;
     const int B = batch;
     MlpWork k = carve(d_work, batch);
-    forward(m, s, B, d_noise, d_type, d_out, k);
+    forward(m, s, B, d_noise, d_type, d_out, k, true);
     hipLaunchKernelGGL(k_mse_grad, dim3(blocks(B, 256)), dim3(256), 0, s, B, d_out, d_target, d_ntors, k.dY,
                        d_loss ? d_loss : k.loss);
     hipLaunchKernelGGL(k_to_bf16, dim3(blocks((long)B * kOut, 256)), dim3(256), 0, s, k.dY, k.dYb, (long)B * kOut);
     // layer 4: dW4 = dY^T H3, db4 = colsum dY, dH3 = dY W4
     float *g = m->d_g;
     gemm(s, kOut, kWidth, B, k.dYb, 1, kOut, k.H[2], kWidth, 1, nullptr, 0, g + m->off_W[3], kWidth, nullptr, 0,
-         nullptr, 0);
+         nullptr, 0, 0, k.part);
     hipLaunchKernelGGL(k_colsum, dim3(1), dim3(1024), 0, s, B, kOut, k.dY, (long)kOut, g + m->off_b[3]);
     gemm(s, B, kWidth, kOut, k.dYb, kOut, 1, m->d_pb + m->off_W[3], kWidth, 1, nullptr, 0, k.dH, kWidth, nullptr, 0,
          nullptr, 0);
@@ -411,7 +508,8 @@ extern "C" gff_status gff_mlp_train_step(gff_mlp *m, int batch, const float *d_n
                            k.Z[l], k.dZ, k.dZb);
         const unsigned short *Xin = l == 0 ? k.X0 : k.H[l - 1];
         // dW_l = dZ^T X_in  [dout x din]
-        gemm(s, dout, din, B, k.dZb, 1, dout, Xin, din, 1, nullptr, 0, g + m->off_W[l], din, nullptr, 0, nullptr, 0);
+        gemm(s, dout, din, B, k.dZb, 1, dout, Xin, din, 1, nullptr, 0, g + m->off_W[l], din, nullptr, 0, nullptr, 0, 0,
+             k.part);
         hipLaunchKernelGGL(k_colsum, dim3(blocks(dout, 64)), dim3(1024), 0, s, B, dout, k.dZ, (long)dout,
                            g + m->off_b[l]);
         // dX_in = dZ W_l [B x din]
@@ -466,6 +564,21 @@ extern "C" gff_status gff_gather_rows(int n, int len, const float *d_src, int K,
     if (n == 0) return GFF_OK;
     hipLaunchKernelGGL(k_gather_rows, dim3(blocks((long)n * len, 256)), dim3(256), 0, (hipStream_t)stream, n, len,
                        d_src, K, d_idx, d_dst);
+    return hip_status(hipGetLastError());
+}
+
+extern "C" size_t gff_gemm_bf16_workspace_bytes(void) { return kPartFloats * sizeof(float); }
+
+// strided GEMM on the MLP's tile, split K when a workspace is given
+extern "C" gff_status gff_gemm_bf16_strided(int M, int N, int K, const void *d_A, long sam, long sak, const void *d_B,
+                                            long sbk, long sbn, float *d_C, long ldc, void *d_work, size_t work_bytes,
+                                            void *stream) {
+    if (M < 0 || N < 0 || K < 0 || !d_A || !d_B || !d_C) return GFF_EINVAL;
+    if (sam < 1 || sak < 1 || sbk < 1 || sbn < 1 || ldc < N) return GFF_EINVAL;
+    if (d_work && work_bytes < gff_gemm_bf16_workspace_bytes()) return GFF_EWORKSPACE;
+    if (M == 0 || N == 0) return GFF_OK;
+    gemm((hipStream_t)stream, M, N, K, (const unsigned short *)d_A, sam, sak, (const unsigned short *)d_B, sbk, sbn,
+         nullptr, 0, d_C, ldc, nullptr, 0, nullptr, 0, 0, (float *)d_work);
     return hip_status(hipGetLastError());
 }
 

@@ -321,7 +321,8 @@ def relax_batch_direct(direct, topo, plan, params, st, d_E_rep, d_fnorm, d_steps
 EXPORTS += ["gff_propose_uniform", "gff_pose_from_dof", "gff_encode_pose", "gff_decode_dof", "gff_dedupe_energy",
             "gff_mlp_n_params", "gff_mlp_create", "gff_mlp_destroy", "gff_mlp_get_params", "gff_mlp_workspace_bytes",
             "gff_mlp_forward", "gff_mlp_train_step", "gff_imle_select", "gff_normal_philox", "gff_gemm_bf16",
-            "gff_gather_rows", "gff_relax_graph_create", "gff_graph_launch", "gff_graph_destroy", "gff_autotune",
+            "gff_gemm_bf16_strided", "gff_gemm_bf16_workspace_bytes", "gff_gather_rows", "gff_relax_graph_create",
+            "gff_graph_launch", "gff_graph_destroy", "gff_autotune",
             "gff_refill", "gff_dedupe_rmsd", "gff_dedupe_rmsd_workspace_bytes"]
 N_ENC = 41
 
@@ -390,6 +391,22 @@ def gemm_bf16(d_A, d_B, d_C, stream=None):
     M, K = d_A.shape
     N = d_B.shape[1]
     check(lib().gff_gemm_bf16(C.c_int(M), C.c_int(N), C.c_int(K), _ptr(d_A), _ptr(d_B), _ptr(d_C), _stream(stream)))
+
+
+def gemm_bf16_workspace_bytes():
+    L = lib()
+    L.gff_gemm_bf16_workspace_bytes.restype = C.c_size_t
+    return L.gff_gemm_bf16_workspace_bytes()
+
+
+def gemm_bf16_strided(M, N, K, d_A, sam, sak, d_B, sbk, sbn, d_C, ldc, d_work=None, stream=None):
+    """C[m*ldc + n] = sum_k A[m*sam + k*sak] B[k*sbk + n*sbn] (element strides; BF16 words in
+    int16 tensors, FP32 out); with d_work (uint8, gemm_bf16_workspace_bytes()) K may split."""
+    check(lib().gff_gemm_bf16_strided(C.c_int(M), C.c_int(N), C.c_int(K), _ptr(d_A), C.c_long(sam), C.c_long(sak),
+                                      _ptr(d_B), C.c_long(sbk), C.c_long(sbn), _ptr(d_C), C.c_long(ldc),
+                                      _ptr(d_work),
+                                      C.c_size_t(0 if d_work is None else d_work.numel() * d_work.element_size()),
+                                      _stream(stream)))
 
 
 def imle_select(d_cand, d_target, d_ntors, d_best, d_bestd=None, stream=None):

@@ -314,12 +314,15 @@ def train_imle(mlp, targets, ntors, types, steps, batch=1024, K=64, lr=1e-3, see
     out = torch.empty(batch, 41, device="cuda")
     loss = torch.empty(batch, device="cuda")
     hist = []
+    # every step's batch drawn up front and copied once, so that the loop queues work without
+    # waiting for the device
+    if cdf is None:
+        picks = rng.integers(0, m, (steps, batch))
+    else:
+        picks = np.minimum(np.searchsorted(cdf, rng.random((steps, batch)) * cdf[-1], side="right"), m - 1)
+    picks = torch.from_numpy(np.ascontiguousarray(picks, np.int64)).cuda()
     for s in range(steps):
-        if cdf is None:
-            pick = rng.integers(0, m, batch)
-        else:
-            pick = np.minimum(np.searchsorted(cdf, rng.random(batch) * cdf[-1], side="right"), m - 1)
-        idx = torch.from_numpy(pick).cuda()
+        idx = picks[s]
         tg = targets.index_select(0, idx).contiguous()
         nt = ntors.index_select(0, idx).contiguous()
         ty = types.index_select(0, idx).contiguous()

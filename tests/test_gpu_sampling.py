@@ -226,6 +226,65 @@ def test_gemm_bf16_mfma_layout(shape):
     assert err < 1e-5 * np.sqrt(K) * np.abs(ref).max() + 1e-5, err
 
 
+def _strided_case(rng, M, N, K, sam, sak, sbk, sbn, offA=0, offB=0):
+    """Flat BF16 buffers holding A(m,k) at offA + m*sam + k*sak and B(k,n) at offB + k*sbk + n*sbn
+    (other words random too), and the exact FP64 product of the two logical matrices."""
+    na = offA + (M - 1) * sam + (K - 1) * sak + 1 if M and K else offA + 1
+    nb = offB + (K - 1) * sbk + (N - 1) * sbn + 1 if N and K else offB + 1
+    fa, fb = _bf16_bits(rng.normal(size=na)), _bf16_bits(rng.normal(size=nb))
+    m, k, n = np.arange(M)[:, None], np.arange(K)[None, :], np.arange(N)[None, :]
+    A = fa[offA + m * sam + k * sak] if K else np.zeros((M, 0), np.uint16)
+    B = fb[offB + np.arange(K)[:, None] * sbk + n * sbn] if K else np.zeros((0, N), np.uint16)
+    to64 = lambda w: (w.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    return fa, fb, to64(A) @ to64(B)
+
+
+@pytest.mark.parametrize("case", [
+    # (M, N, K, sam, sak, sbk, sbn, offA, offB, split): the staging layouts and the split-K path
+    (200, 200, 1000, 1, 200, 200, 1, 0, 0, True),      # A and B contiguous along rows, K split, ragged tail
+    (200, 200, 1000, 1, 200, 200, 1, 0, 0, False),     # the same in one pass over K
+    (41, 256, 1024, 1, 41, 256, 1, 0, 0, True),        # A rows of 41: element loads, K split in 16
+    (130, 72, 256, 256, 1, 1, 259, 0, 0, True),        # A along k; B along k with an odd stride
+    (96, 64, 320, 320, 1, 64, 1, 1, 3, True),          # both operands misaligned by whole words
+    (64, 40, 0, 8, 1, 40, 1, 0, 0, True),              # K = 0: zeros
+])
+def test_gemm_bf16_strided_layouts_and_split(case):
+    """Every staging layout (16-byte loads along k or along rows, element loads for odd
+    strides or misaligned bases) and the split-K reduction against the exact product."""
+    M, N, K, sam, sak, sbk, sbn, offA, offB, split = case
+    announce(f"gemm strided {case}")
+    rng = np.random.default_rng(M * 7 + N + K)
+    fa, fb, ref = _strided_case(rng, M, N, K, sam, sak, sbk, sbn, offA, offB)
+    dA = torch.from_numpy(fa.view(np.int16)).cuda()[offA:]
+    dB = torch.from_numpy(fb.view(np.int16)).cuda()[offB:]
+    ldc = N + 5
+    dC = torch.full((M, ldc), 7.0, device="cuda")
+    work = torch.empty(G.gemm_bf16_workspace_bytes(), dtype=torch.uint8, device="cuda") if split else None
+    G.gemm_bf16_strided(M, N, K, dA, sam, sak, dB, sbk, sbn, dC, ldc, work)
+    torch.cuda.synchronize()
+    C = dC.cpu().numpy()
+    err = np.abs(C[:, :N] - ref).max() if K else np.abs(C[:, :N]).max()
+    assert err <= 1e-5 * np.sqrt(max(K, 1)) * (np.abs(ref).max() if K else 0.0) + 1e-5, err
+    assert (C[:, N:] == 7.0).all()                       # the row padding is left alone
+    if split:                                            # deterministic: a second call agrees bit for bit
+        dC2 = torch.zeros_like(dC)
+        G.gemm_bf16_strided(M, N, K, dA, sam, sak, dB, sbk, sbn, dC2, ldc, work)
+        torch.cuda.synchronize()
+        assert torch.equal(dC[:, :N], dC2[:, :N])
+
+
+def test_gemm_bf16_strided_rejects_invalid_arguments():
+    dA = torch.zeros(64 * 64, dtype=torch.int16, device="cuda")
+    dC = torch.empty(64, 64, device="cuda")
+    small = torch.empty(G.gemm_bf16_workspace_bytes() - 4, dtype=torch.uint8, device="cuda")
+    for bad in (dict(sam=0), dict(sak=-1), dict(ldc=63)):
+        a = dict(sam=64, sak=1, ldc=64); a.update(bad)
+        with pytest.raises(G.GffError):
+            G.gemm_bf16_strided(64, 64, 64, dA, a["sam"], a["sak"], dA, 64, 1, dC, a["ldc"])
+    with pytest.raises(G.GffError):
+        G.gemm_bf16_strided(64, 64, 64, dA, 64, 1, dA, 64, 1, dC, 64, small)
+
+
 def test_normal_philox_parity():
     n = 10001
     z = torch.empty(n, device="cuda")
