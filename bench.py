@@ -40,11 +40,13 @@ COUNTER_SCALE = {"fetch": 2.0, "write": 1.0}
 MEASURED_TRAFFIC = {
     ("f32", 16384, 5000, 192): {
         "sources": {"paper_2508_15522_amd/csrc/gff_relax.hip":
-                    "dbf5c9473d39d40af71b5502b2d8b731e98a2e406f7ddf493044987ca2b82111",
+                    "c723c7e4d7803785415e2a55e8c9bfa866bbb4049cfe618010dfe194b124d842",
                     "paper_2508_15522_amd/csrc/gff_internal.hpp":
-                    "56468c79b1c704b1db9f8607714a5d167a4691f89ff6d5a71d11baaf78e37ac9"},
-        "fetch_kib": 291617255.5625, "write_kib": 11595372.625,
-        "valu_insts": 204741970915.0,          # SQ_INSTS_VALU (wave instructions) of the launch
+                    "61bc1f04b2dc056901d1a189d182f83d4b4d3f1e8b212e9b3f571786f724024f",
+                    "paper_2508_15522_amd/csrc/gff_host.hip":
+                    "5e7ba03db58d76beb6af9be21a67720fe0b846376aa4ceea76cc4c3e57295003"},
+        "fetch_kib": 292808819.4375, "write_kib": 100323.4375,
+        "valu_insts": 192205263525.0,          # SQ_INSTS_VALU (wave instructions) of the launch
     },
 }
 # FP32 VALU issue slots per second: 256 CUs x 4 SIMDs x 2.4 GHz / 4 cycles per wave64 instruction

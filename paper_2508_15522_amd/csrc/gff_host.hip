@@ -73,7 +73,8 @@ extern "C" gff_status gff_topology_create(const gff_mol_type *types, int n_types
     std::vector<float> khalf;
     std::vector<uint4> excl;
     std::vector<int4> incA, rotq;
-    std::vector<int2> incT, rotinfo(n_types);
+    std::vector<int4> incT;
+    std::vector<int2> rotinfo(n_types);
     std::vector<BondInc> bnd;
     std::vector<AngInc> ang;
     std::vector<TorDef> tdef;
@@ -136,25 +137,41 @@ extern "C" gff_status gff_topology_create(const gff_mol_type *types, int n_types
             }
             ia.w = (int)ang.size() - ia.z;
             incA.push_back(ia);
-            int2 it;
-            it.x = (int)tinc.size();
-            for (int q = 0; q < m.n_tors; ++q) {
-                const int *Q4 = m.tors + 4 * q;
-                for (int s = 0; s < 4; ++s)
-                    if (Q4[s] == a) { tinc.push_back((q << 2) | s); break; }
+            // incident torsion terms grouped by the atom's slot (i, j, k, l), terms ascending
+            // within a slot: (first entry, end of the slot-0, slot-1 and slot-2 groups)
+            int ends[4];
+            const int first = (int)tinc.size();
+            for (int s = 0; s < 4; ++s) {
+                for (int q = 0; q < m.n_tors; ++q) {
+                    const int *Q4 = m.tors + 4 * q;
+                    int slot = -1;
+                    for (int u = 0; u < 4 && slot < 0; ++u) if (Q4[u] == a) slot = u;
+                    if (slot == s) tinc.push_back((q << 2) | s);
+                }
+                ends[s] = (int)tinc.size();
             }
-            it.y = (int)tinc.size() - it.x;
-            incT.push_back(it);
+            incT.push_back(make_int4(first, ends[0], ends[1], ends[2]));
         }
         // the type's torsion block (indices relative to its own sections)
         {
             TypeInfo &T0 = ti[t];
             std::vector<int4> b;
             auto words = [](size_t bytes) { return (int)((bytes + 15) / 16); };
+            const int tend = (int)tinc.size() - tinc0;          // where the last atom's slot-3 group ends
             std::vector<int> it2;
-            for (int a = 0; a < n; ++a) { it2.push_back(incT[T0.abase + a].x - tinc0); it2.push_back(incT[T0.abase + a].y); }
+            for (int a = 0; a < n; ++a) {
+                const int first = incT[T0.abase + a].x - tinc0;
+                const int end = a + 1 < n ? incT[T0.abase + a + 1].x - tinc0 : tend;
+                it2.push_back(first); it2.push_back(end - first);
+            }
             it2.resize((size_t)words(it2.size() * 4) * 4, 0);
             for (size_t k = 0; k < it2.size(); k += 4) b.push_back(make_int4(it2[k], it2[k + 1], it2[k + 2], it2[k + 3]));
+            // incG starts at word ceil(8 n / 16) = (n + 1) / 2, where the kernel looks for it
+            for (int a = 0; a < n; ++a) {
+                const int4 r = incT[T0.abase + a];
+                b.push_back(make_int4(r.x - tinc0, r.y - tinc0, r.z - tinc0, r.w - tinc0));
+            }
+            b.push_back(make_int4(tend, tend, tend, tend));
             T0.o_tor = (int)b.size();
             for (int q = 0; q < m.n_tors; ++q) {
                 int4 w; std::memcpy(&w, &tdef[T0.tbase + q], 16); b.push_back(w);

@@ -47,10 +47,14 @@ struct TypeInfo {              // per molecule type
     int tbase;                 // first torsion of the type in the torsion-term table
     int nt;                    // torsion terms of the type
     // the type's torsion topology as one block of 16-byte words, copied to LDS by the replica
-    // kernel: [incT: n int2, padded][torsion terms, one word each][torsion incidences, int,
-    // padded]; indices inside are relative to the block's own sections
+    // kernel: [incT: n int2 (first incidence, count), padded to (n + 1) / 2 words][incG: n + 1
+    // int4][torsion terms, one word each][torsion incidences, int (term << 2 | slot),
+    // padded].  An atom's incidences are stored grouped by its slot in the term (i, j, k, l),
+    // terms ascending within a group; incG[a] = (first incidence, ends of the slot-0, slot-1
+    // and slot-2 groups), the slot-3 group ending at incG[a + 1].x.  Indices inside are
+    // relative to the block's own sections
     int blob_off, blob_words;  // first word in the blob table, length in words
-    int o_tor, o_tinc;         // section starts (words); incT starts at word 0
+    int o_tor, o_tinc;         // section starts (words); incT at word 0, incG at (n + 1) / 2
 };
 
 // Torsion term: atoms (i,j,k,l) packed seven bits each with the multiplicity n in the top

@@ -797,19 +797,51 @@ k_replicas(KArgs A) {
                 }
                 lds_sync();                                      // B: torsion results visible
                 if (live) {
-                    const int2 itc = reinterpret_cast<const int2 *>(s_topo)[at];
+                    // the atom's shares of its incident terms: F_i = A, F_j = -(1+p) A + q B,
+                    // F_k = p A - (1+q) B, F_l = B (incidence code: term << 2 | slot)
                     const int *tinc = reinterpret_cast<const int *>(s_topo + ti.o_tinc);
                     float fx = 0.f, fy = 0.f, fz = 0.f;
-                    for (int c = itc.x; c < itc.x + itc.y; ++c) {
-                        const int code = tinc[c];
-                        const int q = code >> 2, slot = code & 3;
-                        const float4 ra = s_tres[2 * (lr * nt + q)], rb = s_tres[2 * (lr * nt + q) + 1];
-                        float ca, cb;
-                        if (slot == 0) { ca = 1.f; cb = 0.f; }
-                        else if (slot == 3) { ca = 0.f; cb = 1.f; }
-                        else if (slot == 1) { ca = -(1.f + ra.w); cb = rb.w; }
-                        else { ca = ra.w; cb = -(1.f + rb.w); }
-                        fx += ca * ra.x + cb * rb.x; fy += ca * ra.y + cb * rb.y; fz += ca * ra.z + cb * rb.z;
+                    if constexpr (MODE == MODE_NVE) {
+                        // one branch-free loop per slot group (the incidences are stored grouped)
+                        const int4 *itg = reinterpret_cast<const int4 *>(s_topo + ((n + 1) >> 1));
+                        const int4 r = itg[at];
+                        const int e3 = itg[at + 1].x;
+                        const float4 *tr = s_tres + 2 * lr * nt;
+                        for (int c = r.x; c < r.y; ++c) {
+                            const float4 ra = tr[2 * (tinc[c] >> 2)];
+                            fx += ra.x; fy += ra.y; fz += ra.z;
+                        }
+                        for (int c = r.y; c < r.z; ++c) {
+                            const int q = tinc[c] >> 2;
+                            const float4 ra = tr[2 * q], rb = tr[2 * q + 1];
+                            const float ca = -(1.f + ra.w);
+                            fx += ca * ra.x + rb.w * rb.x; fy += ca * ra.y + rb.w * rb.y; fz += ca * ra.z + rb.w * rb.z;
+                        }
+                        for (int c = r.z; c < r.w; ++c) {
+                            const int q = tinc[c] >> 2;
+                            const float4 ra = tr[2 * q], rb = tr[2 * q + 1];
+                            const float cb = -(1.f + rb.w);
+                            fx += ra.w * ra.x + cb * rb.x; fy += ra.w * ra.y + cb * rb.y; fz += ra.w * ra.z + cb * rb.z;
+                        }
+                        for (int c = r.w; c < e3; ++c) {
+                            const float4 rb = tr[2 * (tinc[c] >> 2) + 1];
+                            fx += rb.x; fy += rb.y; fz += rb.z;
+                        }
+                    } else {
+                        // one loop over the incidences, the slot from the code (in the FIRE and
+                        // Langevin kernels this form spills less)
+                        const int2 itc = reinterpret_cast<const int2 *>(s_topo)[at];
+                        for (int c = itc.x; c < itc.x + itc.y; ++c) {
+                            const int code = tinc[c];
+                            const int q = code >> 2, slot = code & 3;
+                            const float4 ra = s_tres[2 * (lr * nt + q)], rb = s_tres[2 * (lr * nt + q) + 1];
+                            float ca, cb;
+                            if (slot == 0) { ca = 1.f; cb = 0.f; }
+                            else if (slot == 3) { ca = 0.f; cb = 1.f; }
+                            else if (slot == 1) { ca = -(1.f + ra.w); cb = rb.w; }
+                            else { ca = ra.w; cb = -(1.f + rb.w); }
+                            fx += ca * ra.x + cb * rb.x; fy += ca * ra.y + cb * rb.y; fz += ca * ra.z + cb * rb.z;
+                        }
                     }
                     F = F + make_float3(fx, fy, fz);
                 }
