@@ -274,6 +274,8 @@ def main():
         cmp = SM.compare_learned_vs_uniform(g32, S.mol_chain24(), collect_minima=1_000_000, collect_rep=4096,
                                             train_steps=args.train_steps, eval_rounds=4, eval_rep=8192, log=log,
                                             weight_power=args.weight_power)
+        for name in ("uniform", "learned"):
+            log(f"{name} discovery curve (proposals, distinct minima, s): {cmp[name]['short_curve']}")
         res["minima_per_s"] = {"learned": cmp["learned"]["minima_per_s"], "uniform": cmp["uniform"]["minima_per_s"],
                                "gain": cmp["gain_minima_per_s"],
                                "flow_learned": cmp["learned"]["flow"]["minima_per_s"],
@@ -283,6 +285,11 @@ def main():
                                "flow_gain_rmsd": cmp["gain_minima_per_s_flow_rmsd"], "detail": cmp,
                                "workload": ("chain24 FIRE to 1e-4 eV/A (max 5000 steps), distinct within 0.01 eV; "
                                             "proposer trained on >= 1M converged minima of uniform rounds")}
+        uc, lc = cmp["uniform"]["short_curve"], cmp["learned"]["short_curve"]
+        rate = lambda c: c[1] / c[2]
+        res["minima_per_s"]["short_horizon"] = {
+            "proposals": [c[0] for c in uc], "uniform": [c[1] for c in uc], "learned": [c[1] for c in lc],
+            "gain_first_round": rate(lc[0]) / rate(uc[0]), "gain_last_round": rate(lc[-1]) / rate(uc[-1])}
     if args.hopping:
         from paper_2508_15522_amd import sampling as SM
         log("minima hopping vs uniform proposals (minima found per second)")

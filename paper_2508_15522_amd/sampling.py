@@ -342,14 +342,15 @@ def train_imle(mlp, targets, ntors, types, steps, batch=1024, K=64, lr=1e-3, see
 
 def compare_learned_vs_uniform(grid, mol, collect_minima=50_000, collect_rep=4096, train_steps=400, eval_rounds=6,
                                eval_rep=1024, seed=S.SEED_PHILOX, log=None, max_collect_rounds=4000,
-                               weight_power=1.0):
+                               weight_power=1.0, short_rep=512, short_rounds=8):
     """Collect at least collect_minima converged minima with rounds of uniform proposals,
     train the proposer on every converged minimum (the relaxed poses the method generated),
     a minimum of an energy class with c members weighted c^-weight_power (1: every distinct
     minimum the same total weight, 0: every minimum the same weight), then run equal numbers
     of proposals with each
     method against fresh archives.  Returns a dict of counts, wall times, minima/s, mean FIRE
-    steps and mean RMS relaxation move per converged minimum."""
+    steps and mean RMS relaxation move per converged minimum, and for each form the curve
+    (proposals, distinct minima, seconds) over short_rounds rounds of short_rep proposals."""
     say = log or (lambda m: None)
     col = Sampler(grid, mol, collect_rep, seed=seed)
     arch = Archive(max_atoms=mol.n)
@@ -420,6 +421,17 @@ def compare_learned_vs_uniform(grid, mol, collect_minima=50_000, collect_rep=409
                                  minima_per_s_rmsd=r["new_minima_rmsd"] / r["seconds"])
         say(f"{name} (flow): {r['new_minima']} distinct minima ({r['new_minima_rmsd']} by RMSD) from "
             f"{r['proposals']} proposals ({r['converged']} converged) in {r['seconds']:.2f} s")
+    # discovery curve at a short horizon: distinct minima (energy) after each of short_rounds
+    # rounds of short_rep proposals, both forms from fresh archives
+    for name in ("uniform", "learned"):
+        sh = Sampler(grid, mol, short_rep, seed=seed + 41)
+        a = Archive(max_atoms=mol.n)
+        curve, secs = [], 0.0
+        for r in range(short_rounds):
+            rs = sh.round_uniform(a, 2000 + r) if name == "uniform" else sh.round_learned(a, mlp, 2000 + r)
+            secs += rs.seconds
+            curve.append((short_rep * (r + 1), a.count(), round(secs, 4)))
+        res[name]["short_curve"] = curve
     res["gain_minima_per_s_flow"] = (res["learned"]["flow"]["minima_per_s"] /
                                      max(res["uniform"]["flow"]["minima_per_s"], 1e-12))
     res["training"] = dict(minima=m, distinct=arch.count(), steps=train_steps, loss_first=hist[0][1],
