@@ -108,6 +108,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--minima", action="store_true", help="learned vs uniform proposals: minima found per second")
     ap.add_argument("--train-steps", type=int, default=1000, help="IMLE steps of the proposer (--minima)")
+    ap.add_argument("--imle-batch", type=int, default=1024, help="training minima per IMLE step (--minima)")
+    ap.add_argument("--imle-k", type=int, default=64, help="noise candidates per training minimum (--minima)")
     ap.add_argument("--weight-power", type=float, default=1.0,
                     help="training weight of a minimum: (members of its energy class)^-p (--minima)")
     ap.add_argument("--scans", action="store_true",
@@ -273,7 +275,8 @@ def main():
         g32 = grid if args.storage == "f32" else setup(G.STORE_F32)
         cmp = SM.compare_learned_vs_uniform(g32, S.mol_chain24(), collect_minima=1_000_000, collect_rep=4096,
                                             train_steps=args.train_steps, eval_rounds=4, eval_rep=8192, log=log,
-                                            weight_power=args.weight_power)
+                                            weight_power=args.weight_power, imle_batch=args.imle_batch,
+                                            imle_k=args.imle_k)
         for name in ("uniform", "learned"):
             log(f"{name} discovery curve (proposals, distinct minima, s): {cmp[name]['short_curve']}")
         res["minima_per_s"] = {"learned": cmp["learned"]["minima_per_s"], "uniform": cmp["uniform"]["minima_per_s"],

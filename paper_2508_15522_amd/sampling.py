@@ -342,7 +342,7 @@ def train_imle(mlp, targets, ntors, types, steps, batch=1024, K=64, lr=1e-3, see
 
 def compare_learned_vs_uniform(grid, mol, collect_minima=50_000, collect_rep=4096, train_steps=400, eval_rounds=6,
                                eval_rep=1024, seed=S.SEED_PHILOX, log=None, max_collect_rounds=4000,
-                               weight_power=1.0, short_rep=512, short_rounds=8):
+                               weight_power=1.0, short_rep=512, short_rounds=8, imle_batch=1024, imle_k=64):
     """Collect at least collect_minima converged minima with rounds of uniform proposals,
     train the proposer on every converged minimum (the relaxed poses the method generated),
     a minimum of an energy class with c members weighted c^-weight_power (1: every distinct
@@ -387,7 +387,8 @@ def compare_learned_vs_uniform(grid, mol, collect_minima=50_000, collect_rep=409
     w = np.bincount(cl, minlength=len(aE))[cl].astype(np.float64) ** -weight_power
     mlp = G.MLP(1, S.mlp_init_params(1))
     t0 = time.time()
-    hist = train_imle(mlp, tg, ntors, types, train_steps, batch=min(1024, max(64, m)), log=say, weights=w)
+    hist = train_imle(mlp, tg, ntors, types, train_steps, batch=min(imle_batch, max(64, m)), K=imle_k, log=say,
+                      weights=w)
     torch.cuda.synchronize()
     train_s = time.time() - t0
     ev = Sampler(grid, mol, eval_rep, seed=seed + 17)
