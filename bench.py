@@ -40,7 +40,7 @@ COUNTER_SCALE = {"fetch": 2.0, "write": 1.0}
 MEASURED_TRAFFIC = {
     ("f32", 16384, 5000, 192): {
         "sources": {"paper_2508_15522_amd/csrc/gff_relax.hip":
-                    "c723c7e4d7803785415e2a55e8c9bfa866bbb4049cfe618010dfe194b124d842",
+                    "86d0b5830e6af6851b159c48b2b74c24eefbc44c801f78107a5153fa3df72826",
                     "paper_2508_15522_amd/csrc/gff_internal.hpp":
                     "61bc1f04b2dc056901d1a189d182f83d4b4d3f1e8b212e9b3f571786f724024f",
                     "paper_2508_15522_amd/csrc/gff_host.hip":

@@ -828,8 +828,8 @@ k_replicas(KArgs A) {
                             fx += rb.x; fy += rb.y; fz += rb.z;
                         }
                     } else {
-                        // one loop over the incidences, the slot from the code (in the FIRE and
-                        // Langevin kernels this form spills less)
+                        // one loop over the incidences, the slot from the code (the FIRE and
+                        // Langevin kernels run faster in this form)
                         const int2 itc = reinterpret_cast<const int2 *>(s_topo)[at];
                         for (int c = itc.x; c < itc.x + itc.y; ++c) {
                             const int code = tinc[c];
