@@ -339,12 +339,12 @@ def run_workload(name, log):
     prm = G.relax_params(G.MODE_FIRE, wl.n_steps, True, f_conv=1e-4)
     launch = (192, 0, 0)          # 8 x 24 or 5 x 38 atoms fill a 192-thread block
     tuned = None
-    if name == "c3":
+    if name in ("c1", "c3"):      # small or mixed batches: the launch shape is measured
         plan0 = G.Plan(topo, rep_type)
         st = D.fire_state(plan0, per_rep)
         tune_prm = G.relax_params(G.MODE_FIRE, 50, True, f_conv=1e-4)
         launch, tuned = AT.launch_for(grid, topo, rep_type, tune_prm, st, use_cache=False)
-        log(f"c3 autotuned launch {launch} ({tuned:.3e} replica-steps/s on 50 steps)")
+        log(f"{name} autotuned launch {launch} ({tuned:.3e} replica-steps/s on 50 steps)")
     plan = G.Plan(topo, rep_type, *launch)
     st = D.fire_state(plan, per_rep)
     out = D.outputs(plan)

@@ -345,8 +345,10 @@ void gff_graph_destroy(gff_graph *graph);
 
 /* Measured launch shape for a batch (setup step: allocates scratch and synchronises): runs
  * `params` for every block size 64..1024 (multiple of 64, >= the largest molecule) with the
- * default grid and with persistent grids of 1-4 blocks per compute unit, on copies of
- * `state`; returns the fastest shape and its replica-steps/s (nullable). */
+ * densest packing and, when that gives fewer than two packs per compute unit, with at most
+ * 1, 2, 4 or 8 replicas per block; each with the default grid and with persistent grids of
+ * 1-4 blocks per compute unit, on copies of `state`; returns the fastest shape and its
+ * replica-steps/s (nullable). */
 gff_status gff_autotune(const gff_grid *grid, const gff_topology *topo, int n_rep, const int *rep_type_h,
                         const gff_relax_params *params, const gff_state *state, gff_launch *best,
                         float *best_rate, void *stream);

@@ -57,8 +57,8 @@ extern "C" void gff_graph_destroy(gff_graph *g) {
 }
 
 // Measured choice of the launch shape for a batch: every candidate block size (and, per
-// block size, the default packing and persistent grids of 1-4 blocks per CU) runs
-// `params` on a copy of the caller's state; the fastest (replica-steps per second) wins.
+// block size, the packings below and persistent grids of 1-4 blocks per CU) runs `params` on
+// a copy of the caller's state; the fastest (replica-steps per second) wins.
 // Candidates that the device cannot launch are skipped.  The caller's state is untouched.
 extern "C" gff_status gff_autotune(const gff_grid *grid, const gff_topology *topo, int n_rep, const int *rep_type_h,
                                    const gff_relax_params *params, const gff_state *state, gff_launch *best,
@@ -99,33 +99,49 @@ extern "C" gff_status gff_autotune(const gff_grid *grid, const gff_topology *top
     float best_t = -1.f;
     gff_launch chosen{256, 0, 0};
     gff_status rc = GFF_OK;
+    // replicas per block: the densest packing, and when that leaves fewer than two packs per
+    // compute unit, sparser packings (at most 1, 2, 4, 8 replicas per block) that spread a
+    // small batch over more of the GPU
+    const int rpb_cand[5] = {0, 1, 2, 4, 8};
     for (int bt = 64; bt <= 1024 && rc == GFF_OK; bt += 64) {
         if (bt < max_n) continue;
-        for (int gm = 0; gm <= 4; ++gm) {
-            gff_launch L{bt, 0, gm == 0 ? 0 : gm * n_cu};
-            gff_plan *plan = nullptr;
-            if (gff_plan_create(topo, n_rep, rep_type_h, &L, &plan) != GFF_OK) break;
-            if (gm > 0 && L.grid_blocks >= plan->n_packs) { gff_plan_destroy(plan); break; }
-            auto cp = [&](void *d, const void *src, size_t b) {
-                return src ? hipMemcpyAsync(d, src, b, hipMemcpyDeviceToDevice, s) : hipSuccess;
-            };
-            hipError_t e = cp(t.d_pos, state->d_pos, a3);
-            if (e == hipSuccess) e = cp(t.d_vel, state->d_vel, a3);
-            if (e == hipSuccess) e = cp(t.d_fire_dt, state->d_fire_dt, rb);
-            if (e == hipSuccess) e = cp(t.d_fire_alpha, state->d_fire_alpha, rb);
-            if (e == hipSuccess) e = cp(t.d_fire_npos, state->d_fire_npos, rb);
-            if (e == hipSuccess) e = cp(t.d_status, state->d_status, rb);
-            if (e != hipSuccess) { gff_plan_destroy(plan); rc = GFF_EHIP; break; }
-            (void)hipEventRecord(e0, s);
-            const gff_status r = gff_relax_batch(grid, topo, plan, params, &t, E, fn, steps,
-                                                 params->mode == GFF_MODE_NVE ? drift : nullptr, s);
-            (void)hipEventRecord(e1, s);
-            gff_plan_destroy(plan);
-            if (r != GFF_OK) { (void)hipGetLastError(); continue; }
-            if (hipEventSynchronize(e1) != hipSuccess) { rc = GFF_EHIP; break; }
-            float ms = 0.f;
-            (void)hipEventElapsedTime(&ms, e0, e1);
-            if (best_t < 0.f || ms < best_t) { best_t = ms; chosen = L; }
+        int dense_packs = -1, last_packs = -1;
+        for (int ri = 0; ri < 5 && rc == GFF_OK; ++ri) {
+            if (ri > 0 && (dense_packs < 0 || dense_packs >= 2 * n_cu)) break;
+            for (int gm = 0; gm <= 4; ++gm) {
+                gff_launch L{bt, rpb_cand[ri], gm == 0 ? 0 : gm * n_cu};
+                gff_plan *plan = nullptr;
+                if (gff_plan_create(topo, n_rep, rep_type_h, &L, &plan) != GFF_OK) break;
+                if (gm == 0) {
+                    if (ri == 0) dense_packs = plan->n_packs;
+                    else if (plan->n_packs == last_packs || plan->n_packs == dense_packs) {   // same packing
+                        gff_plan_destroy(plan);
+                        break;
+                    }
+                    last_packs = plan->n_packs;
+                }
+                if (gm > 0 && L.grid_blocks >= plan->n_packs) { gff_plan_destroy(plan); break; }
+                auto cp = [&](void *d, const void *src, size_t b) {
+                    return src ? hipMemcpyAsync(d, src, b, hipMemcpyDeviceToDevice, s) : hipSuccess;
+                };
+                hipError_t e = cp(t.d_pos, state->d_pos, a3);
+                if (e == hipSuccess) e = cp(t.d_vel, state->d_vel, a3);
+                if (e == hipSuccess) e = cp(t.d_fire_dt, state->d_fire_dt, rb);
+                if (e == hipSuccess) e = cp(t.d_fire_alpha, state->d_fire_alpha, rb);
+                if (e == hipSuccess) e = cp(t.d_fire_npos, state->d_fire_npos, rb);
+                if (e == hipSuccess) e = cp(t.d_status, state->d_status, rb);
+                if (e != hipSuccess) { gff_plan_destroy(plan); rc = GFF_EHIP; break; }
+                (void)hipEventRecord(e0, s);
+                const gff_status r = gff_relax_batch(grid, topo, plan, params, &t, E, fn, steps,
+                                                     params->mode == GFF_MODE_NVE ? drift : nullptr, s);
+                (void)hipEventRecord(e1, s);
+                gff_plan_destroy(plan);
+                if (r != GFF_OK) { (void)hipGetLastError(); continue; }
+                if (hipEventSynchronize(e1) != hipSuccess) { rc = GFF_EHIP; break; }
+                float ms = 0.f;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                if (best_t < 0.f || ms < best_t) { best_t = ms; chosen = L; }
+            }
         }
     }
     (void)hipEventDestroy(e0);

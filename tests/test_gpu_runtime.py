@@ -55,7 +55,8 @@ def test_autotune_choice_is_launchable_and_result_invariant(world):
     st0 = _state(w, plan0, rep_type, 700)
     ref = {k: v.clone() for k, v in st0.items()}
     best, rate = G.autotune(w["grid"].desc, w["topo"], rep_type, prm, st0)
-    announce(f"  best block {best.block_threads} grid {best.grid_blocks}: {rate:.3e} replica-steps/s")
+    announce(f"  best block {best.block_threads}, replicas per block {best.reps_per_block}, grid {best.grid_blocks}: "
+             f"{rate:.3e} replica-steps/s")
     assert rate > 0 and best.block_threads % 64 == 0
     for k in st0:                                   # the caller's state is untouched
         assert torch.equal(st0[k], ref[k])
