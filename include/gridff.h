@@ -451,8 +451,12 @@ gff_status gff_mlp_create(int n_types, const float *params_h, gff_mlp **out);
 void gff_mlp_destroy(gff_mlp *mlp);
 /* synchronous copies of the FP32 parameters and/or the last gradient (either may be NULL) */
 gff_status gff_mlp_get_params(const gff_mlp *mlp, float *params_h, float *grads_h);
+/* Bytes of the device workspace (caller-owned, overwritten) that gff_mlp_forward and
+ * gff_mlp_train_step need for `batch` rows: activations, pre-activations, gradients and the
+ * split-K partial sums of the weight gradients.  Calls sharing one workspace must not overlap. */
 size_t gff_mlp_workspace_bytes(int batch);
-/* d_noise [batch][64], d_type [batch] -> d_out [batch][41] */
+/* d_noise [batch][64], d_type [batch] -> d_out [batch][41]; GFF_EWORKSPACE if work_bytes is
+ * below gff_mlp_workspace_bytes(batch) */
 gff_status gff_mlp_forward(gff_mlp *mlp, int batch, const float *d_noise, const int *d_type, float *d_out,
                            void *d_work, size_t work_bytes, void *stream);
 /* one training step on (noise, type, target encoding, torsion count) rows: outputs, per-sample
