@@ -234,6 +234,8 @@ def main():
                      "kernel": f"k_replicas<{args.storage},NVE>",
                      "bytes_per_launch": alg_bytes},
     }
+    res["gather_probe"] = gather_probe(grid, log)
+    res["roofline"]["serving_probe_GBps"] = res["gather_probe"]["grid_coefficients"]
     if args.compare_f16 and args.storage == "f32":
         g16 = setup(G.STORE_F16)
         w16, p16, _ = timed(g16, args.steps, 1)
@@ -522,6 +524,40 @@ def run_direct(name, log):
     return r
 
 
+def gather_probe(grid, log, reps=10):
+    """Random 64-byte-chunk gather bandwidth (gff_gather_probe) on three working sets: the
+    grid's own coefficient buffer (the interpolation's working set), 4 MiB (one XCD's L2) and
+    4 GiB (beyond the Infinity Cache: HBM).  GB/s, median of `reps` calls timed with HIP
+    events on the launch stream."""
+    import torch
+    from paper_2508_15522_amd import gridff as G
+    n_threads, iters = 256 * 2048, 64
+    sink = torch.empty(n_threads, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+    moved = n_threads * iters * 16
+    out = {"unit": "GB/s", "chunk_bytes": 64, "bytes_per_call": moved}
+    bufs = {"grid_coefficients": grid.coef.view(torch.uint8),
+            "l2_4MiB": torch.zeros(4 << 20, dtype=torch.uint8, device="cuda"),
+            "hbm_4GiB": torch.zeros(4 << 30, dtype=torch.uint8, device="cuda")}
+    for name, buf in bufs.items():
+        nbytes = buf.numel() // 64 * 64
+        b = buf[:nbytes]
+        G.gather_probe(b, n_threads, iters, 1, sink, stream)                 # warm-up
+        times = []
+        for r in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            G.gather_probe(b, n_threads, iters, 2 + r, sink, stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1) / 1e3)
+        out[name] = moved / float(np.median(times)) / 1e9
+        out[name + "_bytes"] = nbytes
+        log(f"gather probe {name} ({nbytes / 2**20:.1f} MiB): {out[name]:.0f} GB/s")
+    del bufs
+    return out
+
+
 def cpu_baseline(mol, cfg, budget_s):
     """The FP64 oracle on the host cores: NVE of the same molecule on a grid of the same
     size (random coefficients from the seeded generator -- the oracle's cost does not
@@ -552,9 +588,27 @@ def cpu_baseline(mol, cfg, budget_s):
     t = time.time()
     O.nve_batch(B, geo, [mol], np.zeros(n_rep, np.int32), pos, vel, n_steps)
     el = time.time() - t
+    # one thread, on 1024 replicas for about a third of the budget
+    n1 = 1024
+    prev = O.set_threads(1)
+    try:
+        steps1 = int(max(2, min(5000, budget_s / 3 / (per * max(threads, 1) * n1))))
+        t = time.time()
+        O.nve_batch(B, geo, [mol], np.zeros(n1, np.int32), pos[:n1 * mol.n], vel[:n1 * mol.n], steps1)
+        el1 = time.time() - t
+    finally:
+        O.set_threads(prev)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": n_rep * n_steps / el, "unit": "replica-steps/s", "cores": threads, "kind": "oracle",
             "sample": f"{n_rep} replicas x {n_steps} NVE steps of the 38-atom molecule, FP64 B-spline model + "
-                      f"intramolecular field, {el:.1f} s"}
+                      f"intramolecular field, {el:.1f} s",
+            "one_thread": {"value": n1 * steps1 / el1, "sample": f"{n1} replicas x {steps1} steps, {el1:.1f} s"},
+            "cpu_model": model, "nproc": os.cpu_count()}
 
 
 if __name__ == "__main__":

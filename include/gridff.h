@@ -490,6 +490,19 @@ gff_status gff_gemm_bf16_strided(int M, int N, int K, const void *d_A, long sam,
                                  long sbk, long sbn, float *d_C, long ldc, void *d_work, size_t work_bytes,
                                  void *stream);
 
+/* ------------------------------------------------------------------ measurement aid */
+
+/* Random-gather bandwidth probe (not a step of the method: the peak against which the
+ * replica kernel's interpolation traffic is compared).  n_threads (a multiple of 256) lanes
+ * in quads; quad q draws `iters` chunk indices c from xorshift32 (h ^= h << 13; h ^= h >> 17;
+ * h ^= h << 5) started at h = q * 0x9E3779B9 ^ seed (0x6D2B79F5 if that is 0), c = the high
+ * 32 bits of h * (bytes / 64); lane s of the quad loads the 16-byte word s of 64-byte chunk c
+ * of d_buf.  d_sink[n_threads] receives each lane's XOR of the 32-bit words it loaded.
+ * d_buf: device, 16-byte aligned, `bytes` a multiple of 64 (at most 2^32 chunks).  Bytes moved
+ * per call: n_threads * iters * 16.  Asynchronous on `stream`; GFF_EINVAL on bad arguments. */
+gff_status gff_gather_probe(const void *d_buf, size_t bytes, int n_threads, int iters, unsigned seed,
+                            unsigned *d_sink, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

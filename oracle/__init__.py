@@ -76,6 +76,12 @@ def _d(a):
     return a, a.ctypes.data_as(C.POINTER(C.c_double))
 
 
+def set_threads(n):
+    """Thread count of the oracle's OpenMP loops (n <= 0: the initial count); returns the
+    previous count.  For timing only: no result depends on it."""
+    return lib().orc_set_threads(C.c_int(n))
+
+
 def _i(a):
     a = np.ascontiguousarray(a, dtype=np.int32)
     return a, a.ctypes.data_as(C.POINTER(C.c_int))

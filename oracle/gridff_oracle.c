@@ -24,6 +24,7 @@
  * or points; no result depends on the thread count.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -31,6 +32,16 @@
 #ifndef M_PI
 #define M_PI 3.14159265358979323846
 #endif
+
+/* Thread count of the OpenMP loops (timing only: no result depends on it); n <= 0 restores
+ * the count the process started with.  Returns the count in force before the call. */
+int orc_set_threads(int n) {
+    static int initial = 0;
+    const int before = omp_get_max_threads();
+    if (initial == 0) initial = before;
+    omp_set_num_threads(n > 0 ? n : initial);
+    return before;
+}
 
 /* ------------------------------------------------------------------ helpers */
 static long pmod(long a, long n) { long r = a % n; return r < 0 ? r + n : r; }

@@ -323,7 +323,7 @@ EXPORTS += ["gff_propose_uniform", "gff_pose_from_dof", "gff_encode_pose", "gff_
             "gff_mlp_forward", "gff_mlp_train_step", "gff_imle_select", "gff_normal_philox", "gff_gemm_bf16",
             "gff_gemm_bf16_strided", "gff_gemm_bf16_workspace_bytes", "gff_gather_rows", "gff_relax_graph_create",
             "gff_graph_launch", "gff_graph_destroy", "gff_autotune",
-            "gff_refill", "gff_dedupe_rmsd", "gff_dedupe_rmsd_workspace_bytes"]
+            "gff_refill", "gff_dedupe_rmsd", "gff_dedupe_rmsd_workspace_bytes", "gff_gather_probe"]
 N_ENC = 41
 
 
@@ -407,6 +407,13 @@ def gemm_bf16_strided(M, N, K, d_A, sam, sak, d_B, sbk, sbn, d_C, ldc, d_work=No
                                       _ptr(d_work),
                                       C.c_size_t(0 if d_work is None else d_work.numel() * d_work.element_size()),
                                       _stream(stream)))
+
+
+def gather_probe(d_buf, n_threads, iters, seed, d_sink, stream=None):
+    """Random 64-byte-chunk gather over the bytes of d_buf (see gff_gather_probe)."""
+    check(lib().gff_gather_probe(_ptr(d_buf), C.c_size_t(d_buf.numel() * d_buf.element_size()),
+                                 C.c_int(n_threads), C.c_int(iters), C.c_uint(seed), _ptr(d_sink),
+                                 _stream(stream)))
 
 
 def imle_select(d_cand, d_target, d_ntors, d_best, d_bestd=None, stream=None):
