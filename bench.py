@@ -234,6 +234,21 @@ def main():
                      "kernel": f"k_replicas<{args.storage},NVE>",
                      "bytes_per_launch": alg_bytes},
     }
+    # interpolation alone: one evaluation launch (grid part only, no stencil reuse) over the
+    # same atoms, repeated
+    F = torch.empty_like(st0["pos"])
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    G.eval_forces(grid.desc, topo, plan, False, st0["pos"], F, None, None, None, stream)
+    n_eval = 20
+    e0.record(stream)
+    for _ in range(n_eval):
+        G.eval_forces(grid.desc, topo, plan, False, st0["pos"], F, None, None, None, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ev_s = e0.elapsed_time(e1) / 1e3 / n_eval
+    res["eval_interpolations_per_s"] = n_rep * mol.n / ev_s
+    res["eval_launch_s"] = ev_s
+    log(f"eval_forces (grid only): {res['eval_interpolations_per_s']:.3e} interpolations/s, {ev_s * 1e3:.3f} ms per launch")
     res["gather_probe"] = gather_probe(grid, log)
     res["roofline"]["serving_probe_GBps"] = res["gather_probe"]["grid_coefficients"]
     if args.compare_f16 and args.storage == "f32":
