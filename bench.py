@@ -613,6 +613,23 @@ def cpu_baseline(mol, cfg, budget_s):
         el1 = time.time() - t
     finally:
         O.set_threads(prev)
+    # the oracle's molecule-substrate part alone, B-spline model against the all-atom direct
+    # sum over the cell and its 8 lateral images, on the same atoms (all threads)
+    plq = np.tile(O.mixing(mol.eps, mol.R, mol.q), (n_rep, 1))
+    pts = pos.reshape(-1, 3)
+    rates = {}
+    for name, fn in (("bspline", lambda p, q: O.bspline_eval(B, geo, p, q)),
+                     ("all_atom", lambda p, q: O.direct_images(sub, p, q, nimg=1))):
+        n_pts = 4096
+        while True:
+            t = time.time()
+            fn(pts[:n_pts], plq[:n_pts])
+            dt = time.time() - t
+            if dt > budget_s / 20 or n_pts >= len(pts):
+                break
+            n_pts = min(len(pts), n_pts * 4)
+        rates[name] = {"atom_evaluations_per_s": n_pts / dt, "sample": f"{n_pts} atoms, {dt:.2f} s"}
+    rates["substrate_terms_per_atom"] = int(sub.n * 9)
     model = ""
     try:
         with open("/proc/cpuinfo") as f:
@@ -623,7 +640,7 @@ def cpu_baseline(mol, cfg, budget_s):
             "sample": f"{n_rep} replicas x {n_steps} NVE steps of the 38-atom molecule, FP64 B-spline model + "
                       f"intramolecular field, {el:.1f} s",
             "one_thread": {"value": n1 * steps1 / el1, "sample": f"{n1} replicas x {steps1} steps, {el1:.1f} s"},
-            "cpu_model": model, "nproc": os.cpu_count()}
+            "grid_vs_all_atom": rates, "cpu_model": model, "nproc": os.cpu_count()}
 
 
 if __name__ == "__main__":
