@@ -32,8 +32,14 @@ PINS = {
     "bspline_eval": "cubic-polynomial exactness (P2), FD gradient (P5), special case vs direct (P8)",
     "morse_direct": "single-atom analytic case, FD gradient, lattice symmetry (P6)",
     "coulomb_ewald2d": "eta independence, Fourier form above slab, corrugation decay (P7)",
-    "intra": "FD gradient, zero net force/torque, rigid-motion invariance (P11)",
-    "fire_batch": "quadratic-bowl convergence (P10); restraint: held atom, bond-length and inactive-restraint cases",
+    "intra": "FD gradient, zero net force/torque, rigid-motion invariance (P11); closed forms of each term: "
+             "Morse minimum depth and slope, half-attraction point, Coulomb pair force, cosine-harmonic "
+             "angle and torsion (four (V, n, phi0) variants, IUPAC sign) with their lever-arm forces; "
+             "hand-listed exclusion sets on a chain and on 5-, 6- and substituted 6-rings",
+    "fire_batch": "quadratic-bowl convergence (P10); hand-worked three-move trajectory fixing the update "
+                  "order (restart decided before mixing, mix then adapt, kick with the adapted dt), the "
+                  "displacement cap and the convergence test before the move; restraint: held atom, "
+                  "bond-length and inactive-restraint cases",
     "nve_batch": "dt^2 scaling of the energy fluctuation (P9)",
     "philox4x32_10": "published known-answer vectors",
     "pose": "torsion set to target, rigid-body invariants",

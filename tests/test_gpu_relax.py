@@ -224,3 +224,34 @@ def test_fire_teacher_forced_steps_and_final_certificate(world):
     assert np.array_equal(out2["steps"].cpu().numpy(), ref["steps"])
     assert np.array_equal(st2["status"].cpu().numpy(), ref["status"])
     assert np.abs(st2["fire_dt"].cpu().numpy() - ref["dt"]).max() < 1e-6
+
+
+def test_fire_hand_worked_trajectory_on_the_gpu():
+    """The GPU's FIRE moves follow the hand-worked trajectory of the update order (one
+    charge in an anisotropic quadratic bowl represented exactly by the B-spline model,
+    N_min = 0, a restart on the first move, then two adapting moves).  Tolerances are set by
+    the FP32 rounding of the start position (~1.2e-7 A) and of the coefficients."""
+    from tests.test_oracle_closed_forms import FIRE_HAND, _bowl_grid, _charge
+    D.require_gpu()
+    announce("fire hand-worked trajectory")
+    B, spec_o, rs = _bowl_grid()
+    n, h = spec_o["nx"], spec_o["dx"]
+    spec = G.grid_spec(n, n, n, 0.0, 0.0, 0.0, h)
+    grid = D.pack_from_coefficients(B, spec, G.STORE_F32, n * h, n * h)
+    topo = G.Topology([_charge()])
+    x0 = rs + np.array([0.3, 0.2, 0.0])
+    for moves in (1, 2, 3):
+        plan = G.Plan(topo, np.array([0]), block_threads=64)
+        st = D.fire_state(plan, [x0[None]], vel_per_rep=[np.array([[0.206, -0.142, 0.0]])])
+        out = D.outputs(plan)
+        prm = G.relax_params(G.MODE_FIRE, moves, False, f_conv=1e-9, nmin=0)
+        G.relax_batch(grid.desc, topo, plan, prm, st, out["E"], out["fnorm"], out["steps"])
+        torch.cuda.synchronize()
+        v, d, dt, a, npos = FIRE_HAND[moves - 1]
+        xg = D.unsoa(plan, st["pos"])[0][0]
+        vg = D.unsoa(plan, st["vel"])[0][0]
+        announce(f"  {moves} moves: |dx| {np.abs(xg[:2] - rs[:2] - d).max():.2e} A, |dv| {np.abs(vg[:2] - v).max():.2e}")
+        assert np.abs(xg[:2] - rs[:2] - d).max() < 5e-7
+        assert np.abs(vg[:2] - v).max() < 2e-7
+        assert abs(st["fire_dt"].item() - dt) < 1e-8 and abs(st["fire_alpha"].item() - a) < 1e-8
+        assert st["fire_npos"].item() == npos and out["steps"].item() == moves
