@@ -40,13 +40,13 @@ COUNTER_SCALE = {"fetch": 2.0, "write": 1.0}
 MEASURED_TRAFFIC = {
     ("f32", 16384, 5000, 192): {
         "sources": {"paper_2508_15522_amd/csrc/gff_relax.hip":
-                    "86d0b5830e6af6851b159c48b2b74c24eefbc44c801f78107a5153fa3df72826",
+                    "81b766e99bfc0331cc1e3b8f860744e1c3021d514af70deeddd74824380e892c",
                     "paper_2508_15522_amd/csrc/gff_internal.hpp":
-                    "61bc1f04b2dc056901d1a189d182f83d4b4d3f1e8b212e9b3f571786f724024f",
+                    "b090b6df99d75275733cb0c74fc406542c6559062673e1161cd6ea392b6ced4f",
                     "paper_2508_15522_amd/csrc/gff_host.hip":
                     "5e7ba03db58d76beb6af9be21a67720fe0b846376aa4ceea76cc4c3e57295003"},
-        "fetch_kib": 292808819.4375, "write_kib": 100323.4375,
-        "valu_insts": 192205263525.0,          # SQ_INSTS_VALU (wave instructions) of the launch
+        "fetch_kib": 290547659.0, "write_kib": 100337.4375,
+        "valu_insts": 197220102503.0,          # SQ_INSTS_VALU (wave instructions) of the launch
     },
 }
 # FP32 VALU issue slots per second: 256 CUs x 4 SIMDs x 2.4 GHz / 4 cycles per wave64 instruction

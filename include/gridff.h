@@ -116,10 +116,14 @@ gff_status gff_fit_bspline(const gff_grid_spec *spec, const double *d_V, double 
 
 /* Storage cast of fitted coefficients into the evaluation layout:
  * coef[i][j][p][c4], p = 0 .. nz+2 holds z node p-1 with even-mirror padding
- * (node -1 -> 1, node nz -> nz-2, node nz+1 -> nz-3), c4 = (Pauli, London, Coulomb, 0).
- * GFF_STORE_F32: float; GFF_STORE_F16: IEEE half of b / s_c (round to nearest even), with
- * per-channel scale s_c = 2^(ceil(log2 max|b_c|) - 15) written to d_scale[0..2]
- * (d_scale[3] = 0).  For F32, d_scale (if not NULL) receives 1,1,1,0.
+ * (node -1 -> 1, node nz -> nz-2, node nz+1 -> nz-3), c4 = (Pauli, London, Coulomb, 0)
+ * (F16: (Pauli, London, Coulomb, Pauli residual)).
+ * GFF_STORE_F32: float; GFF_STORE_F16: IEEE half h_c of b_c / s_c (round to nearest even),
+ * with per-channel scale s_c = 2^(ceil(log2 max|b_c|) - 15) written to d_scale[0..2]
+ * (d_scale[3] = 0); the fourth half holds l = half(b_P / s_P - h_P), the rounding residual
+ * of the Pauli channel, whose mixed values dominate the force near the surface, and the
+ * evaluation decodes Pauli as (h_P + l) s_P (8 bytes per node either way).  For F32,
+ * d_scale (if not NULL) receives 1,1,1,0.
  * GFF_STORE_TRILINEAR, the earlier scheme the paper compares against (Section
  * "Interpolation": energy and force stored per node and interpolated trilinearly, each on
  * its own): tri[i][j][k][c] = float4 (E, dE/du, dE/dv, dE/dw) of channel c, the fitted

@@ -40,7 +40,9 @@ PINS = {
                   "order (restart decided before mixing, mix then adapt, kick with the adapted dt), the "
                   "displacement cap and the convergence test before the move; restraint: held atom, "
                   "bond-length and inactive-restraint cases",
-    "nve_batch": "dt^2 scaling of the energy fluctuation (P9)",
+    "nve_batch": "dt^2 scaling of the energy fluctuation (P9); drift record recomputed from its definition "
+                 "at the states of separate runs (sampling cadence 3)",
+    "fp16_quantize": "hand-worked scales and round-to-nearest-even ties, the Pauli residual half",
     "philox4x32_10": "published known-answer vectors",
     "pose": "torsion set to target, rigid-body invariants",
     "mlp": "FD gradient check (P12); one-path forward closed form; Adam constant-gradient closed form; "
@@ -260,14 +262,20 @@ def mixing(eps, R, q, alpha=1.6):
 
 def fp16_quantize(B):
     """Per-channel power-of-two scale s_c = 2^(ceil(log2 max|b_c|) - 15) and the
-    round-to-nearest-even FP16 value of b/s_c, returned decoded in FP64: (Bq, s)."""
+    round-to-nearest-even FP16 value h of b/s_c; the Pauli channel also keeps the FP16
+    value l of its residual b/s_c - h, so that it is stored as h + l.  Returned decoded in
+    FP64, (h [+ l]) s_c: (Bq, s)."""
     B = np.asarray(B, dtype=np.float64)
     s = np.empty(3)
     out = np.empty_like(B)
     for c in range(3):
         m = np.abs(B[c]).max()
         s[c] = 2.0 ** (int(np.ceil(np.log2(m))) - 15) if m > 0 else 1.0
-        out[c] = (B[c] / s[c]).astype(np.float16).astype(np.float64) * s[c]
+        r = B[c] / s[c]
+        h = r.astype(np.float16).astype(np.float64)
+        if c == 0:
+            h = h + (r - h).astype(np.float16).astype(np.float64)
+        out[c] = h * s[c]
     return out, s
 
 

@@ -259,10 +259,13 @@ __global__ void __launch_bounds__(256) k_pack(const double *B, int nx, int ny, i
     if constexpr (STORE == GFF_STORE_F32) {
         reinterpret_cast<float4 *>(out)[t] = make_float4((float)b0, (float)b1, (float)b2, 0.f);
     } else {
-        const _Float16 h0 = (_Float16)(b0 / (double)scale[0]);
+        // the Pauli channel, whose mixed values dominate near the surface, also keeps the
+        // rounding residual of its half (exact in FP64) as a second half in the spare slot
+        const double r0 = b0 / (double)scale[0];
+        const _Float16 h0 = (_Float16)r0;
         const _Float16 h1 = (_Float16)(b1 / (double)scale[1]);
         const _Float16 h2 = (_Float16)(b2 / (double)scale[2]);
-        const _Float16 h3 = (_Float16)0.0;
+        const _Float16 h3 = (_Float16)(r0 - (double)h0);
         ushort4 u;
         u.x = __builtin_bit_cast(unsigned short, h0); u.y = __builtin_bit_cast(unsigned short, h1);
         u.z = __builtin_bit_cast(unsigned short, h2); u.w = __builtin_bit_cast(unsigned short, h3);

@@ -115,7 +115,7 @@ inline gff_status hip_status(hipError_t e) { return e == hipSuccess ? GFF_OK : G
 }
 
 // Dynamic LDS of the replica kernel: five float4 slots and one int per lane, two float4 per
-// (replica, torsion term), six doubles of NVE drift record per replica, two flag words and
+// (replica, torsion term), six doubles of NVE drift record per replica, three flag words (16 bytes) and
 // the largest torsion block of the batch.
 inline size_t replica_lds_bytes(int block_threads, int tres_max, int max_pack_reps, int topo_words) {
     return (size_t)block_threads * (5 * 16 + 4) + (size_t)tres_max * 32 + (size_t)max_pack_reps * 48 + 16 +

@@ -96,10 +96,11 @@ __device__ __forceinline__ float4 load_node(const void *coef, int node) {
     if constexpr (STORE == GFF_STORE_F32) {
         return reinterpret_cast<const float4 *>(coef)[node];
     } else {
+        // halves (Pauli, London, Coulomb, Pauli residual)
         uint2 h = reinterpret_cast<const uint2 *>(coef)[node];
         __half2 a = *reinterpret_cast<__half2 *>(&h.x), b = *reinterpret_cast<__half2 *>(&h.y);
         float2 fa = __half22float2(a), fb = __half22float2(b);
-        return make_float4(fa.x, fa.y, fb.x, fb.y);
+        return make_float4(fa.x + fb.y, fa.y, fb.x, 0.f);
     }
 }
 
@@ -132,7 +133,7 @@ __device__ __forceinline__ float4 load_node_buf(__amdgpu_buffer_rsrc_t r, int of
         const unsigned lo = v[0], hi = v[1];
         __half2 a = *reinterpret_cast<const __half2 *>(&lo), b = *reinterpret_cast<const __half2 *>(&hi);
         const float2 fa = __half22float2(a), fb = __half22float2(b);
-        return make_float4(fa.x, fa.y, fb.x, 0.f);
+        return make_float4(fa.x + fb.y, fa.y, fb.x, 0.f);
     }
 }
 
@@ -386,7 +387,7 @@ __device__ __forceinline__ float mix_raw(const RawNode<STORE> &n, float Ps, floa
         const unsigned lo = n.w[0], hi = n.w[1];
         const float2 fa = __half22float2(*reinterpret_cast<const __half2 *>(&lo));
         const float2 fb = __half22float2(*reinterpret_cast<const __half2 *>(&hi));
-        return Ps * fa.x + Ls * fa.y + Qs * fb.x;
+        return Ps * (fa.x + fb.y) + Ls * fa.y + Qs * fb.x;
     }
 }
 
@@ -633,7 +634,7 @@ k_replicas(KArgs A) {
         for (int k = tid; k < ti.blob_words; k += BT) s_topo[k] = A.t.blob[ti.blob_off + k];
         if (MODE == MODE_NVE)
             for (int k = tid; k < 6 * nrep; k += BT) s_drift[k] = 0.0;
-        if (tid == 0) { s_any[0] = 0; s_any[1] = 0; }
+        if (tid == 0) { s_any[0] = 0; s_any[1] = 0; s_any[2] = 0; }
         lds_sync();
 
         unsigned fl = 0;                 // per-lane sticky flags (out of domain, non-finite position)
@@ -654,7 +655,11 @@ k_replicas(KArgs A) {
         int tcid = -1;                          // their cell (CACHE; -1: none)
 
         const int total = (MODE == MODE_EVAL) ? 0 : A.n_steps;
-        for (int it = 0; it <= total; ++it) {
+        // "any replica of the pack still live" flag of step it lives in slot it % 3: a slot
+        // is cleared two steps before it is used again, so a wave that lags behind (no block
+        // barrier between two steps' barrier A in some modes) still reads its own step's flag
+        int aslot = 0;
+        for (int it = 0; it <= total; ++it, aslot = aslot == 2 ? 0 : aslot + 1) {
             const int par = it & 1;
             float4 *sp = par ? s_pos1 : s_pos0;
             float4 *s_gres = par ? s_pos0 : s_pos1;
@@ -670,11 +675,11 @@ k_replicas(KArgs A) {
                 v = A.lg_c1 * v + (A.lg_c2 * sqrtf(A.kT * me.w)) * xi;
                 x = x + (0.5f * A.dt) * v;
             }
-            if (live) s_any[par] = 1;
-            if (tid == 0) s_any[par ^ 1] = 0;
+            if (live) s_any[aslot] = 1;
+            if (tid == 0) s_any[aslot == 2 ? 0 : aslot + 1] = 0;
             sp[tid] = make_float4(x.x, x.y, x.z, 0.f);
             lds_sync();                                          // A: positions visible
-            if (s_any[par] == 0) break;                          // every replica of the pack is done
+            if (s_any[aslot] == 0) break;                        // every replica of the pack is done
             if (MODE == MODE_NVE && live && s_nf[lr]) { st |= GFF_REP_NONFINITE; live = false; }
 
             float pfx = 0.f, pfy = 0.f, pfz = 0.f, pe = 0.f;    // non-bonded pair sums (CACHE)

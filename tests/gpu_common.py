@@ -12,6 +12,22 @@ from paper_2508_15522_amd import synth as S
 COEF_SCALE = (1e-3, 1e-2, 1e-1)
 
 
+def drift_tolerances(eps, steps):
+    """Bounds on the drift-record fields {E(0), E(last), max |dE|, sum dE, sum s dE, samples}
+    that follow from a per-sample error |E_gpu(s) - E_oracle(s)| <= eps: each dE(s) =
+    E(s) - E(0) is within 2 eps, so max |dE| is within 2 eps, sum dE within 2 eps per sample
+    after the first and sum s dE within 2 eps sum s; the sample count is exact."""
+    s = np.asarray(steps[1:], dtype=np.float64)
+    return np.array([eps, eps, 2 * eps, 2 * eps * len(s), 2 * eps * s.sum(), 0.0])
+
+
+# per-sample energy error of one 38-atom replica after 50 steps: FP32 evaluation at the same
+# positions (64 grid terms per atom of |P b| <~ 0.05 eV, ~600 pair terms of <~ 1 eV, each
+# rounded at 2^-24, give <~ 5e-5 eV) plus the energy difference of the two trajectories,
+# which is second order in their 1e-5 A separation because both conserve E_tot
+NVE_EPS = 1e-4
+
+
 def announce(msg):
     print(f"[gpu-test] {msg}", flush=True)
 

@@ -112,7 +112,8 @@ def test_physical_model_vs_direct_and_f16_accuracy():
         per axis by (1/24) h^3 |d^4 V| for the force and (5/384) h^4 |d^4 V| for the energy;
         with |d^4 V_P| <= (2 alpha)^4 V_P dominating near the surface this is ~4e-3 eV/A and
         ~1e-4 eV at 2.5 A.  Reported, and checked against those bounds.
-    (ii) FP16 storage against FP32 storage on the same grid and points: <= 1e-3 eV/A."""
+    (ii) FP16 storage against FP32 storage on the same grid and points: <= 1e-3 eV/A at
+        every point."""
     cfg = configs.GRID_SMALL
     announce("physical model vs direct")
     sub = cfg.substrate()
@@ -146,13 +147,11 @@ def test_physical_model_vs_direct_and_f16_accuracy():
     assert (dF <= np.sqrt(3) * h ** 3 / 24 * d4 * 2 + 1e-4).all()
     assert (dE <= 3 * 5 / 384 * h ** 4 * d4 * 2 + 2e-5).all()
     d16 = np.linalg.norm(F16 - F32, axis=1)
-    hi = pts[:, 2] >= 2.8
-    announce(f"  FP16 vs FP32 storage: max |dF| {d16.max():.2e} eV/A (z >= 2.8 A: {d16[hi].max():.2e}), "
+    announce(f"  FP16 vs FP32 storage: max |dF| {d16.max():.2e} eV/A (z < 2.8 A: {d16[pts[:, 2] < 2.8].max():.2e}), "
              f"max |dE| {np.abs(E16 - E32).max():.2e} eV")
-    # the FP16 relative step 2^-11 times the steep Pauli coefficients sets the error; the
-    # 1e-3 eV/A bound holds from 2.8 A above the top plane (closer it grows like exp(-2 alpha z))
-    assert d16[hi].max() < 1e-3
-    assert d16.max() < 4e-3
+    # with one half per channel the FP16 relative step 2^-11 times the steep Pauli term gave
+    # 1.4e-3 eV/A at 2.5-2.8 A; the Pauli residual half brings it under the bound everywhere
+    assert d16.max() < 1e-3
 
 
 def test_build_grid_defect_supercell_sampled_nodes():

@@ -88,7 +88,8 @@ def test_interp_points_full_grid_random_coefficients(storage):
 
 def test_pack_layout_f32_and_f16_bitexact():
     """The storage cast is exact: F32 is the rounded coefficient, F16 the RNE half of
-    b / s_c; plane p holds node p-1 with even-mirror padding (R9)."""
+    b / s_c (plus the RNE half of the Pauli channel's residual); plane p holds node p-1
+    with even-mirror padding."""
     announce("pack layout")
     nx, ny, nz = 9, 7, 11
     spec = _spec(nx, ny, nz)
@@ -108,6 +109,10 @@ def test_pack_layout_f32_and_f16_bitexact():
     for c in range(3):
         ref = (B[c][:, :, kk] / s[c]).astype(np.float16).view(np.uint16)
         assert np.array_equal(c16[..., c], ref)
+    # the fourth half: the Pauli channel's rounding residual
+    r = B[0][:, :, kk] / s[0]
+    res = (r - r.astype(np.float16).astype(np.float64)).astype(np.float16).view(np.uint16)
+    assert np.array_equal(c16[..., 3], res)
 
 
 def test_interp_domain_edges_and_nonfinite():
@@ -150,18 +155,21 @@ def _batch(mols, rep_type, seed, h=(2.5, 4.5), Lx=2 * S.SLAB_A):
     return pos
 
 
+@pytest.mark.parametrize("storage", [G.STORE_F32, G.STORE_F16])
 @pytest.mark.parametrize("block", [128, 256, 1024])
-def test_eval_forces_batch_with_intra(block):
+def test_eval_forces_batch_with_intra(block, storage):
     """Grid + intramolecular energies and forces of a mixed batch (all eight size-series
-    types plus the chain and the planar molecule), compared atom by atom."""
-    announce(f"eval_forces block={block}")
+    types plus the chain and the planar molecule), compared atom by atom; FP16 storage
+    against the oracle on the same quantised coefficients."""
+    announce(f"eval_forces block={block} storage={storage}")
     mols = S.molecule_types("sizes") + [S.mol_chain24(), S.mol_pah38()]
     rng = np.random.default_rng(1)
     rep_type = rng.integers(0, len(mols), 61)
     Lx = Ly = 2 * S.SLAB_A
     spec = _spec()
     B = S.random_coefficients(NX, NY, NZ, 12, COEF_SCALE)
-    grid = D.pack_from_coefficients(B, spec, G.STORE_F32, Lx, Ly)
+    grid = D.pack_from_coefficients(B, spec, storage, Lx, Ly)
+    Bref = O.fp16_quantize(B)[0] if storage == G.STORE_F16 else S.f32(B)
     topo = G.Topology(mols)
     try:
         plan = G.Plan(topo, rep_type, block_threads=block)
@@ -177,7 +185,7 @@ def test_eval_forces_batch_with_intra(block):
     st = torch.empty(plan.n_rep, dtype=torch.int32, device="cuda")
     G.eval_forces(grid.desc, topo, plan, True, dpos, F, Ea, Er, st)
     torch.cuda.synchronize()
-    Fo, Ero, Eao, sto = O.eval_batch(S.f32(B), grid.geometry, mols, rep_type, np.concatenate(pos))
+    Fo, Ero, Eao, sto = O.eval_batch(Bref, grid.geometry, mols, rep_type, np.concatenate(pos))
     Fg = F.cpu().numpy().T.astype(np.float64)
     dF = np.linalg.norm(Fg - Fo, axis=1)
     announce(f"  max |dF| = {dF.max():.3e} (max |F| {np.abs(Fo).max():.2f}); max |dE_rep| = "

@@ -323,13 +323,16 @@ def test_mlp_forward_backward_adam_imle():
     pg, gg = mlp.params()
     assert np.array_equal(pg, p0)
     o = 0
+    blocks = []
     for l in range(4):
         nW = OS.DIMS[l + 1] * OS.DIMS[l]
-        for a, b in ((o, o + nW), (o + nW, o + nW + OS.DIMS[l + 1])):
-            sc = np.abs(gref[a:b]).max()
-            assert np.abs(gg[a:b] - gref[a:b]).max() < 3e-2 * sc, (l, a, np.abs(gg[a:b] - gref[a:b]).max(), sc)
+        blocks += [(f"W{l}", o, o + nW), (f"b{l}", o + nW, o + nW + OS.DIMS[l + 1])]
         o += nW + OS.DIMS[l + 1]
-    assert np.abs(gg[o:] - gref[o:]).max() < 3e-2 * np.abs(gref[o:]).max()
+    blocks.append(("emb", o, len(gref)))
+    rel = {name: np.abs(gg[a:b] - gref[a:b]).max() / np.abs(gref[a:b]).max() for name, a, b in blocks}
+    announce("  gradient error / largest magnitude: " + ", ".join(f"{k} {v:.2e}" for k, v in rel.items()))
+    for name, v in rel.items():
+        assert v < 2e-2, (name, v)
     assert abs(loss.cpu().numpy().mean() - L) < 2e-2 * L
     # first Adam step against the oracle's step from its own gradient: the step is
     # -lr g/(|g| + eps) ~ -lr sign(g), fixed wherever the gradient is not near zero
@@ -355,8 +358,16 @@ def test_mlp_forward_backward_adam_imle():
     bd = torch.empty(B, device="cuda")
     G.imle_select(cand, dtg, dnt, best, bd)
     torch.cuda.synchronize()
-    bo, do = OS.imle_select(cand.cpu().numpy().astype(np.float64), target, ntors)
-    assert (best.cpu().numpy() == bo).mean() > 0.99
+    cn = cand.cpu().numpy().astype(np.float64)
+    bo, do = OS.imle_select(cn, target, ntors)
+    bg = best.cpu().numpy()
+    # indices agree exactly, except where the candidate the GPU chose is, in the oracle's
+    # FP64 distance, as near as the oracle's best within FP32 rounding of the 41-term sum
+    # (a near-tie the two precisions may break differently)
+    for i in np.where(bg != bo)[0]:
+        dg = OS.enc_dist(cn[i, bg[i]], target[i], ntors[i])[0]
+        assert dg - do[i] <= 41 * 2.0 ** -23 * do[i], (i, dg, do[i])
+    announce(f"  IMLE: {int((bg != bo).sum())} near-tie index differences of {B}")
     assert np.allclose(bd.cpu().numpy(), do, rtol=1e-5)
 
 

@@ -258,3 +258,59 @@ def test_fire_convergence_test_precedes_the_move():
                        f_conv=1e-6)
     assert out["status"][0] & 1 and out["steps"][0] == 0
     assert np.array_equal(out["pos"][0], x0) and np.array_equal(out["vel"][0], [0.3, 0.1, 0.0])
+
+
+# ------------------------------------------------------------------ FP16 storage
+def test_fp16_quantize_hand_worked():
+    """Per-channel scale s_c = 2^(ceil(log2 max|b_c|) - 15); each coefficient stored as the
+    RNE half h of b / s_c; the Pauli channel also stores the RNE half l of b / s_c - h.
+    Values worked out by hand (FP16 has 10 fraction bits, so the ulp at 1 is 2^-10)."""
+    B = np.zeros((3, 4, 4, 4))
+    B[0, 3, 3, 3] = B[1, 3, 3, 3] = 4.3          # ceil(log2 4.3) = 3: s = 2^-12
+    B[2, 3, 3, 3] = -4.0                         # an exact power of two: ceil(log2 4) = 2, s = 2^-13
+    s = 2.0 ** -12
+    cases = [  # b / s, decoded Pauli / s, decoded London / s
+        (1 + 2 ** -11, 1 + 2 ** -11, 1.0),                        # tie: h = 1 (even), l = 2^-11
+        (1 + 3 * 2 ** -11, 1 + 3 * 2 ** -11, 1 + 2 ** -9),        # tie: h = 1 + 2^-9 (even), l = -2^-11
+        (1 + 2 ** -11 + 2 ** -25, 1 + 2 ** -11, 1 + 2 ** -10),    # h = 1 + 2^-10; l = -2^-11 (1 - 2^-14 rounds to 1)
+        (3.0, 3.0, 3.0),
+    ]
+    for k, (r, _, _) in enumerate(cases):
+        B[0, 0, 0, k] = B[1, 0, 0, k] = r * s
+    Bq, sc = O.fp16_quantize(B)
+    assert list(sc) == [2.0 ** -12, 2.0 ** -12, 2.0 ** -13]
+    for k, (_, p, l) in enumerate(cases):
+        assert Bq[0, 0, 0, k] == p * s and Bq[1, 0, 0, k] == l * s, k
+    assert Bq[2, 3, 3, 3] == -4.0 and Bq[0, 3, 3, 3] != 4.3   # 4.3 / 2^-12 needs more than 22 bits
+    assert abs(Bq[0, 3, 3, 3] - 4.3) <= 2.0 ** -22 * 4.3 and abs(Bq[1, 3, 3, 3] - 4.3) <= 2.0 ** -11 * 4.3
+    # an all-zero channel keeps scale 1
+    _, sc0 = O.fp16_quantize(np.zeros((3, 4, 4, 4)))
+    assert list(sc0) == [1.0, 1.0, 1.0]
+
+
+# ------------------------------------------------------------------ NVE drift record
+def test_nve_drift_record_follows_its_definition():
+    """The drift record {E(0), E(last sample), max |E(s) - E(0)|, sum dE, sum s dE, samples}
+    over the samples s = 0, k, 2k, ... <= n, recomputed from E_tot(s) = E_pot + sum m v^2 / 2
+    at the states of separate runs of s steps (E_pot from the model evaluation, the kinetic
+    energy in eV from amu A^2/fs^2)."""
+    mol = S.mol_size(10, 2)
+    nx, ny, nz = 16, 16, 40
+    spec = dict(nx=nx, ny=ny, nz=nz, x0=0.0, y0=0.0, z0=1.0, dx=0.4, dy=0.4, dz=0.25)
+    B = S.random_coefficients(nx, ny, nz, 5, (1e-3, 1e-2, 1e-1))
+    sub = S.rocksalt_slab(1, 1)
+    x0 = S.place_replicas(mol, 1, sub, 31, (3.0, 3.5))[0]
+    v0 = S.mb_velocities(mol.mass, 1, 600.0, 32)[0]
+    n, k = 11, 3
+    rec = O.nve_batch(B, spec, [mol], [0], x0, v0, n, dt=0.5, drift_every=k)["drift"][0]
+    E = {}
+    for s_ in range(0, n + 1, k):
+        st = O.nve_batch(B, spec, [mol], [0], x0, v0, s_, dt=0.5, drift_every=k)
+        Ep = O.eval_batch(B, spec, [mol], [0], st["pos"])[1][0]
+        ke = 0.5 * (mol.mass[:, None] * st["vel"] ** 2).sum() * O.AMU_A2_FS2_EV
+        E[s_] = Ep + ke
+    s_ = np.array(sorted(E))
+    dE = np.array([E[t] - E[0] for t in s_])
+    want = [E[0], E[s_[-1]], np.abs(dE).max(), dE.sum(), (s_ * dE).sum(), len(s_)]
+    np.testing.assert_allclose(rec, want, rtol=1e-12, atol=1e-12)
+    assert rec[5] == 4 and s_[-1] == 9
