@@ -199,10 +199,16 @@ int gff_plan_n_packs(const gff_plan *plan);
 /* atom_off_h[n_rep+1]: the replica atom offsets of the per-atom arrays */
 gff_status gff_plan_atom_offsets(const gff_plan *plan, int *atom_off_h);
 
-/* Energy and forces at fixed positions.  d_F [3][N] = -grad E (grid part plus, if
- * include_intra, the intramolecular field); d_E_atom [N] (nullable) the per-atom grid
- * energy E_i; d_E_rep [n_rep] (nullable) the replica's total energy, summed in FP64;
- * d_status [n_rep] (nullable) OUT_OF_DOMAIN / NONFINITE bits. */
+/* Energy and forces at fixed positions.  The grid part is the per-atom tricubic B-spline
+ * interpolation of the three channels mixed with the atom's (P, L, Q) (Section
+ * "Interpolation", Eqs. Bspline1D and Bspline; Section "Principles", Eqs. E, E_Morse,
+ * E_Coulomb and V_Morse: E_i = P_i V^P + L_i V^L + Q_i V^C, F_i = -grad E_i); the
+ * intramolecular field is the force field the paper takes from UFF (Section "Accuracy and
+ * performance tests on CPU"), here with the explicit terms documented with gff_mol_type.
+ * d_F [3][N] = -grad E (grid part plus, if include_intra, the intramolecular field);
+ * d_E_atom [N] (nullable) the per-atom grid energy E_i; d_E_rep [n_rep] (nullable) the
+ * replica's total energy, summed in FP64; d_status [n_rep] (nullable) OUT_OF_DOMAIN /
+ * NONFINITE bits. */
 gff_status gff_eval_forces(const gff_grid *grid, const gff_topology *topo, const gff_plan *plan,
                            int include_intra, const float *d_pos, float *d_F, float *d_E_atom,
                            double *d_E_rep, unsigned *d_status, void *stream);
@@ -228,6 +234,8 @@ typedef struct {
     float gamma;              /* Langevin: friction [1/fs] (>= 0) */
     unsigned long long seed;  /* Langevin: Philox key (low word, high word) */
     unsigned round;           /* Langevin: fourth Philox counter word; use a new value per launch */
+    int check_every;          /* FIRE: replica-wide decisions every k-th move (the paper's GPU
+                                 sampler checks every 100 steps); 0 or 1: every move */
 } gff_relax_params;
 
 /* Caller-owned replica state (in/out). */
@@ -248,12 +256,22 @@ typedef struct {
     const float *d_fixed_pos;
 } gff_state;
 
-/* FIRE (Bitzek et al. 2006) per replica with unit masses, every step on the GPU:
- * evaluate F, E at x; if |F|_2 < f_conv set CONVERGED and freeze; P = F.v;
+/* Batched relaxation and dynamics of independent replicas, the whole step loop in one
+ * launch (Section "Configuration sampling on GPU": many replicas at once, the MD loop kept on
+ * the GPU; the energy and forces are those of gff_eval_forces).
+ *
+ * FIRE (Bitzek et al. 2006; the relaxation of Sections "Accuracy and performance tests on
+ * CPU" and "Configuration sampling on GPU") per replica with unit masses, every step on the
+ * GPU: evaluate F, E at x; if |F|_2 < f_conv set CONVERGED and freeze; P = F.v;
  * v <- (1-a) v + a |v| F/|F|; if P > 0 { npos++; if npos > nmin: dt <- min(dt finc, dtmax),
  * a <- a falpha } else { dt <- dt fdec; a <- alpha0; v <- 0; npos <- 0 }; v <- v + F dt;
  * dx = v dt scaled per atom to |dx_i| <= max_disp; x <- x + dx.  After n_steps moves the
  * final state is evaluated once more.  Replicas converged on entry are evaluated, not moved.
+ * With check_every = k > 1 (the paper's form, which downloads the state every 100 steps to
+ * test convergence and stop uphill motion) the steps that need sums over the replica (the
+ * convergence test, P, mixing, adaptation, restart) are taken only on moves 0, k, 2k, ... and
+ * at the final evaluation; the moves in between are plain kicks v <- v + F dt with capped
+ * moves at the current dt.  Not supported by gff_relax_scan (GFF_EINVAL).
  *
  * NVE: velocity Verlet with masses in amu, a = F/(m 103.6427) [A/fs^2]; forces at the
  * entry positions are evaluated first.  Every drift_every steps the total energy

@@ -316,7 +316,7 @@ class _Fire(C.Structure):
     _fields_ = [("n_steps", C.c_int), ("dt0", C.c_double), ("f_conv", C.c_double),
                 ("max_disp", C.c_double), ("finc", C.c_double), ("fdec", C.c_double),
                 ("alpha0", C.c_double), ("falpha", C.c_double), ("dtmax", C.c_double),
-                ("nmin", C.c_int), ("intra", C.c_int)]
+                ("nmin", C.c_int), ("intra", C.c_int), ("check_every", C.c_int)]
 
 
 class MolView:
@@ -413,7 +413,7 @@ def eval_batch(B, spec, mols, rep_type, pos, intra_on=True, alpha=1.6):
 # atom) put the semi-implicit Euler stability limit near 0.18; larger steps keep FIRE
 # resetting and it stalls
 FIRE_DEFAULTS = dict(dt0=0.05, f_conv=1e-4, max_disp=0.1, finc=1.1, fdec=0.5, alpha0=0.1,
-                     falpha=0.99, dtmax=0.1, nmin=5)
+                     falpha=0.99, dtmax=0.1, nmin=5, check_every=1)
 
 
 def fire_batch(B, spec, mols, rep_type, pos, n_steps, vel=None, state=None, intra_on=True,
@@ -435,7 +435,7 @@ def fire_batch(B, spec, mols, rep_type, pos, n_steps, vel=None, state=None, intr
     status = np.array(st.get("status", np.zeros(nr)), np.int32)
     E, fn, steps = np.zeros(nr), np.zeros(nr), np.zeros(nr, np.int32)
     prm = _Fire(n_steps, p["dt0"], p["f_conv"], p["max_disp"], p["finc"], p["fdec"], p["alpha0"],
-                p["falpha"], p["dtmax"], p["nmin"], int(intra_on))
+                p["falpha"], p["dtmax"], p["nmin"], int(intra_on), p["check_every"])
     ip = lambda a: a.ctypes.data_as(C.POINTER(C.c_int))
     lib().orc_fire_batch(C.byref(gv.s), C.byref(tv.s), C.byref(prm), C.c_int(nr), _i(rep_type)[1],
                          _i(off)[1], _nullable(pos), _nullable(vel), _nullable(fdt), _nullable(fal),

@@ -617,6 +617,7 @@ void orc_eval_batch(const orc_grid *g, const orc_types *T, int intra, int n_rep,
 typedef struct {
     int n_steps; double dt0, f_conv, max_disp, finc, fdec, alpha0, falpha, dtmax; int nmin;
     int intra;
+    int check_every;            /* global decisions every k-th move (<= 1: every move) */
 } orc_fire_params;
 
 /* FIRE (Bitzek et al. 2006) for each replica, unit masses.  Each iteration: evaluate F and E
@@ -631,7 +632,13 @@ typedef struct {
  * held, the rest relaxed): if fixed_atom is given and 0 <= fixed_atom[r] < n, that atom is
  * placed at fixed_pos[r] on entry, its velocity is zero and its force is replaced by zero
  * (the restraint's reaction), so it never moves and takes no part in |F|, F.v or the mixing;
- * the energy is the whole replica's. */
+ * the energy is the whole replica's.
+ * Check cadence (the paper's GPU sampler downloads the state every 100 steps to test the
+ * force norm and to zero the velocities when P < 0, Section "Configuration sampling on GPU"):
+ * with check_every = k > 1 the steps above that need sums over the replica (convergence test,
+ * P, mixing, dt/alpha adaptation, restart) are taken only on moves it = 0, k, 2k, ... and at
+ * the final evaluation; every other move is a plain kick v <- v + F dt and capped move with
+ * the current dt. */
 void orc_fire_batch(const orc_grid *g, const orc_types *T, const orc_fire_params *prm, int n_rep,
                     const int *rep_type, const int *atom_off, double *pos, double *vel,
                     double *fdt, double *falpha, int *fnpos, int *status,
@@ -657,6 +664,18 @@ void orc_fire_batch(const orc_grid *g, const orc_types *T, const orc_fire_params
         for (int it = 0; it <= prm->n_steps && !(st & 4); ++it) {
             st |= replica_force(g, &m, plq, prm->intra, ex, x, F, &E, NULL, Ft);
             if (fa >= 0) F[3*fa] = F[3*fa+1] = F[3*fa+2] = 0;
+            if (prm->check_every > 1 && it % prm->check_every != 0 && it < prm->n_steps) {
+                const double dt = fdt[r];          /* no sums over the replica on this move */
+                for (int i = 0; i < 3 * n; ++i) v[i] += F[i] * dt;
+                for (int i = 0; i < n; ++i) {
+                    double d[3] = { v[3*i] * dt, v[3*i+1] * dt, v[3*i+2] * dt };
+                    double l = sqrt(dot3(d, d));
+                    double s = l > prm->max_disp ? prm->max_disp / l : 1.0;
+                    for (int c = 0; c < 3; ++c) x[3*i+c] += d[c] * s;
+                }
+                steps++;
+                continue;
+            }
             double ff = 0, fv = 0, vv = 0;
             for (int i = 0; i < 3 * n; ++i) { ff += F[i] * F[i]; fv += F[i] * v[i]; vv += v[i] * v[i]; }
             fn = sqrt(ff);

@@ -170,7 +170,8 @@ __global__ void __launch_bounds__(256) k_dft_x(const double2 *T, const double2 *
 // ------------------------------------------------------------------ B-spline fit
 // Constant tridiagonal system (1/6, 4/6, 1/6) factors: forward-sweep multipliers cp[i] and
 // pivots inv[i] (1/pivot); for the cyclic case the Sherman-Morrison vector zsm and factor.
-struct TriFactors { const double *cp, *inv, *lo, *zsm; double vfac0, vfacN, gam; int cyclic; };
+// scal = (vfac0, vfacN): the Sherman-Morrison scalars, on the device beside the arrays.
+struct TriFactors { const double *cp, *inv, *lo, *zsm, *scal; int cyclic; };
 
 __device__ __forceinline__ void tri_solve_strided(double *d, long stride, int n, const TriFactors &f) {
     // forward: d'[0] = d[0]*inv0; d'[i] = (d[i] - lo[i] d'[i-1]) inv[i]
@@ -186,8 +187,8 @@ __device__ __forceinline__ void tri_solve_strided(double *d, long stride, int n,
     }
     if (f.cyclic) {
         // x = y - (v.y)/(1 + v.z) z with v = (1, 0.., a/gam)
-        const double vy = d[0] + f.vfacN * d[(long)(n - 1) * stride];
-        const double s = vy * f.vfac0;
+        const double vy = d[0] + f.scal[1] * d[(long)(n - 1) * stride];
+        const double s = vy * f.scal[0];
         for (int i = 0; i < n; ++i) d[i * stride] -= s * f.zsm[i];
     }
 }
@@ -414,55 +415,56 @@ extern "C" gff_status gff_build_grid(const gff_substrate *sub, const gff_grid_sp
 
 // ------------------------------------------------------------------ fit
 namespace gff {
-struct HostTri { std::vector<double> lo, cp, inv, zsm; double vfac0 = 0, vfacN = 0, gam = 0; int cyclic = 0; };
+// Elimination factors of the constant (1/6, 4/6, 1/6) system of size n, one thread per axis
+// (a short sequential recurrence).  cyclic: the Sherman-Morrison split A = T + u v^T with
+// u = (gam, 0.., a), v = (1, 0.., a/gam), gam = -4/6; mirror: rows 0 and n-1 have
+// off-diagonal 2/6.  Outputs: lo, cp (forward-sweep multipliers), inv (1/pivot), zsm
+// (T^-1 u, cyclic only) and scal = (vfac0, vfacN).
+struct AxisOut { double *lo, *cp, *inv, *zsm, *scal; int n, cyclic; };
+struct FactorArgs { AxisOut ax[3]; };
 
-// Elimination factors of the constant (1/6, 4/6, 1/6) system of size n.  cyclic: the
-// Sherman-Morrison split A = T + u v^T with u = (gam, 0.., a), v = (1, 0.., a/gam);
-// mirror: rows 0 and n-1 have off-diagonal 2/6.
-static HostTri tri_factors(int n, bool cyclic) {
-    HostTri f;
-    const double a = 1.0 / 6.0, b = 4.0 / 6.0;
-    std::vector<double> lo(n, a), di(n, b), up(n, a);
-    f.cyclic = cyclic ? 1 : 0;
-    if (cyclic) {
-        f.gam = -b;
-        di[0] = b - f.gam;
-        di[n - 1] = b - a * a / f.gam;
-    } else {
-        up[0] = 2.0 / 6.0;
-        lo[n - 1] = 2.0 / 6.0;
-    }
-    f.lo = lo; f.cp.assign(n, 0.0); f.inv.assign(n, 0.0);
-    double piv = di[0];
-    f.inv[0] = 1.0 / piv;
-    f.cp[0] = up[0] / piv;
+__global__ void k_tri_factors(FactorArgs fa) {
+    if (threadIdx.x >= 3) return;
+    const AxisOut o = fa.ax[threadIdx.x];
+    const int n = o.n;
+    const double a = 1.0 / 6.0, b = 4.0 / 6.0, gam = -b;
+    auto diag = [&](int i) {
+        if (o.cyclic) return i == 0 ? b - gam : (i == n - 1 ? b - a * a / gam : b);
+        return b;
+    };
+    auto upper = [&](int i) { return (!o.cyclic && i == 0) ? 2.0 / 6.0 : a; };
+    for (int i = 0; i < n; ++i) o.lo[i] = (!o.cyclic && i == n - 1) ? 2.0 / 6.0 : a;
+    double piv = diag(0);
+    o.inv[0] = 1.0 / piv;
+    o.cp[0] = upper(0) / piv;
     for (int i = 1; i < n; ++i) {
-        piv = di[i] - lo[i] * f.cp[i - 1];
-        f.inv[i] = 1.0 / piv;
-        f.cp[i] = up[i] / piv;
+        piv = diag(i) - o.lo[i] * o.cp[i - 1];
+        o.inv[i] = 1.0 / piv;
+        o.cp[i] = upper(i) / piv;
     }
-    if (cyclic) {
-        // z = T^{-1} u
-        std::vector<double> z(n, 0.0);
-        z[0] = f.gam; z[n - 1] = a;
-        double prev = z[0] * f.inv[0];
-        z[0] = prev;
-        for (int i = 1; i < n; ++i) { z[i] = (z[i] - lo[i] * prev) * f.inv[i]; prev = z[i]; }
-        for (int i = n - 2; i >= 0; --i) { z[i] -= f.cp[i] * z[i + 1]; }
-        f.zsm = z;
-        f.vfacN = a / f.gam;
-        const double vz = z[0] + f.vfacN * z[n - 1];
-        f.vfac0 = 1.0 / (1.0 + vz);
+    if (o.cyclic) {
+        // z = T^-1 u by the same forward and backward sweeps
+        double prev = gam * o.inv[0];
+        o.zsm[0] = prev;
+        for (int i = 1; i < n; ++i) {
+            const double u = (i == n - 1) ? a : 0.0;
+            prev = (u - o.lo[i] * prev) * o.inv[i];
+            o.zsm[i] = prev;
+        }
+        for (int i = n - 2; i >= 0; --i) o.zsm[i] -= o.cp[i] * o.zsm[i + 1];
+        const double vfacN = a / gam;
+        o.scal[0] = 1.0 / (1.0 + o.zsm[0] + vfacN * o.zsm[n - 1]);
+        o.scal[1] = vfacN;
     } else {
-        f.zsm.assign(n, 0.0);
+        for (int i = 0; i < n; ++i) o.zsm[i] = 0.0;
+        o.scal[0] = 0.0; o.scal[1] = 0.0;
     }
-    return f;
 }
 }  // namespace gff
 
 extern "C" size_t gff_fit_workspace_bytes(const gff_grid_spec *spec) {
     if (!spec_ok(spec)) return 0;
-    return 3 * 4 * align256((size_t)std::max(spec->nx, std::max(spec->ny, spec->nz)) * sizeof(double));
+    return 3 * (4 * align256((size_t)std::max(spec->nx, std::max(spec->ny, spec->nz)) * sizeof(double)) + 256);
 }
 
 extern "C" gff_status gff_fit_bspline(const gff_grid_spec *spec, const double *d_V, double *d_B, void *d_work,
@@ -477,21 +479,19 @@ extern "C" gff_status gff_fit_bspline(const gff_grid_spec *spec, const double *d
     if (e != hipSuccess) return GFF_EHIP;
     const int L = std::max(nx, std::max(ny, nz));
     char *w = static_cast<char *>(d_work);
+    // factors computed on the device in the workspace (x, y cyclic; z mirror rows)
     TriFactors F[3];
-    HostTri H[3] = {tri_factors(nx, true), tri_factors(ny, true), tri_factors(nz, false)};
+    FactorArgs fa;
+    const int ns[3] = {nx, ny, nz};
     for (int a = 0; a < 3; ++a) {
         double *arr[4];
         for (int q = 0; q < 4; ++q) { arr[q] = reinterpret_cast<double *>(w); w += align256((size_t)L * sizeof(double)); }
-        const std::vector<double> *src[4] = {&H[a].lo, &H[a].cp, &H[a].inv, &H[a].zsm};
-        for (int q = 0; q < 4; ++q)
-            if ((e = hipMemcpyAsync(arr[q], src[q]->data(), src[q]->size() * sizeof(double), hipMemcpyHostToDevice, s)) !=
-                hipSuccess)
-                return GFF_EHIP;
-        F[a].lo = arr[0]; F[a].cp = arr[1]; F[a].inv = arr[2]; F[a].zsm = arr[3];
-        F[a].vfac0 = H[a].vfac0; F[a].vfacN = H[a].vfacN; F[a].gam = H[a].gam; F[a].cyclic = H[a].cyclic;
+        double *scal = reinterpret_cast<double *>(w);
+        w += 256;
+        fa.ax[a] = AxisOut{arr[0], arr[1], arr[2], arr[3], scal, ns[a], a < 2 ? 1 : 0};
+        F[a] = TriFactors{arr[1], arr[2], arr[0], arr[3], scal, a < 2 ? 1 : 0};
     }
-    // pageable copies above are staged before returning; keep the host factors alive until then
-    if ((e = hipStreamSynchronize(s)) != hipSuccess) return GFF_EHIP;
+    hipLaunchKernelGGL(k_tri_factors, dim3(1), dim3(64), 0, s, fa);
     for (int c = 0; c < 3; ++c) {
         double *Bc = d_B + c * plane;
         {   // along x: lines (j,k), element stride ny*nz

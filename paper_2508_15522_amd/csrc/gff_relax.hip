@@ -57,6 +57,7 @@ struct KArgs {
     float *fdt, *falpha; int *fnpos; unsigned *status;
     float *F; float *E_atom; double *E_rep; float *fnorm; int *steps; double *drift;
     int n_steps, include_intra, drift_every, nmin;
+    int check_every;                    // FIRE: replica-wide decisions every k-th move (>= 1)
     float dt, f_conv, max_disp, finc, fdec, a0, falpha_f, dtmax;
     float lg_c1, lg_c2, kT;             // Langevin: exp(-gamma dt), sqrt(1 - c1^2), k_B T
     unsigned seed_lo, seed_hi, round;   // Langevin: Philox key and fourth counter word
@@ -856,7 +857,19 @@ k_replicas(KArgs A) {
 
             if (MODE == MODE_EVAL) break;
 
-            if (MODE == MODE_FIRE) {
+            if (MODE == MODE_FIRE && A.check_every > 1 && it % A.check_every != 0 && it < total) {
+                // a move between checks: no sums over the replica, a plain kick and capped
+                // move with the current dt (block-uniform condition: no barrier is skipped
+                // by some waves only)
+                if (live) {
+                    v = v + fdt * F;
+                    float3 d = fdt * v;
+                    const float l2 = dot(d, d);
+                    if (l2 > A.max_disp * A.max_disp) d = (A.max_disp * __builtin_amdgcn_rsqf(l2)) * d;
+                    x = x + d;
+                    steps++;
+                }
+            } else if (MODE == MODE_FIRE) {
                 const bool scan = A.path != nullptr;
                 s_red[tid] = make_float4(dot(F, F), dot(F, v), dot(v, v), scan ? e_atom : 0.f);
                 lds_sync();                                      // C: partials visible
@@ -1179,6 +1192,7 @@ static gff_status relax_check(const gff_topology *topo, const gff_plan *plan, co
     if (p->mode == GFF_MODE_FIRE && (!state->d_fire_dt || !state->d_fire_alpha || !state->d_fire_npos))
         return GFF_EINVAL;
     if (p->mode == GFF_MODE_NVE && d_drift_rep && p->drift_every < 1) return GFF_EINVAL;
+    if (p->check_every < 0) return GFF_EINVAL;
     if ((state->d_fixed_atom != nullptr) != (state->d_fixed_pos != nullptr)) return GFF_EINVAL;
     if (state->d_fixed_atom && p->mode != GFF_MODE_FIRE) return GFF_EUNSUPPORTED;
     if (p->mode == GFF_MODE_LANGEVIN &&
@@ -1200,6 +1214,7 @@ static gff_status relax_common(int storage, KArgs &A, const gff_topology *topo, 
     A.drift = p->mode == GFF_MODE_NVE ? d_drift_rep : nullptr;
     A.n_steps = p->n_steps; A.include_intra = p->include_intra;
     A.drift_every = p->drift_every < 1 ? 1 : p->drift_every;
+    A.check_every = p->check_every < 1 ? 1 : p->check_every;
     A.nmin = p->fire_nmin;
     A.dt = p->dt; A.f_conv = p->f_conv; A.max_disp = p->max_disp;
     A.finc = p->fire_finc; A.fdec = p->fire_fdec; A.a0 = p->fire_alpha0; A.falpha_f = p->fire_falpha;
@@ -1218,7 +1233,7 @@ extern "C" gff_status gff_relax_scan(const gff_grid *grid, const gff_topology *t
                                      int *d_steps_points, unsigned *d_status_points, float *d_pos_points,
                                      double *d_E_rep, float *d_fnorm_rep, int *d_steps_rep, void *stream) {
     if (!p || p->mode != GFF_MODE_FIRE || !d_path || n_points < 1 || moves_per_point < 0 || !d_E_points ||
-        !(dt0 > 0.f))
+        !(dt0 > 0.f) || p->check_every > 1)
         return GFF_EINVAL;
     if ((long)n_points * ((long)moves_per_point + 1) >= 2147483647L) return GFF_EINVAL;
     if (!state || !state->d_fixed_atom) return GFF_EINVAL;       // the scanned atom

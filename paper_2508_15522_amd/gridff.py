@@ -62,7 +62,8 @@ class RelaxParams(C.Structure):
                 ("f_conv", C.c_float), ("max_disp", C.c_float), ("fire_finc", C.c_float),
                 ("fire_fdec", C.c_float), ("fire_alpha0", C.c_float), ("fire_falpha", C.c_float),
                 ("fire_dtmax", C.c_float), ("fire_nmin", C.c_int), ("drift_every", C.c_int),
-                ("kT", C.c_float), ("gamma", C.c_float), ("seed", C.c_ulonglong), ("round", C.c_uint)]
+                ("kT", C.c_float), ("gamma", C.c_float), ("seed", C.c_ulonglong), ("round", C.c_uint),
+                ("check_every", C.c_int)]
 
 
 class State(C.Structure):
@@ -249,10 +250,10 @@ def interp_points(grid_desc, d_pos, d_plq, d_F, d_E=None, stream=None):
 
 def relax_params(mode=MODE_FIRE, n_steps=1000, include_intra=True, dt=0.5, f_conv=1e-4, max_disp=0.1,
                  finc=1.1, fdec=0.5, alpha0=0.1, falpha=0.99, dtmax=0.1, nmin=5, drift_every=1,
-                 T=300.0, gamma=0.01, seed=0, rnd=0):
+                 T=300.0, gamma=0.01, seed=0, rnd=0, check_every=1):
     """T is the Langevin bath temperature in K (kT = k_B T in the C struct)."""
     return RelaxParams(mode, n_steps, int(include_intra), dt, f_conv, max_disp, finc, fdec, alpha0, falpha,
-                       dtmax, nmin, drift_every, K_B * T, gamma, seed, rnd)
+                       dtmax, nmin, drift_every, K_B * T, gamma, seed, rnd, check_every)
 
 
 def _state(st):

@@ -91,6 +91,28 @@ def test_fire_short_run_parity(world, n_steps, storage, block):
     assert np.allclose(st["fire_dt"].cpu().numpy(), ref["dt"], rtol=1e-6)
 
 
+def test_fire_check_cadence_parity(world):
+    """The paper's form: replica-wide decisions (convergence test, P, mixing, adaptation,
+    restart) every 7th move, plain kicks in between; 40 moves against the oracle."""
+    w = world
+    announce("fire check cadence 7")
+    rng = np.random.default_rng(4)
+    rep_type = rng.integers(0, len(w["mols"]), 30)
+    plan = G.Plan(w["topo"], rep_type, block_threads=256)
+    pos = _positions(w, rep_type, 800)
+    st, out = _fire(w, plan, pos, 40, check_every=7)
+    ref = O.fire_batch(w["B"], w["geo"], w["mols"], rep_type, np.concatenate(pos), 40, check_every=7)
+    dx = np.abs(np.concatenate(D.unsoa(plan, st["pos"])) - ref["pos"]).max()
+    nat = np.array([w["mols"][t].n for t in rep_type])
+    dE = np.abs(out["E"].cpu().numpy() - ref["E"])
+    announce(f"  max |dx| = {dx:.3e} A, max |dE|/atom = {(dE / nat).max():.3e} eV")
+    assert dx < 2e-4
+    assert (dE < 2e-5 * nat + 1e-6 * np.abs(ref["E"])).all()
+    assert np.array_equal(out["steps"].cpu().numpy(), ref["steps"])
+    assert np.array_equal(st["status"].cpu().numpy(), ref["status"])
+    assert np.array_equal(st["fire_npos"].cpu().numpy(), ref["npos"])
+
+
 def test_fire_long_run_properties_and_determinism(world):
     w = world
     announce("fire long run")

@@ -171,3 +171,6 @@ def test_relax_scan_rejects_invalid_arguments(world):
         G.relax_scan(w["grid"].desc, w["topo"], plan, G.relax_params(G.MODE_NVE, 0, True), st, path, 3, 10, 0.05, E)
     with pytest.raises(G.GffError):          # the per-point energies are required
         G.relax_scan(w["grid"].desc, w["topo"], plan, fire, st, path, 3, 10, 0.05, None)
+    with pytest.raises(G.GffError):          # no check cadence in scans
+        G.relax_scan(w["grid"].desc, w["topo"], plan, G.relax_params(G.MODE_FIRE, 0, True, f_conv=1e-3,
+                                                                     check_every=100), st, path, 3, 10, 0.05, E)

@@ -314,3 +314,28 @@ def test_nve_drift_record_follows_its_definition():
     want = [E[0], E[s_[-1]], np.abs(dE).max(), dE.sum(), (s_ * dE).sum(), len(s_)]
     np.testing.assert_allclose(rec, want, rtol=1e-12, atol=1e-12)
     assert rec[5] == 4 and s_[-1] == 9
+
+
+def test_fire_check_cadence_hand_worked():
+    """With replica-wide decisions every second move (the paper's GPU form checks every 100
+    steps), move 1 is the restart of the trajectory above and move 2 a plain kick and move
+    with the unchanged dt = 0.025: F = -(d1x, 2 d1y) = (-0.2998125, -0.3995),
+    v2 = v1 + F dt = (-0.0149953125, -0.0199875), d2 = d1 + v2 dt = (0.2994376171875,
+    0.1992503125); alpha and the streak are untouched.  Move 3 is a full FIRE step again."""
+    B, spec, rs = _bowl_grid()
+    x0 = rs + np.array([0.3, 0.2, 0.0])
+    v0 = np.array([[0.206, -0.142, 0.0]])
+    kw = dict(vel=v0, intra_on=False, f_conv=1e-9, nmin=0, check_every=2)
+    out = O.fire_batch(B, spec, [_charge()], [0], x0[None], 2, **kw)
+    np.testing.assert_allclose(out["pos"][0, :2] - rs[:2], [0.2994376171875, 0.1992503125], rtol=0, atol=1e-13)
+    np.testing.assert_allclose(out["vel"][0, :2], [-0.0149953125, -0.0199875], rtol=0, atol=1e-14)
+    assert out["dt"][0] == 0.025 and out["alpha"][0] == 0.1 and out["npos"][0] == 0 and out["steps"][0] == 2
+    # move 3 (a check): P = F.v > 0 at d2, so the streak grows and dt, alpha adapt (N_min = 0)
+    out3 = O.fire_batch(B, spec, [_charge()], [0], x0[None], 3, **kw)
+    assert out3["npos"][0] == 1 and out3["dt"][0] == pytest.approx(0.0275, abs=1e-16)
+    assert out3["alpha"][0] == pytest.approx(0.099, abs=1e-16) and out3["steps"][0] == 3
+    # cadence 1 is the plain form
+    a = O.fire_batch(B, spec, [_charge()], [0], x0[None], 3, vel=v0, intra_on=False, f_conv=1e-9, nmin=0)
+    b = O.fire_batch(B, spec, [_charge()], [0], x0[None], 3, vel=v0, intra_on=False, f_conv=1e-9, nmin=0,
+                     check_every=1)
+    assert np.array_equal(a["pos"], b["pos"])
