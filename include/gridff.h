@@ -456,6 +456,20 @@ gff_status gff_dedupe_rmsd(const gff_plan *plan, const float *d_pos, const int *
                            int capacity, int max_atoms, float *d_arch_pos, double *d_arch_cen, int *d_arch_type,
                            int *d_arch_n, int *d_is_new, void *d_work, size_t work_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * sampling loops, harnesses that forbid allocation): gff_dedupe_rmsd with its scratch in a
+ * static device array of GFF_DEDUPE_NOALLOC_MAX_REP candidates (2.25 MiB per GPU, held
+ * until the process ends) instead of a workspace argument.  Same arguments, results and
+ * errors as gff_dedupe_rmsd; plans of more than GFF_DEDUPE_NOALLOC_MAX_REP replicas return
+ * GFF_EWORKSPACE and enqueue nothing.  Calls no allocating routine; the scratch address of a
+ * device is looked up on the first call made with that device current.  All calls on one
+ * GPU share the array: calls that overlap in time on one GPU (different streams, or other
+ * host threads) race and give undefined results; calls in one stream are ordered. */
+#define GFF_DEDUPE_NOALLOC_MAX_REP 65536
+gff_status gff_dedupe_rmsd_noalloc(const gff_plan *plan, const float *d_pos, const int *d_ok, float tol, float Lx,
+                                   float Ly, int capacity, int max_atoms, float *d_arch_pos, double *d_arch_cen,
+                                   int *d_arch_type, int *d_arch_n, int *d_is_new, void *stream);
+
 /* ------------------------------------------------------------------ learned proposer */
 
 /* A 4-layer MLP (widths 96 -> 256 -> 256 -> 256 -> 41, SiLU between layers) maps

@@ -12,6 +12,7 @@
 #include "gff_internal.hpp"
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 namespace gff {
 
@@ -579,6 +580,49 @@ extern "C" gff_status gff_dedupe_rmsd(const gff_plan *plan, const float *d_pos, 
     hipLaunchKernelGGL(k_rmsd_batch, dim3(1), dim3(1024), 0, s, A);
     hipLaunchKernelGGL(k_rmsd_final, dim3(plan->n_rep), dim3(128), 0, s, A);
     return hip_status(hipGetLastError());
+}
+
+// ---------------------------------------------------------------- allocation-free dedupe
+// The RMSD dedupe's per-candidate scratch (centroids and decisions, accepted list) in a
+// file-scope device array, for callers that cannot allocate.  Every GPU holds its own copy
+// until the process ends; host code uses only the address hipGetSymbolAddress returns for
+// the current device, looked up once per device on the first call there.
+namespace gff {
+static __device__ __align__(256) unsigned char scratch[(size_t)GFF_DEDUPE_NOALLOC_MAX_REP * (sizeof(double4) + sizeof(int))];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices];
+
+static gff_status scratch_for_current_device(void **out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return GFF_EHIP;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return GFF_EHIP;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return GFF_OK;
+}
+}  // namespace gff
+
+extern "C" gff_status gff_dedupe_rmsd_noalloc(const gff_plan *plan, const float *d_pos, const int *d_ok, float tol,
+                                              float Lx, float Ly, int capacity, int max_atoms, float *d_arch_pos,
+                                              double *d_arch_cen, int *d_arch_type, int *d_arch_n, int *d_is_new,
+                                              void *stream) {
+    if (!plan) return GFF_EINVAL;
+    if (plan->n_rep > GFF_DEDUPE_NOALLOC_MAX_REP) return GFF_EWORKSPACE;
+    void *work = nullptr;
+    if (plan->n_rep > 0) {
+        const gff_status rc = scratch_for_current_device(&work);
+        if (rc != GFF_OK) return rc;
+    }
+    // the kernels write every scratch entry they read within the call, so nothing is cleared
+    return gff_dedupe_rmsd(plan, d_pos, d_ok, tol, Lx, Ly, capacity, max_atoms, d_arch_pos, d_arch_cen, d_arch_type,
+                           d_arch_n, d_is_new, work, gff_dedupe_rmsd_workspace_bytes(GFF_DEDUPE_NOALLOC_MAX_REP),
+                           stream);
 }
 
 extern "C" gff_status gff_encode_pose(const gff_topology *topo, const gff_plan *plan, const float *d_pos, float Lx,

@@ -324,7 +324,8 @@ EXPORTS += ["gff_propose_uniform", "gff_pose_from_dof", "gff_encode_pose", "gff_
             "gff_mlp_forward", "gff_mlp_train_step", "gff_imle_select", "gff_normal_philox", "gff_gemm_bf16",
             "gff_gemm_bf16_strided", "gff_gemm_bf16_workspace_bytes", "gff_gather_rows", "gff_relax_graph_create",
             "gff_graph_launch", "gff_graph_destroy", "gff_autotune",
-            "gff_refill", "gff_dedupe_rmsd", "gff_dedupe_rmsd_workspace_bytes", "gff_gather_probe"]
+            "gff_refill", "gff_dedupe_rmsd", "gff_dedupe_rmsd_workspace_bytes", "gff_dedupe_rmsd_noalloc",
+            "gff_gather_probe"]
 N_ENC = 41
 
 
@@ -382,6 +383,18 @@ def dedupe_rmsd(plan, d_pos, d_ok, tol, Lx, Ly, capacity, max_atoms, d_arch_pos,
                                 _ptr(d_arch_type), _ptr(d_arch_n), _ptr(d_is_new), _ptr(d_work),
                                 C.c_size_t(0 if d_work is None else d_work.numel() * d_work.element_size()),
                                 _stream(stream)))
+
+
+DEDUPE_NOALLOC_MAX_REP = 65536
+
+
+def dedupe_rmsd_noalloc(plan, d_pos, d_ok, tol, Lx, Ly, capacity, max_atoms, d_arch_pos, d_arch_cen, d_arch_type,
+                        d_arch_n, d_is_new, stream=None):
+    """dedupe_rmsd with the library's static scratch (no allocation anywhere in the call)."""
+    check(lib().gff_dedupe_rmsd_noalloc(plan.handle, _ptr(d_pos), _ptr(d_ok), C.c_float(tol), C.c_float(Lx),
+                                        C.c_float(Ly), C.c_int(capacity), C.c_int(max_atoms), _ptr(d_arch_pos),
+                                        _ptr(d_arch_cen), _ptr(d_arch_type), _ptr(d_arch_n), _ptr(d_is_new),
+                                        _stream(stream)))
 
 
 def normal_philox(n, seed, rnd, d_out, stream=None):

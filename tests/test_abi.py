@@ -51,6 +51,8 @@ def test_invalid_arguments_rejected_without_device(lib):
     assert lib.gff_mlp_create(0, None, None) == -1
     assert lib.gff_refill(None, None, None, C.c_float(0.05), C.c_float(0.1), None, None) == -1
     assert lib.gff_relax_occupancy(None, None, 2, None, None) == -1
+    assert lib.gff_dedupe_rmsd_noalloc(None, None, None, C.c_float(0.1), C.c_float(1.0), C.c_float(1.0), 0, 24,
+                                       None, None, None, None, None, None) == -1
     g = G.Grid(5, 8, 8, 8, 0, 0, 0, 0.1, 0.1, 0.1, None, None)      # unknown storage
     assert lib.gff_interp_points(C.byref(g), 1, None, None, None, None, None) == -1
     spec = G.grid_spec(3, 8, 8, 0.0, 0.0, 1.0, 0.1)                # nx < 4
