@@ -477,7 +477,8 @@ def run_defect(log, n_paths=512, n_points=200):
     out = {}
     mol = S.mol_pah38()
     topo = G.Topology([mol])
-    plan = G.Plan(topo, np.zeros(n_paths, np.int32), block_threads=192)
+    # 512 paths of 38 atoms leave most of the GPU idle at one lane per atom: four lanes per atom
+    plan = G.Plan(topo, np.zeros(n_paths, np.int32), block_threads=256, lanes_per_atom=4)
     held = np.full(n_paths, mol.elem.index("O"), np.int32)
     rng = np.random.default_rng(77)
     cfg = configs.GRID_DEFECT

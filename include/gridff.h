@@ -179,12 +179,19 @@ gff_status gff_topology_create(const gff_mol_type *types_h, int n_types, float a
 void gff_topology_destroy(gff_topology *topo);
 
 /* Launch shape of the replica kernels.  block_threads: multiple of 64 in [64, 1024];
- * replicas of one type are packed densely into blocks, one lane per atom, floor(block/n)
- * replicas per block (at most reps_per_block if > 0).  grid_blocks <= 0: one block per pack. */
+ * replicas of one type are packed densely into blocks, lanes_per_atom lanes per atom (1, 2
+ * or 4; 0 means 1), floor(block / (lanes_per_atom n)) replicas per block (at most
+ * reps_per_block if > 0).  grid_blocks <= 0: one block per pack.  Several lanes per atom
+ * split an atom's non-bonded partners, bonded terms and the replica's torsion terms (and,
+ * at four, give every atom its own gather quad): for batches too small to fill the GPU.
+ * They apply to FIRE, NVE and Langevin launches on FP32 and FP16 B-spline grids; other
+ * launches on such a plan use one lane per atom on the same packing.  Results depend on
+ * lanes_per_atom only through the FP32 summation order of the split sums. */
 typedef struct {
     int block_threads;
     int reps_per_block;
     int grid_blocks;
+    int lanes_per_atom;
 } gff_launch;
 
 typedef struct gff_plan_s gff_plan;
@@ -369,8 +376,11 @@ void gff_graph_destroy(gff_graph *graph);
  * `params` for every block size 64..1024 (multiple of 64, >= the largest molecule) with the
  * densest packing and, when that gives fewer than two packs per compute unit, with at most
  * 1, 2, 4 or 8 replicas per block; each with the default grid and with persistent grids of
- * 1-4 blocks per compute unit, on copies of `state`; returns the fastest shape and its
- * replica-steps/s (nullable). */
+ * 1-4 blocks per compute unit; on FP32/FP16 B-spline grids, for batches of fewer atoms than
+ * 256 per compute unit, all of this again with 2 and 4 lanes per atom (Section
+ * "Configuration sampling on GPU": the GPU has far more cores than a small molecule has
+ * atoms); on copies of `state`; returns the fastest shape and its replica-steps/s
+ * (nullable). */
 gff_status gff_autotune(const gff_grid *grid, const gff_topology *topo, int n_rep, const int *rep_type_h,
                         const gff_relax_params *params, const gff_state *state, gff_launch *best,
                         float *best_rate, void *stream);

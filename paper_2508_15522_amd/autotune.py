@@ -26,7 +26,8 @@ def _key(topo, rep_type, params, storage):
 
 
 def launch_for(grid, topo, rep_type, params, st, use_cache=True):
-    """(block_threads, reps_per_block, grid_blocks) for this batch, measured once per key."""
+    """(block_threads, reps_per_block, grid_blocks, lanes_per_atom) for this batch, measured
+    once per key."""
     path = cache_path()
     key = _key(topo, rep_type, params, grid.storage)
     db = {}
@@ -36,12 +37,12 @@ def launch_for(grid, topo, rep_type, params, st, use_cache=True):
                 db = json.load(f)
         except (OSError, ValueError):
             db = {}
-    if key in db:
+    if key in db and "lanes_per_atom" in db[key]:
         v = db[key]
-        return (v["block_threads"], v["reps_per_block"], v["grid_blocks"]), v["rate"]
+        return (v["block_threads"], v["reps_per_block"], v["grid_blocks"], v["lanes_per_atom"]), v["rate"]
     best, rate = G.autotune(grid.desc, topo, rep_type, params, st)
     v = dict(block_threads=best.block_threads, reps_per_block=best.reps_per_block, grid_blocks=best.grid_blocks,
-             rate=rate)
+             lanes_per_atom=best.lanes_per_atom, rate=rate)
     if use_cache:
         db[key] = v
         os.makedirs(os.path.dirname(path), exist_ok=True)
@@ -49,4 +50,4 @@ def launch_for(grid, topo, rep_type, params, st, use_cache=True):
         with open(tmp, "w") as f:
             json.dump(db, f, indent=1)
         os.replace(tmp, path)
-    return (v["block_threads"], v["reps_per_block"], v["grid_blocks"]), rate
+    return (v["block_threads"], v["reps_per_block"], v["grid_blocks"], v["lanes_per_atom"]), rate

@@ -219,13 +219,16 @@ extern "C" void gff_topology_destroy(gff_topology *T) {
 extern "C" gff_status gff_plan_create(const gff_topology *topo, int n_rep, const int *rep_type_h,
                                       const gff_launch *launch, gff_plan **out) {
     if (!topo || n_rep < 0 || (n_rep > 0 && !rep_type_h) || !out) return GFF_EINVAL;
-    int BT = 256, rpb_cap = 0, grid = 0;
+    int BT = 256, rpb_cap = 0, grid = 0, lpa = 1;
     if (launch) {
         BT = launch->block_threads > 0 ? launch->block_threads : 256;
         rpb_cap = launch->reps_per_block;
         grid = launch->grid_blocks;
+        lpa = launch->lanes_per_atom > 0 ? launch->lanes_per_atom : 1;
     }
     if (BT % 64 != 0 || BT < 64 || BT > 1024) return GFF_EINVAL;
+    if (lpa != 1 && lpa != 2 && lpa != 4) return GFF_EINVAL;
+    const int NS = BT / lpa;                              // atom slots per block
     std::vector<int> atom_off(n_rep + 1, 0);
     int max_n = 0;
     for (int r = 0; r < n_rep; ++r) {
@@ -234,14 +237,14 @@ extern "C" gff_status gff_plan_create(const gff_topology *topo, int n_rep, const
         atom_off[r + 1] = atom_off[r] + topo->natoms[t];
         max_n = std::max(max_n, topo->natoms[t]);
     }
-    if (max_n > BT) return GFF_EUNSUPPORTED;
+    if (max_n > NS) return GFF_EUNSUPPORTED;
     // packs of same-type replicas, densest packing of one lane per atom
     std::vector<std::vector<int>> by_type(topo->n_types);
     for (int r = 0; r < n_rep; ++r) by_type[rep_type_h[r]].push_back(r);
     std::vector<int> order(topo->n_types);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return topo->natoms[a] > topo->natoms[b]; });
-    // LDS per block: 84 bytes per lane, the largest torsion block, 48 bytes per replica and
+    // LDS per block: 84 bytes per atom slot, the largest torsion block, 48 bytes per replica and
     // 32 bytes per (replica, torsion term); packs of torsion-heavy types hold fewer replicas
     // when the block's LDS would overflow
     int dev = 0, lds_limit = 65536;
@@ -253,14 +256,14 @@ extern "C" gff_status gff_plan_create(const gff_topology *topo, int n_rep, const
     int topo_words = 0;                                   // largest torsion block of the batch
     for (int t = 0; t < topo->n_types; ++t)
         if (!by_type[t].empty()) topo_words = std::max(topo_words, topo->blob_words[t]);
-    const long lane_lds = (long)BT * (5 * 16 + 4) + 16 + 16L * topo_words;
+    const long lane_lds = (long)NS * (5 * 16 + 4) + 16 + 16L * topo_words;
     if (lane_lds >= lds_limit) return GFF_EUNSUPPORTED;
     std::vector<int4> packs;
     std::vector<int> reps;
     int tres_max = 0, max_pack_reps = 0;
     for (int t : order) {
         const int n = topo->natoms[t];
-        int rpb = BT / n;
+        int rpb = NS / n;
         if (rpb_cap > 0) rpb = std::min(rpb, rpb_cap);
         if (topo->ntors[t] > 0 && !by_type[t].empty()) {
             const long fit = (lds_limit - lane_lds - 48L * rpb) / (32L * topo->ntors[t]);
@@ -280,7 +283,8 @@ extern "C" gff_status gff_plan_create(const gff_topology *topo, int n_rep, const
     P->n_rep = n_rep; P->n_atoms = atom_off[n_rep]; P->n_packs = (int)packs.size();
     P->block_threads = BT; P->grid_blocks = grid; P->max_n = max_n; P->tres_max = tres_max;
     P->max_pack_reps = max_pack_reps; P->topo_words = topo_words;
-    if ((long)replica_lds_bytes(BT, tres_max, max_pack_reps, topo_words) > lds_limit) {
+    P->lanes_per_atom = lpa; P->lds_limit = lds_limit;
+    if ((long)replica_lds_bytes(NS, tres_max, max_pack_reps, topo_words) > lds_limit) {
         delete P;
         return GFF_EUNSUPPORTED;
     }

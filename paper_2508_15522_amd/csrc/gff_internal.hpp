@@ -99,6 +99,8 @@ struct gff_topology_s {
 struct gff_plan_s {
     int n_rep, n_atoms, n_packs;
     int block_threads, grid_blocks, max_n;
+    int lanes_per_atom;        // 1, 2 or 4 (B-spline relaxation and dynamics launches)
+    int lds_limit;             // the device's LDS bytes per block
     int tres_max;              // largest (replicas per pack) x (torsion terms) of the batch
     int max_pack_reps;         // largest number of replicas in one pack
     int topo_words;            // largest torsion block of the batch (16-byte words)
@@ -114,11 +116,12 @@ namespace gff {
 inline gff_status hip_status(hipError_t e) { return e == hipSuccess ? GFF_OK : GFF_EHIP; }
 }
 
-// Dynamic LDS of the replica kernel: five float4 slots and one int per lane, two float4 per
+// Dynamic LDS of the replica kernel: five float4 slots and one int per atom slot (lanes / lanes
+// per atom), two float4 per
 // (replica, torsion term), six doubles of NVE drift record per replica, three flag words (16 bytes) and
 // the largest torsion block of the batch.
-inline size_t replica_lds_bytes(int block_threads, int tres_max, int max_pack_reps, int topo_words) {
-    return (size_t)block_threads * (5 * 16 + 4) + (size_t)tres_max * 32 + (size_t)max_pack_reps * 48 + 16 +
+inline size_t replica_lds_bytes(int slots, int tres_max, int max_pack_reps, int topo_words) {
+    return (size_t)slots * (5 * 16 + 4) + (size_t)tres_max * 32 + (size_t)max_pack_reps * 48 + 16 +
            (size_t)topo_words * 16;
 }
 

@@ -18,7 +18,8 @@
 
 namespace gff {
 
-enum { MODE_EVAL = 0, MODE_FIRE = 1, MODE_NVE = 2, MODE_LANGEVIN = 3 };
+enum { MODE_EVAL = 0, MODE_FIRE = 1, MODE_NVE = 2, MODE_LANGEVIN = 3,
+       MODE_FIRE_CHECKED = 4 };   // FIRE with replica-wide decisions every k-th move only
 // storage slot of the all-atom comparison mode (no grid: direct substrate sums)
 constexpr int STORE_DIRECT = 3;
 constexpr int STORE_TRI = GFF_STORE_TRILINEAR;
@@ -287,6 +288,17 @@ __device__ __forceinline__ double quad_sum(double v) {
     return v;
 }
 
+// Sum over the LPA lanes of one atom (consecutive lanes within a quad); every one of them
+// receives the same value.
+template <int LPA>
+__device__ __forceinline__ float sub_sum(float v) {
+    if constexpr (LPA >= 2)
+        v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));  // [1,0,3,2]
+    if constexpr (LPA >= 4)
+        v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false));  // [2,3,0,1]
+    return v;
+}
+
 // Hand-off of one atom's grid lookup: owner lane -> the quad that gathers for it.
 struct GridKey { int i, j, k, valid; };
 
@@ -441,15 +453,18 @@ __device__ __forceinline__ int stencil_id(const GridView &g, int4 ki) {
 // P_i P_j e^{-2 alpha r} - L_i L_j e^{-alpha r}/2, plus k_e Q_i Q_j / r.  Adds the force on i
 // to (fx, fy, fz) and the full pair energies to e (the caller halves the sum).  Ranges are
 // block-uniform; consecutive ranges accumulate in the order of one pass over [0, n).
+template <int LPA>
 __device__ __forceinline__ void pair_range(const KArgs &A, const float4 *sp, const float4 *splq, int rbase, int j0,
-                                           int j1, float3 xi, float4 me, uint4 ex, float &fx, float &fy, float &fz,
-                                           float &e) {
+                                           int j1, float3 xi, float4 me, uint4 ex, int sub, float &fx, float &fy,
+                                           float &fz, float &e) {
     const float keQ = A.ke * me.z;
     for (int jb = j0 & ~31; jb < j1; jb += 32) {
         const int w = jb >> 5;
         const unsigned m = w == 0 ? ex.x : (w == 1 ? ex.y : (w == 2 ? ex.z : ex.w));
-        const int js = max(j0, jb), je = min(j1, jb + 32);
-        for (int j = js; j < je; ++j) {
+        const int js0 = max(j0, jb), je = min(j1, jb + 32);
+        // with several lanes per atom, sub-lane u takes the partners j = u (mod LPA)
+        const int js = LPA == 1 ? js0 : js0 + ((sub - js0) & (LPA - 1));
+        for (int j = js; j < je; j += LPA) {
             const float4 pj = sp[rbase + j];
             const float4 qj = splq[rbase + j];
             const float ddx = xi.x - pj.x, ddy = xi.y - pj.y, ddz = xi.z - pj.z;
@@ -469,11 +484,12 @@ __device__ __forceinline__ void pair_range(const KArgs &A, const float4 *sp, con
 
 // Bonds and angles incident to this lane's atom (each term evaluated by every
 // participant for its own slot; the slot-0 participant carries the energy).
+template <int LPA>
 __device__ __forceinline__ float bond_angle_terms(const KArgs &A, const float4 *sp, int rbase, int abase, int at,
-                                                  float3 xi, float &fx, float &fy, float &fz) {
+                                                  int sub, float3 xi, float &fx, float &fy, float &fz) {
     float e = 0.f;
     const int4 ia = A.t.incA[abase + at];
-    for (int b = ia.x; b < ia.x + ia.y; ++b) {
+    for (int b = ia.x + sub; b < ia.x + ia.y; b += LPA) {
         const BondInc bi = A.t.bnd[b];
         const float3 d = xi - f3(sp[rbase + bi.other]);
         const float d2 = dot(d, d), rinv = __builtin_amdgcn_rsqf(d2);
@@ -482,7 +498,7 @@ __device__ __forceinline__ float bond_angle_terms(const KArgs &A, const float4 *
         fx -= g * d.x; fy -= g * d.y; fz -= g * d.z;
         if (bi.slot == 0) e += 0.5f * bi.k * dr * dr;
     }
-    for (int q = ia.z; q < ia.z + ia.w; ++q) {
+    for (int q = ia.z + sub; q < ia.z + ia.w; q += LPA) {
         const AngInc ai = A.t.ang[q];
         const int ia0 = ai.abcs & 0xff, ib = (ai.abcs >> 8) & 0xff, ic = (ai.abcs >> 16) & 0xff, slot = ai.abcs >> 24;
         const float3 pa = f3(sp[rbase + ia0]), pb = f3(sp[rbase + ib]), pc = f3(sp[rbase + ic]);
@@ -563,13 +579,24 @@ __device__ __forceinline__ float direct_terms(const KArgs &A, float3 xi, float4 
     return e;
 }
 
-// CACHE: keep each lane's four pre-mixed stencil planes (64 values) in registers from step
-// to step; this needs blocks of at most 512 threads (up to 256 registers per lane).
-template <int STORE, int MODE, bool CACHE>
+// CACHE: keep each lane's pre-mixed stencil planes (4 / LPA of them, 16 values each) in
+// registers from step to step; this needs blocks of at most 512 threads.
+// LPA: lanes per atom (1, 2, 4).  The LPA consecutive lanes of an atom slot hold the same
+// position and velocity and integrate identically; they split the atom's non-bonded
+// partners, bonded incidences and the replica's torsion terms, and their partial forces and
+// energies are summed across them (fixed order, identical on every sub-lane).  With
+// LPA = 4 each quad gathers for its own atom; fewer slots per wave mean fewer gather rounds.
+template <int STORE, int MODE, bool CACHE, int LPA>
 __global__ void __launch_bounds__(CACHE ? 512 : 1024) __attribute__((amdgpu_waves_per_eu(CACHE ? 3 : 1)))
 k_replicas(KArgs A) {
+    static_assert(LPA == 1 || ((STORE == GFF_STORE_F32 || STORE == GFF_STORE_F16) && MODE != MODE_EVAL),
+                  "several lanes per atom only for B-spline relaxation and dynamics");
+    constexpr bool FIRE = MODE == MODE_FIRE || MODE == MODE_FIRE_CHECKED;
     extern __shared__ __align__(16) unsigned char smem[];
     const int BT = blockDim.x, tid = threadIdx.x;
+    const int NS = BT / LPA;                     // atom slots of the block
+    const int slot = tid / LPA, sub = tid & (LPA - 1);
+    constexpr int R = 4 / LPA;                   // gather rounds per wave
     // LDS, one float4 slot per lane in each array:
     //   s_pos0/s_pos1  positions (double-buffered by step parity); the buffer of the other
     //                  parity carries the gather results during a step
@@ -582,20 +609,21 @@ k_replicas(KArgs A) {
     //   s_drift        per-replica NVE drift record (6 doubles)
     //   s_nf           per-replica non-finite flags (NVE)
     float4 *s_pos0 = reinterpret_cast<float4 *>(smem);
-    float4 *s_pos1 = s_pos0 + BT;
-    float4 *s_red = s_pos1 + BT;
-    float4 *s_sum = s_red + BT;
-    float4 *s_plq = s_sum + BT;
-    float4 *s_tres = s_plq + BT;
+    float4 *s_pos1 = s_pos0 + NS;
+    float4 *s_red = s_pos1 + NS;
+    float4 *s_sum = s_red + NS;
+    float4 *s_plq = s_sum + NS;
+    float4 *s_tres = s_plq + NS;
     int4 *s_topo = reinterpret_cast<int4 *>(s_tres + 2 * A.tres_max);
     double *s_drift = reinterpret_cast<double *>(s_topo + A.topo_words);
     int *s_nf = reinterpret_cast<int *>(s_drift + 6 * A.max_pack_reps);
-    int *s_any = s_nf + BT;
+    int *s_any = s_nf + NS;
     double2 *s_red64 = reinterpret_cast<double2 *>(s_red);
     float4 *s_gt = s_red;
     int4 *s_gi = reinterpret_cast<int4 *>(s_sum);
     const int N = A.N;
     const int wl = tid & 63, wb = tid - wl, quad_s = wl & 3;
+    const int wbs = wb / LPA;                    // the wave's first atom slot
     GridView gv = A.g;
     if constexpr (STORE == GFF_STORE_F32 || STORE == GFF_STORE_F16) fetch_scales(gv);
 
@@ -603,7 +631,7 @@ k_replicas(KArgs A) {
         const int4 pinfo = A.packs[pk];
         const TypeInfo ti = A.t.types[pinfo.x];
         const int n = ti.n, nrep = pinfo.y, abase = ti.abase, nt = ti.nt;
-        const int lr = tid / n, at = tid - lr * n;
+        const int lr = slot / n, at = slot - lr * n;
         const bool active = lr < nrep;
         const int rbase = active ? lr * n : 0;
         int rep = 0, g = 0;
@@ -622,16 +650,16 @@ k_replicas(KArgs A) {
             ex = A.t.excl[abase + at];
             khalf = A.t.khalf[abase + at];
             st = MODE == MODE_EVAL ? 0u : A.status[rep];
-            if (MODE == MODE_FIRE) { fdt = A.fdt[rep]; fal = A.falpha[rep]; fnp = A.fnpos[rep]; }
-            if (MODE == MODE_FIRE && A.fixed_atom != nullptr && A.fixed_atom[rep] == at) {
+            if (FIRE) { fdt = A.fdt[rep]; fal = A.falpha[rep]; fnp = A.fnpos[rep]; }
+            if (FIRE && A.fixed_atom != nullptr && A.fixed_atom[rep] == at) {
                 held = true;
                 const float *tp = A.path ? A.path + 3 * (size_t)rep * A.n_points : A.fixed_pos + 3 * rep;
                 x = make_float3(tp[0], tp[1], tp[2]);
                 v = make_float3(0.f, 0.f, 0.f);
             }
         }
-        s_plq[tid] = me;
-        s_nf[tid] = 0;
+        if (sub == 0) s_plq[slot] = me;
+        if (tid < NS) s_nf[tid] = 0;
         for (int k = tid; k < ti.blob_words; k += BT) s_topo[k] = A.t.blob[ti.blob_off + k];
         if (MODE == MODE_NVE)
             for (int k = tid; k < 6 * nrep; k += BT) s_drift[k] = 0.0;
@@ -650,8 +678,10 @@ k_replicas(KArgs A) {
         const int RL = n >= 4 ? 4 : 1;
         const int rr = RL == 4 ? (tid >> 2) : tid, rq = tid - rr * RL;
         const bool reducer = rr < nrep;
-        float cm[4][16];                        // cached pre-mixed stencil planes (CACHE)
-        int cid[4] = {-1, -1, -1, -1};          // their stencil ids (-1: none)
+        float cm[R][16];                        // cached pre-mixed stencil planes (CACHE)
+        int cid[R];                             // their stencil ids (-1: none)
+#pragma unroll
+        for (int r = 0; r < R; ++r) cid[r] = -1;
         float4 tq[8];                           // trilinear: the cell's pre-mixed corners
         int tcid = -1;                          // their cell (CACHE; -1: none)
 
@@ -660,6 +690,7 @@ k_replicas(KArgs A) {
         // is cleared two steps before it is used again, so a wave that lags behind (no block
         // barrier between two steps' barrier A in some modes) still reads its own step's flag
         int aslot = 0;
+        int chk = 0;                     // FIRE: moves since the last replica-wide check
         for (int it = 0; it <= total; ++it, aslot = aslot == 2 ? 0 : aslot + 1) {
             const int par = it & 1;
             float4 *sp = par ? s_pos1 : s_pos0;
@@ -678,7 +709,7 @@ k_replicas(KArgs A) {
             }
             if (live) s_any[aslot] = 1;
             if (tid == 0) s_any[aslot == 2 ? 0 : aslot + 1] = 0;
-            sp[tid] = make_float4(x.x, x.y, x.z, 0.f);
+            if (sub == 0) sp[slot] = make_float4(x.x, x.y, x.z, 0.f);
             lds_sync();                                          // A: positions visible
             if (s_any[aslot] == 0) break;                        // every replica of the pack is done
             if (MODE == MODE_NVE && live && s_nf[lr]) { st |= GFF_REP_NONFINITE; live = false; }
@@ -722,8 +753,10 @@ k_replicas(KArgs A) {
                 GridKey key = grid_key(gv, x.x, x.y, x.z, t, fk);
                 if (!live) key.valid = 0;
                 else fl |= fk;
-                s_gi[tid] = make_int4(key.i, key.j, key.k, key.valid);
-                s_gt[tid] = t;
+                if (sub == 0) {
+                    s_gi[slot] = make_int4(key.i, key.j, key.k, key.valid);
+                    s_gt[slot] = t;
+                }
                 wave_sync();
                 if constexpr (CACHE) {
                     // stencils stay in registers across steps; a quad reloads its plane
@@ -732,22 +765,22 @@ k_replicas(KArgs A) {
                     // mixed after it, so the pair work covers the memory latency.
                     const bool pairs = A.include_intra && live;
 #pragma unroll
-                    for (int rnd = 0; rnd < 4; ++rnd) {
-                        const int o = wb + 16 * rnd + (wl >> 2);
+                    for (int rnd = 0; rnd < R; ++rnd) {
+                        const int o = wbs + 16 * rnd + (wl >> 2);
                         const int4 ki = s_gi[o];
                         const int id = stencil_id(gv, ki);
                         const bool need = id != cid[rnd] && id >= 0;
                         RawNode<STORE> c[8];
                         if (need) quad_issue<STORE>(gv, quad_addr<STORE>(gv, ki, quad_s), 0, c);
-                        if (pairs) pair_range(A, sp, s_plq, rbase, (2 * rnd) * n / 8, (2 * rnd + 1) * n / 8, x, me, ex,
-                                              pfx, pfy, pfz, pe);
+                        if (pairs) pair_range<LPA>(A, sp, s_plq, rbase, (2 * rnd) * n / (2 * R),
+                                                   (2 * rnd + 1) * n / (2 * R), x, me, ex, sub, pfx, pfy, pfz, pe);
                         if (need) {
                             const float4 po = s_plq[o];
                             quad_mix<STORE>(c, po.x * gv.s0, po.y * gv.s1, po.z * gv.s2, 0, cm[rnd]);
                             quad_issue<STORE>(gv, quad_addr<STORE>(gv, ki, quad_s), 2, c);
                         }
-                        if (pairs) pair_range(A, sp, s_plq, rbase, (2 * rnd + 1) * n / 8, (2 * rnd + 2) * n / 8, x, me,
-                                              ex, pfx, pfy, pfz, pe);
+                        if (pairs) pair_range<LPA>(A, sp, s_plq, rbase, (2 * rnd + 1) * n / (2 * R),
+                                                   (2 * rnd + 2) * n / (2 * R), x, me, ex, sub, pfx, pfy, pfz, pe);
                         if (need) {
                             const float4 po = s_plq[o];
                             quad_mix<STORE>(c, po.x * gv.s0, po.y * gv.s1, po.z * gv.s2, 2, cm[rnd]);
@@ -758,8 +791,8 @@ k_replicas(KArgs A) {
                     }
                 } else {
 #pragma unroll 1
-                    for (int rnd = 0; rnd < 4; ++rnd) {
-                        const int o = wb + 16 * rnd + (wl >> 2);
+                    for (int rnd = 0; rnd < R; ++rnd) {
+                        const int o = wbs + 16 * rnd + (wl >> 2);
                         const int4 ki = s_gi[o];
                         const float4 ko = s_gt[o];
                         const float4 po = s_plq[o];
@@ -770,7 +803,7 @@ k_replicas(KArgs A) {
                     }
                 }
                 wave_sync();
-                const float4 r = s_gres[tid];
+                const float4 r = s_gres[slot];
                 e_grid = r.x;
                 F = make_float3(-r.y * gv.idx, -r.z * gv.idy, -r.w * gv.idz);
                 if (fk & GFF_REP_NONFINITE) {
@@ -781,55 +814,61 @@ k_replicas(KArgs A) {
             // --- intramolecular: torsion terms once per term, pairs/bonds/angles per atom
             float e_intra = 0.f;
             if (A.include_intra) {
+                float fx = 0.f, fy = 0.f, fz = 0.f;
                 if (live) {
-                    for (int q = at; q < nt; q += n) {
+                    for (int q = at * LPA + sub; q < nt; q += n * LPA) {
                         float4 oA, oB;
                         e_intra += torsion_term(reinterpret_cast<const TorDef *>(s_topo + ti.o_tor)[q], sp, rbase,
                                                 oA, oB);
                         s_tres[2 * (lr * nt + q)] = oA;
                         s_tres[2 * (lr * nt + q) + 1] = oB;
                     }
-                    float fx = 0.f, fy = 0.f, fz = 0.f;
                     if constexpr (CACHE && STORE != STORE_TRI) {
                         fx = pfx; fy = pfy; fz = pfz;
                         e_intra += 0.5f * pe;
                     } else {
                         float e = 0.f;
-                        pair_range(A, sp, s_plq, rbase, 0, n, x, me, ex, fx, fy, fz, e);
+                        pair_range<LPA>(A, sp, s_plq, rbase, 0, n, x, me, ex, sub, fx, fy, fz, e);
                         e_intra += 0.5f * e;
                     }
-                    e_intra += bond_angle_terms(A, sp, rbase, abase, at, x, fx, fy, fz);
+                    e_intra += bond_angle_terms<LPA>(A, sp, rbase, abase, at, sub, x, fx, fy, fz);
+                }
+                if constexpr (LPA > 1) {                         // the atom's sub-lanes' shares
+                    fx = sub_sum<LPA>(fx); fy = sub_sum<LPA>(fy); fz = sub_sum<LPA>(fz);
+                    e_intra = sub_sum<LPA>(e_intra);
+                    if (live) F = F + make_float3(fx, fy, fz);
+                } else if (live) {
                     F = F + make_float3(fx, fy, fz);
                 }
                 lds_sync();                                      // B: torsion results visible
+                fx = 0.f; fy = 0.f; fz = 0.f;
                 if (live) {
                     // the atom's shares of its incident terms: F_i = A, F_j = -(1+p) A + q B,
                     // F_k = p A - (1+q) B, F_l = B (incidence code: term << 2 | slot)
                     const int *tinc = reinterpret_cast<const int *>(s_topo + ti.o_tinc);
-                    float fx = 0.f, fy = 0.f, fz = 0.f;
                     if constexpr (MODE == MODE_NVE) {
                         // one branch-free loop per slot group (the incidences are stored grouped)
                         const int4 *itg = reinterpret_cast<const int4 *>(s_topo + ((n + 1) >> 1));
                         const int4 r = itg[at];
                         const int e3 = itg[at + 1].x;
                         const float4 *tr = s_tres + 2 * lr * nt;
-                        for (int c = r.x; c < r.y; ++c) {
+                        for (int c = r.x + sub; c < r.y; c += LPA) {
                             const float4 ra = tr[2 * (tinc[c] >> 2)];
                             fx += ra.x; fy += ra.y; fz += ra.z;
                         }
-                        for (int c = r.y; c < r.z; ++c) {
+                        for (int c = r.y + sub; c < r.z; c += LPA) {
                             const int q = tinc[c] >> 2;
                             const float4 ra = tr[2 * q], rb = tr[2 * q + 1];
                             const float ca = -(1.f + ra.w);
                             fx += ca * ra.x + rb.w * rb.x; fy += ca * ra.y + rb.w * rb.y; fz += ca * ra.z + rb.w * rb.z;
                         }
-                        for (int c = r.z; c < r.w; ++c) {
+                        for (int c = r.z + sub; c < r.w; c += LPA) {
                             const int q = tinc[c] >> 2;
                             const float4 ra = tr[2 * q], rb = tr[2 * q + 1];
                             const float cb = -(1.f + rb.w);
                             fx += ra.w * ra.x + cb * rb.x; fy += ra.w * ra.y + cb * rb.y; fz += ra.w * ra.z + cb * rb.z;
                         }
-                        for (int c = r.w; c < e3; ++c) {
+                        for (int c = r.w + sub; c < e3; c += LPA) {
                             const float4 rb = tr[2 * (tinc[c] >> 2) + 1];
                             fx += rb.x; fy += rb.y; fz += rb.z;
                         }
@@ -837,7 +876,7 @@ k_replicas(KArgs A) {
                         // one loop over the incidences, the slot from the code (the FIRE and
                         // Langevin kernels run faster in this form)
                         const int2 itc = reinterpret_cast<const int2 *>(s_topo)[at];
-                        for (int c = itc.x; c < itc.x + itc.y; ++c) {
+                        for (int c = itc.x + sub; c < itc.x + itc.y; c += LPA) {
                             const int code = tinc[c];
                             const int q = code >> 2, slot = code & 3;
                             const float4 ra = s_tres[2 * (lr * nt + q)], rb = s_tres[2 * (lr * nt + q) + 1];
@@ -849,15 +888,25 @@ k_replicas(KArgs A) {
                             fx += ca * ra.x + cb * rb.x; fy += ca * ra.y + cb * rb.y; fz += ca * ra.z + cb * rb.z;
                         }
                     }
+                }
+                if constexpr (LPA > 1) {
+                    fx = sub_sum<LPA>(fx); fy = sub_sum<LPA>(fy); fz = sub_sum<LPA>(fz);
+                    if (live) F = F + make_float3(fx, fy, fz);
+                } else if (live) {
                     F = F + make_float3(fx, fy, fz);
                 }
             }
             if (live) e_atom = e_grid + e_intra;
-            if (MODE == MODE_FIRE && held) F = make_float3(0.f, 0.f, 0.f);   // the restraint's reaction
+            if (FIRE && held) F = make_float3(0.f, 0.f, 0.f);   // the restraint's reaction
 
             if (MODE == MODE_EVAL) break;
 
-            if (MODE == MODE_FIRE && A.check_every > 1 && it % A.check_every != 0 && it < total) {
+            bool between_checks = false;
+            if constexpr (MODE == MODE_FIRE_CHECKED) {
+                between_checks = chk != 0 && it < total;
+                if (++chk == A.check_every) chk = 0;
+            }
+            if (between_checks) {
                 // a move between checks: no sums over the replica, a plain kick and capped
                 // move with the current dt (block-uniform condition: no barrier is skipped
                 // by some waves only)
@@ -869,9 +918,9 @@ k_replicas(KArgs A) {
                     x = x + d;
                     steps++;
                 }
-            } else if (MODE == MODE_FIRE) {
+            } else if (FIRE) {
                 const bool scan = A.path != nullptr;
-                s_red[tid] = make_float4(dot(F, F), dot(F, v), dot(v, v), scan ? e_atom : 0.f);
+                if (sub == 0) s_red[slot] = make_float4(dot(F, F), dot(F, v), dot(v, v), scan ? e_atom : 0.f);
                 lds_sync();                                      // C: partials visible
                 if (reducer) {                                   // reducer lanes of replica rr
                     float ff = 0.f, fv = 0.f, vv = 0.f, ee = 0.f;
@@ -896,12 +945,12 @@ k_replicas(KArgs A) {
                     } else if (scan && (conv || spt >= A.mpp)) {
                         // the point is done: record it, then restart FIRE at the next point
                         const size_t o = (size_t)rep * A.n_points + pt;
-                        if (at == 0) {
+                        if (at == 0 && sub == 0) {
                             A.E_pts[o] = (double)sm.w;
                             if (A.steps_pts) A.steps_pts[o] = spt;
                             if (A.st_pts) A.st_pts[o] = conv ? GFF_REP_CONVERGED : GFF_REP_MAXSTEPS;
                         }
-                        if (A.pos_pts) {
+                        if (A.pos_pts && sub == 0) {
                             const size_t N3 = 3 * (size_t)N;
                             A.pos_pts[pt * N3 + g] = x.x; A.pos_pts[pt * N3 + g + N] = x.y;
                             A.pos_pts[pt * N3 + g + 2 * N] = x.z;
@@ -949,7 +998,7 @@ k_replicas(KArgs A) {
                 if (live && it > 0) v = v + (0.5f * A.dt * me.w) * F;
                 if (A.drift != nullptr && (it % A.drift_every) == 0) {
                     const double ke = (double)khalf * ((double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z);
-                    s_red64[tid] = live ? make_double2((double)e_atom, ke) : make_double2(0.0, 0.0);
+                    if (sub == 0) s_red64[slot] = live ? make_double2((double)e_atom, ke) : make_double2(0.0, 0.0);
                     lds_sync();                                  // C: partials visible
                     if (reducer && !s_nf[rr]) {                  // reducer lanes of replica rr
                         double ep = 0.0, kk = 0.0;
@@ -988,9 +1037,9 @@ k_replicas(KArgs A) {
         // ---- outputs: per-atom state, then per-replica sums (FP64) and flags
         lds_sync();       // the last reductions' LDS reads precede these writes
         if (MODE == MODE_NVE && live && s_nf[lr]) { st |= GFF_REP_NONFINITE; live = false; }
-        s_red64[tid] = make_double2((double)e_atom, (double)fl);
+        if (sub == 0) s_red64[slot] = make_double2((double)e_atom, (double)fl);
         lds_sync();
-        if (active) {
+        if (active && sub == 0) {
             if (MODE != MODE_EVAL) {
                 A.pos[g] = x.x; A.pos[g + N] = x.y; A.pos[g + 2 * N] = x.z;
                 A.vel[g] = v.x; A.vel[g + N] = v.y; A.vel[g + 2 * N] = v.z;
@@ -1007,7 +1056,7 @@ k_replicas(KArgs A) {
                     fo |= (unsigned)r.y;
                 }
                 st |= fo;
-                if (MODE == MODE_FIRE && A.f_conv > 0.f && !(st & (GFF_REP_CONVERGED | GFF_REP_NONFINITE)))
+                if (FIRE && A.f_conv > 0.f && !(st & (GFF_REP_CONVERGED | GFF_REP_NONFINITE)))
                     st |= GFF_REP_MAXSTEPS;
                 if (st & GFF_REP_NONFINITE) { es = __builtin_nan(""); fnorm = __builtin_nanf(""); }
                 if (A.E_rep) A.E_rep[rep] = es;
@@ -1016,7 +1065,7 @@ k_replicas(KArgs A) {
                     if (A.fnorm) A.fnorm[rep] = fnorm;
                     if (A.steps) A.steps[rep] = steps;
                 }
-                if (MODE == MODE_FIRE) { A.fdt[rep] = fdt; A.falpha[rep] = fal; A.fnpos[rep] = fnp; }
+                if (FIRE) { A.fdt[rep] = fdt; A.falpha[rep] = fal; A.fnpos[rep] = fnp; }
             }
         }
         if (MODE == MODE_NVE && A.drift && reducer && rq == 0) {
@@ -1102,12 +1151,32 @@ static void fill_common(KArgs &A, const gff_topology *topo, const gff_plan *plan
     A.max_pack_reps = plan->max_pack_reps; A.topo_words = plan->topo_words;
 }
 
-template <int STORE, int MODE, bool CACHE>
+template <int STORE, int MODE, bool CACHE, int LPA>
 static void launch_one(int grid, int BT, size_t lds, const KArgs &A, hipStream_t s) {
     if (lds > 65536)
-        (void)hipFuncSetAttribute((const void *)k_replicas<STORE, MODE, CACHE>,
+        (void)hipFuncSetAttribute((const void *)k_replicas<STORE, MODE, CACHE, LPA>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL((k_replicas<STORE, MODE, CACHE>), dim3(grid), dim3(BT), lds, s, A);
+    hipLaunchKernelGGL((k_replicas<STORE, MODE, CACHE, LPA>), dim3(grid), dim3(BT), lds, s, A);
+}
+
+// Lanes per atom of the launch: the plan's value for B-spline relaxation and dynamics, one
+// for evaluations and the other storages (which then run the plan's packing one lane per atom).
+static int launch_lpa(int storage, int mode, const gff_plan *plan) {
+    const bool multi = mode != MODE_EVAL && (storage == GFF_STORE_F32 || storage == GFF_STORE_F16);
+    return multi ? plan->lanes_per_atom : 1;
+}
+
+static size_t launch_lds(const gff_plan *plan, int lpa) {
+    return replica_lds_bytes(plan->block_threads / lpa, plan->tres_max, plan->max_pack_reps, plan->topo_words);
+}
+
+template <int STORE, int MODE, bool CACHE>
+static void launch_lpa_sel(int lpa, int grid, int BT, size_t lds, const KArgs &A, hipStream_t s) {
+    if constexpr ((STORE == GFF_STORE_F32 || STORE == GFF_STORE_F16) && MODE != MODE_EVAL) {
+        if (lpa == 4) { launch_one<STORE, MODE, CACHE, 4>(grid, BT, lds, A, s); return; }
+        if (lpa == 2) { launch_one<STORE, MODE, CACHE, 2>(grid, BT, lds, A, s); return; }
+    }
+    launch_one<STORE, MODE, CACHE, 1>(grid, BT, lds, A, s);
 }
 
 // Relaxation and MD launches keep stencils in registers when the block fits the cached
@@ -1115,44 +1184,55 @@ static void launch_one(int grid, int BT, size_t lds, const KArgs &A, hipStream_t
 template <int MODE>
 static gff_status launch_mode(int storage, const gff_plan *plan, KArgs &A, hipStream_t s) {
     const int BT = plan->block_threads;
-    const size_t lds = replica_lds_bytes(BT, plan->tres_max, plan->max_pack_reps, plan->topo_words);
+    const int lpa = launch_lpa(storage, MODE, plan);
+    const size_t lds = launch_lds(plan, lpa);
+    if (lds > (size_t)plan->lds_limit) return GFF_EUNSUPPORTED;
     const int grid = plan->grid_blocks > 0 ? std::min(plan->grid_blocks, plan->n_packs) : plan->n_packs;
     if (grid <= 0) return GFF_OK;
     constexpr bool can_cache = MODE != MODE_EVAL;
     const bool cache = can_cache && BT <= 512;
     if (storage == STORE_DIRECT) {
-        launch_one<STORE_DIRECT, MODE, false>(grid, BT, lds, A, s);
+        launch_one<STORE_DIRECT, MODE, false, 1>(grid, BT, lds, A, s);
     } else if (storage == STORE_TRI) {
-        if (cache) launch_one<STORE_TRI, MODE, can_cache>(grid, BT, lds, A, s);
-        else launch_one<STORE_TRI, MODE, false>(grid, BT, lds, A, s);
+        if (cache) launch_one<STORE_TRI, MODE, can_cache, 1>(grid, BT, lds, A, s);
+        else launch_one<STORE_TRI, MODE, false, 1>(grid, BT, lds, A, s);
     } else if (storage == GFF_STORE_F32) {
-        if (cache) launch_one<GFF_STORE_F32, MODE, can_cache>(grid, BT, lds, A, s);
-        else launch_one<GFF_STORE_F32, MODE, false>(grid, BT, lds, A, s);
+        if (cache) launch_lpa_sel<GFF_STORE_F32, MODE, can_cache>(lpa, grid, BT, lds, A, s);
+        else launch_lpa_sel<GFF_STORE_F32, MODE, false>(lpa, grid, BT, lds, A, s);
     } else {
-        if (cache) launch_one<GFF_STORE_F16, MODE, can_cache>(grid, BT, lds, A, s);
-        else launch_one<GFF_STORE_F16, MODE, false>(grid, BT, lds, A, s);
+        if (cache) launch_lpa_sel<GFF_STORE_F16, MODE, can_cache>(lpa, grid, BT, lds, A, s);
+        else launch_lpa_sel<GFF_STORE_F16, MODE, false>(lpa, grid, BT, lds, A, s);
     }
     return hip_status(hipGetLastError());
 }
 
-template <int STORE, int MODE, bool CACHE>
+template <int STORE, int MODE, bool CACHE, int LPA>
 static gff_status occupancy_one(int BT, size_t lds, int *blocks) {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_replicas<STORE, MODE, CACHE>, BT, lds) ==
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_replicas<STORE, MODE, CACHE, LPA>, BT, lds) ==
                    hipSuccess ? GFF_OK : GFF_EHIP;
 }
 
+template <int STORE, int MODE, bool CACHE>
+static gff_status occupancy_lpa_sel(int lpa, int BT, size_t lds, int *blocks) {
+    if constexpr ((STORE == GFF_STORE_F32 || STORE == GFF_STORE_F16) && MODE != MODE_EVAL) {
+        if (lpa == 4) return occupancy_one<STORE, MODE, CACHE, 4>(BT, lds, blocks);
+        if (lpa == 2) return occupancy_one<STORE, MODE, CACHE, 2>(BT, lds, blocks);
+    }
+    return occupancy_one<STORE, MODE, CACHE, 1>(BT, lds, blocks);
+}
+
 template <int MODE>
-static gff_status occupancy_mode(int storage, int BT, size_t lds, int *blocks) {
+static gff_status occupancy_mode(int storage, int lpa, int BT, size_t lds, int *blocks) {
     constexpr bool can_cache = MODE != MODE_EVAL;
     const bool cache = can_cache && BT <= 512;
     if (storage == STORE_TRI)
-        return cache ? occupancy_one<STORE_TRI, MODE, can_cache>(BT, lds, blocks)
-                     : occupancy_one<STORE_TRI, MODE, false>(BT, lds, blocks);
+        return cache ? occupancy_one<STORE_TRI, MODE, can_cache, 1>(BT, lds, blocks)
+                     : occupancy_one<STORE_TRI, MODE, false, 1>(BT, lds, blocks);
     if (storage == GFF_STORE_F32)
-        return cache ? occupancy_one<GFF_STORE_F32, MODE, can_cache>(BT, lds, blocks)
-                     : occupancy_one<GFF_STORE_F32, MODE, false>(BT, lds, blocks);
-    return cache ? occupancy_one<GFF_STORE_F16, MODE, can_cache>(BT, lds, blocks)
-                 : occupancy_one<GFF_STORE_F16, MODE, false>(BT, lds, blocks);
+        return cache ? occupancy_lpa_sel<GFF_STORE_F32, MODE, can_cache>(lpa, BT, lds, blocks)
+                     : occupancy_lpa_sel<GFF_STORE_F32, MODE, false>(lpa, BT, lds, blocks);
+    return cache ? occupancy_lpa_sel<GFF_STORE_F16, MODE, can_cache>(lpa, BT, lds, blocks)
+                 : occupancy_lpa_sel<GFF_STORE_F16, MODE, false>(lpa, BT, lds, blocks);
 }
 
 }  // namespace gff
@@ -1165,13 +1245,16 @@ extern "C" gff_status gff_relax_occupancy(const gff_grid *grid, const gff_plan *
     if (grid->storage != GFF_STORE_F32 && grid->storage != GFF_STORE_F16 && grid->storage != STORE_TRI)
         return GFF_EUNSUPPORTED;
     const int BT = plan->block_threads;
-    const size_t lds = replica_lds_bytes(BT, plan->tres_max, plan->max_pack_reps, plan->topo_words);
+    const int kmode = mode == -1 ? MODE_EVAL : (mode == GFF_MODE_FIRE ? MODE_FIRE :
+                      (mode == GFF_MODE_NVE ? MODE_NVE : (mode == GFF_MODE_LANGEVIN ? MODE_LANGEVIN : -1)));
+    if (kmode < 0) return GFF_EINVAL;
+    const int lpa = launch_lpa(grid->storage, kmode, plan);
+    const size_t lds = launch_lds(plan, lpa);
     if (lds_bytes_out) *lds_bytes_out = lds;
-    if (mode == -1) return occupancy_mode<MODE_EVAL>(grid->storage, BT, lds, blocks_per_cu);
-    if (mode == GFF_MODE_FIRE) return occupancy_mode<MODE_FIRE>(grid->storage, BT, lds, blocks_per_cu);
-    if (mode == GFF_MODE_NVE) return occupancy_mode<MODE_NVE>(grid->storage, BT, lds, blocks_per_cu);
-    if (mode == GFF_MODE_LANGEVIN) return occupancy_mode<MODE_LANGEVIN>(grid->storage, BT, lds, blocks_per_cu);
-    return GFF_EINVAL;
+    if (kmode == MODE_EVAL) return occupancy_mode<MODE_EVAL>(grid->storage, lpa, BT, lds, blocks_per_cu);
+    if (kmode == MODE_FIRE) return occupancy_mode<MODE_FIRE>(grid->storage, lpa, BT, lds, blocks_per_cu);
+    if (kmode == MODE_NVE) return occupancy_mode<MODE_NVE>(grid->storage, lpa, BT, lds, blocks_per_cu);
+    return occupancy_mode<MODE_LANGEVIN>(grid->storage, lpa, BT, lds, blocks_per_cu);
 }
 
 static gff_status eval_common(int storage, KArgs &A, const gff_topology *topo, const gff_plan *plan,
@@ -1222,7 +1305,9 @@ static gff_status relax_common(int storage, KArgs &A, const gff_topology *topo, 
     const double c1 = std::exp(-(double)p->gamma * (double)p->dt);
     A.lg_c1 = (float)c1; A.lg_c2 = (float)std::sqrt(std::max(0.0, 1.0 - c1 * c1)); A.kT = p->kT;
     A.seed_lo = (unsigned)(p->seed & 0xffffffffull); A.seed_hi = (unsigned)(p->seed >> 32); A.round = p->round;
-    if (p->mode == GFF_MODE_FIRE) return launch_mode<MODE_FIRE>(storage, plan, A, s);
+    if (p->mode == GFF_MODE_FIRE)
+        return A.check_every > 1 ? launch_mode<MODE_FIRE_CHECKED>(storage, plan, A, s)
+                                 : launch_mode<MODE_FIRE>(storage, plan, A, s);
     if (p->mode == GFF_MODE_LANGEVIN) return launch_mode<MODE_LANGEVIN>(storage, plan, A, s);
     return launch_mode<MODE_NVE>(storage, plan, A, s);
 }

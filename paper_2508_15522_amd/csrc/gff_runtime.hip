@@ -57,7 +57,8 @@ extern "C" void gff_graph_destroy(gff_graph *g) {
 }
 
 // Measured choice of the launch shape for a batch: every candidate block size (and, per
-// block size, the packings below and persistent grids of 1-4 blocks per CU) runs `params` on
+// block size, the packings below, persistent grids of 1-4 blocks per CU and, for small
+// batches on B-spline grids, 2 or 4 lanes per atom) runs `params` on
 // a copy of the caller's state; the fastest (replica-steps per second) wins.
 // Candidates that the device cannot launch are skipped.  The caller's state is untouched.
 extern "C" gff_status gff_autotune(const gff_grid *grid, const gff_topology *topo, int n_rep, const int *rep_type_h,
@@ -97,19 +98,24 @@ extern "C" gff_status gff_autotune(const gff_grid *grid, const gff_topology *top
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
     float best_t = -1.f;
-    gff_launch chosen{256, 0, 0};
+    gff_launch chosen{256, 0, 0, 1};
     gff_status rc = GFF_OK;
     // replicas per block: the densest packing, and when that leaves fewer than two packs per
     // compute unit, sparser packings (at most 1, 2, 4, 8 replicas per block) that spread a
-    // small batch over more of the GPU
+    // small batch over more of the GPU; lanes per atom 2 and 4 (B-spline grids) when the batch
+    // has fewer atoms than one wave per SIMD of the GPU
     const int rpb_cand[5] = {0, 1, 2, 4, 8};
+    const bool bspline = grid->storage == GFF_STORE_F32 || grid->storage == GFF_STORE_F16;
+    const bool small = (long)n_atoms < 4L * 64 * n_cu;
+    for (int lpa = 1; lpa <= 4 && rc == GFF_OK; lpa *= 2) {
+    if (lpa > 1 && !(bspline && small)) break;
     for (int bt = 64; bt <= 1024 && rc == GFF_OK; bt += 64) {
-        if (bt < max_n) continue;
+        if (bt < max_n * lpa) continue;
         int dense_packs = -1, last_packs = -1;
         for (int ri = 0; ri < 5 && rc == GFF_OK; ++ri) {
             if (ri > 0 && (dense_packs < 0 || dense_packs >= 2 * n_cu)) break;
             for (int gm = 0; gm <= 4; ++gm) {
-                gff_launch L{bt, rpb_cand[ri], gm == 0 ? 0 : gm * n_cu};
+                gff_launch L{bt, rpb_cand[ri], gm == 0 ? 0 : gm * n_cu, lpa};
                 gff_plan *plan = nullptr;
                 if (gff_plan_create(topo, n_rep, rep_type_h, &L, &plan) != GFF_OK) break;
                 if (gm == 0) {
@@ -143,6 +149,7 @@ extern "C" gff_status gff_autotune(const gff_grid *grid, const gff_topology *top
                 if (best_t < 0.f || ms < best_t) { best_t = ms; chosen = L; }
             }
         }
+    }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

@@ -54,7 +54,8 @@ class MolType(C.Structure):
 
 
 class Launch(C.Structure):
-    _fields_ = [("block_threads", C.c_int), ("reps_per_block", C.c_int), ("grid_blocks", C.c_int)]
+    _fields_ = [("block_threads", C.c_int), ("reps_per_block", C.c_int), ("grid_blocks", C.c_int),
+                ("lanes_per_atom", C.c_int)]
 
 
 class RelaxParams(C.Structure):
@@ -205,11 +206,12 @@ class Topology:
 
 
 class Plan:
-    def __init__(self, topo: Topology, rep_type, block_threads=256, reps_per_block=0, grid_blocks=0):
+    def __init__(self, topo: Topology, rep_type, block_threads=256, reps_per_block=0, grid_blocks=0,
+                 lanes_per_atom=1):
         rt = np.ascontiguousarray(rep_type, dtype=np.int32)
         self.n_rep = len(rt)
         self.handle = C.c_void_p()
-        self.launch = Launch(block_threads, reps_per_block, grid_blocks)
+        self.launch = Launch(block_threads, reps_per_block, grid_blocks, lanes_per_atom)
         check(lib().gff_plan_create(topo.handle, C.c_int(self.n_rep), rt.ctypes.data_as(C.c_void_p),
                                     C.byref(self.launch), C.byref(self.handle)))
         self.n_atoms = lib().gff_plan_n_atoms(self.handle)

@@ -151,3 +151,23 @@ def test_c3_sizes_autotuned_full_size_sampled():
     plan = G.Plan(topo, rep_type, *launch)
     idx = _sample(n_rep, extra=range(8, 16))                   # every molecule size
     _fire_check(grid, Bref, mols, rep_type, pos, plan, topo, 10, idx)
+
+
+def test_c1_chain_autotuned_full_size_sampled():
+    """The chain workload (256 x 24 atoms, far too few to fill the GPU) in its autotuned launch
+    shape, which may use several lanes per atom; sampled replicas against the oracle."""
+    D.require_gpu()
+    announce("full size: 256 x chain24 FIRE, autotuned launch")
+    cfg = configs.GRID_SMALL
+    grid, Bref = _grid(cfg, 25)
+    mol = S.mol_chain24()
+    n_rep = configs.C1_CHAIN_FIRE.n_rep
+    rep_type = np.zeros(n_rep, np.int32)
+    pos = list(S.f32(S.place_replicas(mol, n_rep, cfg.substrate(), S.SEED_PLACE)))
+    topo = G.Topology([mol])
+    st0 = D.fire_state(G.Plan(topo, rep_type), pos)
+    launch, rate = AT.launch_for(grid, topo, rep_type, G.relax_params(G.MODE_FIRE, 50, True, f_conv=1e-4), st0,
+                                 use_cache=False)
+    announce(f"  launch {launch} ({rate:.3e} replica-steps/s)")
+    plan = G.Plan(topo, rep_type, *launch)
+    _fire_check(grid, Bref, [mol], rep_type, pos, plan, topo, 20, _sample(n_rep))

@@ -117,16 +117,18 @@ def test_restrained_scan_follows_oracle(world):
             assert np.array_equal(xr[r][5].astype(np.float32), tg[r, k].astype(np.float32))
 
 
-def test_fused_scan_equals_point_by_point_launches(world):
+@pytest.mark.parametrize("lpa,block", [(1, 256), (4, 512)])
+def test_fused_scan_equals_point_by_point_launches(world, lpa, block):
     """gff_relax_scan (every replica advancing to its next point on its own inside one
     launch) against one launch per point with a FIRE restart in between: bit-identical
     positions after every point, identical move counts and flags, energies equal to the
-    FP32 summation order (the fused scan sums each point's energy in FP32)."""
+    FP32 summation order (the fused scan sums each point's energy in FP32); with one and with
+    four lanes per atom."""
     w = world
-    announce("fused scan vs point-by-point launches")
+    announce(f"fused scan vs point-by-point launches, lanes_per_atom={lpa}")
     rng = np.random.default_rng(21)
     rep_type = rng.integers(0, len(w["mols"]), 36)
-    plan = G.Plan(w["topo"], rep_type, block_threads=256)
+    plan = G.Plan(w["topo"], rep_type, block_threads=block, lanes_per_atom=lpa)
     # starts near minima (600 free FIRE moves), so that the points relax in tens of moves
     st = D.fire_state(plan, _positions(w, rep_type, 6700))
     out = D.outputs(plan)
