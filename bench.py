@@ -40,13 +40,13 @@ COUNTER_SCALE = {"fetch": 2.0, "write": 1.0}
 MEASURED_TRAFFIC = {
     ("f32", 16384, 5000, 192): {
         "sources": {"paper_2508_15522_amd/csrc/gff_relax.hip":
-                    "1043872c2afce3c4cb1bb2857d0f789aeb697db6bddcec1956b6f312866be174",
+                    "6bbd16d066507d949c6a83c558ac6c2cf646955188d743786f01a4f773ca67b0",
                     "paper_2508_15522_amd/csrc/gff_internal.hpp":
-                    "b090b6df99d75275733cb0c74fc406542c6559062673e1161cd6ea392b6ced4f",
+                    "678e935cc46abbe009d1a756ca08f31bb22802c80aff928cdac16a63e6c8f54e",
                     "paper_2508_15522_amd/csrc/gff_host.hip":
-                    "5e7ba03db58d76beb6af9be21a67720fe0b846376aa4ceea76cc4c3e57295003"},
-        "fetch_kib": 290547659.0, "write_kib": 100337.4375,
-        "valu_insts": 197220102503.0,          # SQ_INSTS_VALU (wave instructions) of the launch
+                    "2aa04dd935f3d23fd37d27ccea38d3373c1936d34b561ec069f5a5d707862209"},
+        "fetch_kib": 296082712.5625, "write_kib": 100337.0625,
+        "valu_insts": 203169083101.0,          # SQ_INSTS_VALU (wave instructions) of the launch
     },
 }
 # FP32 VALU issue slots per second: 256 CUs x 4 SIMDs x 2.4 GHz / 4 cycles per wave64 instruction
@@ -267,6 +267,11 @@ def main():
     log(f"eval_forces (grid only): {res['eval_interpolations_per_s']:.3e} interpolations/s, {ev_s * 1e3:.3f} ms per launch")
     res["gather_probe"] = gather_probe(grid, log)
     res["roofline"]["serving_probe_GBps"] = res["gather_probe"]["grid_coefficients"]
+    # the evaluation launch in the probe's own unit: every atom reads 16 z-column segments of
+    # four padded 16-byte nodes (64 B each, the probe's chunk), of which 48 B are coefficients
+    chunk_bytes = n_rep * mol.n * 16 * (64 if args.storage == "f32" else 32)
+    res["eval_chunk_GBps"] = chunk_bytes / ev_s / 1e9
+    res["eval_vs_gather_probe"] = res["eval_chunk_GBps"] / res["gather_probe"]["grid_coefficients"]
     if args.compare_f16 and args.storage == "f32":
         g16 = setup(G.STORE_F16)
         w16, p16, st16 = timed(g16, args.steps, 1)
@@ -345,6 +350,26 @@ def main():
         res["minima_per_s"]["short_horizon"] = {
             "proposals": [c[0] for c in uc], "uniform": [c[1] for c in uc], "learned": [c[1] for c in lc],
             "gain_first_round": rate(lc[0]) / rate(uc[0]), "gain_last_round": rate(lc[-1]) / rate(uc[-1])}
+        res["minima_per_s"]["gain_with_training"] = _gain_with_training(cmp)
+        # a landscape that does not saturate within the horizon: the 70-atom molecule of the
+        # size series (seven rotatable torsions), proposer trained on 100k of its minima
+        mol70 = [m for m in S.molecule_types("sizes") if m.n == 70][0]
+        log("learned vs uniform proposals on the 70-atom molecule")
+        c70 = SM.compare_learned_vs_uniform(g32, mol70, collect_minima=100_000, collect_rep=4096,
+                                            train_steps=args.train_steps, eval_rounds=4, eval_rep=8192, log=log,
+                                            weight_power=args.weight_power, imle_batch=args.imle_batch,
+                                            imle_k=args.imle_k)
+        res["minima_per_s_size70"] = {
+            "learned": c70["learned"]["minima_per_s"], "uniform": c70["uniform"]["minima_per_s"],
+            "gain": c70["gain_minima_per_s"], "flow_gain": c70["gain_minima_per_s_flow"],
+            "gain_with_training": _gain_with_training(c70),
+            "distinct": {"uniform": c70["uniform"]["distinct_minima"], "learned": c70["learned"]["distinct_minima"]},
+            "distinct_rmsd": {"uniform": c70["uniform"]["distinct_minima_rmsd"],
+                              "learned": c70["learned"]["distinct_minima_rmsd"]},
+            "gain_rmsd": c70["gain_minima_per_s_rmsd"], "training": c70["training"],
+            "workload": ("size-series 70-atom molecule (7 rotatable torsions), FIRE to 1e-4 eV/A (max 5000 steps), "
+                         "4 x 8192 proposals per form, distinct within 0.01 eV; proposer trained on >= 100k "
+                         "converged minima of uniform rounds")}
     if args.hopping:
         from paper_2508_15522_amd import sampling as SM
         log("minima hopping vs uniform proposals (minima found per second)")
@@ -365,6 +390,14 @@ def main():
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(mol, cfg, args.cpu_seconds)
     print(json.dumps(res), flush=True)
+
+
+def _gain_with_training(cmp):
+    """Learned over uniform distinct minima per second in rounds, with the proposer's IMLE
+    training time added to the learned form's GPU time (the collection of the training minima
+    is uniform sampling and is not counted against either form)."""
+    L, U = cmp["learned"], cmp["uniform"]
+    return (L["distinct_minima"] / (L["seconds"] + cmp["training"]["train_s"])) / max(U["minima_per_s"], 1e-12)
 
 
 def run_workload(name, log):

@@ -18,8 +18,11 @@
 
 namespace gff {
 
-enum { MODE_EVAL = 0, MODE_FIRE = 1, MODE_NVE = 2, MODE_LANGEVIN = 3,
-       MODE_FIRE_CHECKED = 4 };   // FIRE with replica-wide decisions every k-th move only
+// MODE_FIRE and MODE_FIRE_CHECKED (replica-wide decisions every k-th move only) form no
+// energies in the step loop: the final energies come from an evaluation launch after the
+// relaxation, at the same final positions.  MODE_FIRE_SCAN (restrained scans) records each
+// point's energy inside the loop.
+enum { MODE_EVAL = 0, MODE_FIRE = 1, MODE_NVE = 2, MODE_LANGEVIN = 3, MODE_FIRE_CHECKED = 4, MODE_FIRE_SCAN = 5 };
 // storage slot of the all-atom comparison mode (no grid: direct substrate sums)
 constexpr int STORE_DIRECT = 3;
 constexpr int STORE_TRI = GFF_STORE_TRILINEAR;
@@ -62,6 +65,7 @@ struct KArgs {
     float dt, f_conv, max_disp, finc, fdec, a0, falpha_f, dtmax;
     float lg_c1, lg_c2, kT;             // Langevin: exp(-gamma dt), sqrt(1 - c1^2), k_B T
     unsigned seed_lo, seed_hi, round;   // Langevin: Philox key and fourth counter word
+    const unsigned *status_in;          // EVAL after a relaxation: its flags (NONFINITE -> NaN energy)
     const int *fixed_atom;              // FIRE restraint: held atom per replica (nullable)
     const float *fixed_pos;             // its position [n_rep][3]
     // FIRE scan (nullable path): the held atom visits path[rep][p] for p = 0 .. n_points-1,
@@ -453,7 +457,7 @@ __device__ __forceinline__ int stencil_id(const GridView &g, int4 ki) {
 // P_i P_j e^{-2 alpha r} - L_i L_j e^{-alpha r}/2, plus k_e Q_i Q_j / r.  Adds the force on i
 // to (fx, fy, fz) and the full pair energies to e (the caller halves the sum).  Ranges are
 // block-uniform; consecutive ranges accumulate in the order of one pass over [0, n).
-template <int LPA>
+template <int LPA, bool WITH_E>
 __device__ __forceinline__ void pair_range(const KArgs &A, const float4 *sp, const float4 *splq, int rbase, int j0,
                                            int j1, float3 xi, float4 me, uint4 ex, int sub, float &fx, float &fy,
                                            float &fz, float &e) {
@@ -477,14 +481,14 @@ __device__ __forceinline__ void pair_range(const KArgs &A, const float4 *sp, con
             const float g = A.alpha * (2.f * eu - el) + ec * rinv;      // -dE/dr
             const float sc = skip ? 0.f : g * rinv;
             fx += sc * ddx; fy += sc * ddy; fz += sc * ddz;
-            e += skip ? 0.f : (eu - el + ec);
+            if constexpr (WITH_E) e += skip ? 0.f : (eu - el + ec);
         }
     }
 }
 
 // Bonds and angles incident to this lane's atom (each term evaluated by every
 // participant for its own slot; the slot-0 participant carries the energy).
-template <int LPA>
+template <int LPA, bool WITH_E>
 __device__ __forceinline__ float bond_angle_terms(const KArgs &A, const float4 *sp, int rbase, int abase, int at,
                                                   int sub, float3 xi, float &fx, float &fy, float &fz) {
     float e = 0.f;
@@ -496,7 +500,7 @@ __device__ __forceinline__ float bond_angle_terms(const KArgs &A, const float4 *
         const float dr = d2 * rinv - bi.r0;
         const float g = bi.k * dr * rinv;
         fx -= g * d.x; fy -= g * d.y; fz -= g * d.z;
-        if (bi.slot == 0) e += 0.5f * bi.k * dr * dr;
+        if (WITH_E && bi.slot == 0) e += 0.5f * bi.k * dr * dr;
     }
     for (int q = ia.z + sub; q < ia.z + ia.w; q += LPA) {
         const AngInc ai = A.t.ang[q];
@@ -511,7 +515,7 @@ __device__ __forceinline__ float bond_angle_terms(const KArgs &A, const float4 *
         const float3 gc = inv * u - (cs * __builtin_amdgcn_rcpf(vv)) * v;
         float3 gs = slot == 0 ? ga : (slot == 2 ? gc : make_float3(-ga.x - gc.x, -ga.y - gc.y, -ga.z - gc.z));
         fx -= de * gs.x; fy -= de * gs.y; fz -= de * gs.z;
-        if (slot == 0) e += 0.5f * ai.k * (cs - ai.cos0) * (cs - ai.cos0);
+        if (WITH_E && slot == 0) e += 0.5f * ai.k * (cs - ai.cos0) * (cs - ai.cos0);
     }
     return e;
 }
@@ -591,7 +595,8 @@ __global__ void __launch_bounds__(CACHE ? 512 : 1024) __attribute__((amdgpu_wave
 k_replicas(KArgs A) {
     static_assert(LPA == 1 || ((STORE == GFF_STORE_F32 || STORE == GFF_STORE_F16) && MODE != MODE_EVAL),
                   "several lanes per atom only for B-spline relaxation and dynamics");
-    constexpr bool FIRE = MODE == MODE_FIRE || MODE == MODE_FIRE_CHECKED;
+    constexpr bool FIRE = MODE == MODE_FIRE || MODE == MODE_FIRE_CHECKED || MODE == MODE_FIRE_SCAN;
+    constexpr bool WANT_E = MODE != MODE_FIRE && MODE != MODE_FIRE_CHECKED;   // energies in the loop
     extern __shared__ __align__(16) unsigned char smem[];
     const int BT = blockDim.x, tid = threadIdx.x;
     const int NS = BT / LPA;                     // atom slots of the block
@@ -772,14 +777,14 @@ k_replicas(KArgs A) {
                         const bool need = id != cid[rnd] && id >= 0;
                         RawNode<STORE> c[8];
                         if (need) quad_issue<STORE>(gv, quad_addr<STORE>(gv, ki, quad_s), 0, c);
-                        if (pairs) pair_range<LPA>(A, sp, s_plq, rbase, (2 * rnd) * n / (2 * R),
+                        if (pairs) pair_range<LPA, WANT_E>(A, sp, s_plq, rbase, (2 * rnd) * n / (2 * R),
                                                    (2 * rnd + 1) * n / (2 * R), x, me, ex, sub, pfx, pfy, pfz, pe);
                         if (need) {
                             const float4 po = s_plq[o];
                             quad_mix<STORE>(c, po.x * gv.s0, po.y * gv.s1, po.z * gv.s2, 0, cm[rnd]);
                             quad_issue<STORE>(gv, quad_addr<STORE>(gv, ki, quad_s), 2, c);
                         }
-                        if (pairs) pair_range<LPA>(A, sp, s_plq, rbase, (2 * rnd + 1) * n / (2 * R),
+                        if (pairs) pair_range<LPA, WANT_E>(A, sp, s_plq, rbase, (2 * rnd + 1) * n / (2 * R),
                                                    (2 * rnd + 2) * n / (2 * R), x, me, ex, sub, pfx, pfy, pfz, pe);
                         if (need) {
                             const float4 po = s_plq[o];
@@ -828,10 +833,10 @@ k_replicas(KArgs A) {
                         e_intra += 0.5f * pe;
                     } else {
                         float e = 0.f;
-                        pair_range<LPA>(A, sp, s_plq, rbase, 0, n, x, me, ex, sub, fx, fy, fz, e);
+                        pair_range<LPA, WANT_E>(A, sp, s_plq, rbase, 0, n, x, me, ex, sub, fx, fy, fz, e);
                         e_intra += 0.5f * e;
                     }
-                    e_intra += bond_angle_terms<LPA>(A, sp, rbase, abase, at, sub, x, fx, fy, fz);
+                    e_intra += bond_angle_terms<LPA, WANT_E>(A, sp, rbase, abase, at, sub, x, fx, fy, fz);
                 }
                 if constexpr (LPA > 1) {                         // the atom's sub-lanes' shares
                     fx = sub_sum<LPA>(fx); fy = sub_sum<LPA>(fy); fz = sub_sum<LPA>(fz);
@@ -919,7 +924,7 @@ k_replicas(KArgs A) {
                     steps++;
                 }
             } else if (FIRE) {
-                const bool scan = A.path != nullptr;
+                constexpr bool scan = MODE == MODE_FIRE_SCAN;
                 if (sub == 0) s_red[slot] = make_float4(dot(F, F), dot(F, v), dot(v, v), scan ? e_atom : 0.f);
                 lds_sync();                                      // C: partials visible
                 if (reducer) {                                   // reducer lanes of replica rr
@@ -1037,7 +1042,7 @@ k_replicas(KArgs A) {
         // ---- outputs: per-atom state, then per-replica sums (FP64) and flags
         lds_sync();       // the last reductions' LDS reads precede these writes
         if (MODE == MODE_NVE && live && s_nf[lr]) { st |= GFF_REP_NONFINITE; live = false; }
-        if (sub == 0) s_red64[slot] = make_double2((double)e_atom, (double)fl);
+        if (sub == 0) s_red64[slot] = make_double2(WANT_E ? (double)e_atom : 0.0, (double)fl);
         lds_sync();
         if (active && sub == 0) {
             if (MODE != MODE_EVAL) {
@@ -1045,7 +1050,7 @@ k_replicas(KArgs A) {
                 A.vel[g] = v.x; A.vel[g + N] = v.y; A.vel[g + 2 * N] = v.z;
             }
             if (MODE == MODE_EVAL) {
-                A.F[g] = F.x; A.F[g + N] = F.y; A.F[g + 2 * N] = F.z;
+                if (A.F) { A.F[g] = F.x; A.F[g + N] = F.y; A.F[g + 2 * N] = F.z; }
                 if (A.E_atom) A.E_atom[g] = e_grid;
             }
             if (at == 0) {
@@ -1058,8 +1063,9 @@ k_replicas(KArgs A) {
                 st |= fo;
                 if (FIRE && A.f_conv > 0.f && !(st & (GFF_REP_CONVERGED | GFF_REP_NONFINITE)))
                     st |= GFF_REP_MAXSTEPS;
+                if (MODE == MODE_EVAL && A.status_in && (A.status_in[rep] & GFF_REP_NONFINITE)) st |= GFF_REP_NONFINITE;
                 if (st & GFF_REP_NONFINITE) { es = __builtin_nan(""); fnorm = __builtin_nanf(""); }
-                if (A.E_rep) A.E_rep[rep] = es;
+                if (WANT_E && A.E_rep) A.E_rep[rep] = es;
                 if (A.status) A.status[rep] = st;
                 if (MODE != MODE_EVAL) {
                     if (A.fnorm) A.fnorm[rep] = fnorm;
@@ -1305,9 +1311,17 @@ static gff_status relax_common(int storage, KArgs &A, const gff_topology *topo, 
     const double c1 = std::exp(-(double)p->gamma * (double)p->dt);
     A.lg_c1 = (float)c1; A.lg_c2 = (float)std::sqrt(std::max(0.0, 1.0 - c1 * c1)); A.kT = p->kT;
     A.seed_lo = (unsigned)(p->seed & 0xffffffffull); A.seed_hi = (unsigned)(p->seed >> 32); A.round = p->round;
-    if (p->mode == GFF_MODE_FIRE)
-        return A.check_every > 1 ? launch_mode<MODE_FIRE_CHECKED>(storage, plan, A, s)
-                                 : launch_mode<MODE_FIRE>(storage, plan, A, s);
+    if (p->mode == GFF_MODE_FIRE) {
+        if (A.path) return launch_mode<MODE_FIRE_SCAN>(storage, plan, A, s);
+        const gff_status rc = A.check_every > 1 ? launch_mode<MODE_FIRE_CHECKED>(storage, plan, A, s)
+                                                : launch_mode<MODE_FIRE>(storage, plan, A, s);
+        if (rc != GFF_OK || !d_E_rep) return rc;
+        // the energies at the final positions (the relaxation loop forms forces only)
+        KArgs E = A;
+        E.F = nullptr; E.E_atom = nullptr; E.status = nullptr; E.status_in = state->d_status;
+        E.E_rep = d_E_rep;
+        return launch_mode<MODE_EVAL>(storage, plan, E, s);
+    }
     if (p->mode == GFF_MODE_LANGEVIN) return launch_mode<MODE_LANGEVIN>(storage, plan, A, s);
     return launch_mode<MODE_NVE>(storage, plan, A, s);
 }
