@@ -241,6 +241,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(args.storage, n_rep, args.md_steps, block),
+                     "effective_GBps": achieved,
                      "valu": valu_utilisation(args.storage, n_rep, args.md_steps, block, kern_avg),
                      "kernel": f"k_replicas<{args.storage},NVE>",
                      "bytes_per_launch": alg_bytes,
@@ -250,6 +251,9 @@ def main():
                      # register stencil cache removes most of the gather traffic
                      "binding_resource": "valu_issue"},
     }
+    tr = res["roofline"]["traffic"]
+    res["roofline"]["fabric_GBps"] = tr / kern_avg / 1e9 if tr else None
+    res["roofline"]["fabric_frac"] = tr / kern_avg / 1e9 / HBM_PEAK_GBS if tr else None
     # interpolation alone: one evaluation launch (grid part only, no stencil reuse) over the
     # same atoms, repeated
     F = torch.empty_like(st0["pos"])

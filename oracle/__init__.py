@@ -39,7 +39,8 @@ PINS = {
     "fire_batch": "quadratic-bowl convergence (P10); hand-worked three-move trajectory fixing the update "
                   "order (restart decided before mixing, mix then adapt, kick with the adapted dt), the "
                   "displacement cap and the convergence test before the move; restraint: held atom, "
-                  "bond-length and inactive-restraint cases",
+                  "bond-length and inactive-restraint cases; check cadence: hand-worked plain kick between "
+                  "checks",
     "nve_batch": "dt^2 scaling of the energy fluctuation (P9); drift record recomputed from its definition "
                  "at the states of separate runs (sampling cadence 3)",
     "fp16_quantize": "hand-worked scales and round-to-nearest-even ties, the Pauli residual half",

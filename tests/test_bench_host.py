@@ -49,3 +49,9 @@ def test_more_than_one_gpu_is_refused():
     assert r.returncode == 2
     assert "one GPU" in r.stderr
     assert r.stdout == ""
+
+
+def test_learned_gain_with_training_counts_the_training_time_against_the_learned_form():
+    cmp = {"learned": {"distinct_minima": 86, "seconds": 2.88}, "uniform": {"minima_per_s": 58 / 2.82},
+           "training": {"train_s": 0.61}}
+    assert bench._gain_with_training(cmp) == pytest.approx((86 / (2.88 + 0.61)) / (58 / 2.82), rel=1e-15)
