@@ -40,13 +40,13 @@ COUNTER_SCALE = {"fetch": 2.0, "write": 1.0}
 MEASURED_TRAFFIC = {
     ("f32", 16384, 5000, 192): {
         "sources": {"paper_2508_15522_amd/csrc/gff_relax.hip":
-                    "6bbd16d066507d949c6a83c558ac6c2cf646955188d743786f01a4f773ca67b0",
+                    "421638986581c61a4522949cf5f9e2245df2c91650c26a5a03a4282045bff62b",
                     "paper_2508_15522_amd/csrc/gff_internal.hpp":
                     "678e935cc46abbe009d1a756ca08f31bb22802c80aff928cdac16a63e6c8f54e",
                     "paper_2508_15522_amd/csrc/gff_host.hip":
                     "2aa04dd935f3d23fd37d27ccea38d3373c1936d34b561ec069f5a5d707862209"},
-        "fetch_kib": 296082712.5625, "write_kib": 100337.0625,
-        "valu_insts": 203169083101.0,          # SQ_INSTS_VALU (wave instructions) of the launch
+        "fetch_kib": 292717012.375, "write_kib": 100353.9375,
+        "valu_insts": 192352849774.0,          # SQ_INSTS_VALU (wave instructions) of the launch
     },
 }
 # FP32 VALU issue slots per second: 256 CUs x 4 SIMDs x 2.4 GHz / 4 cycles per wave64 instruction

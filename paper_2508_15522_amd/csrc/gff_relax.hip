@@ -693,10 +693,11 @@ k_replicas(KArgs A) {
         const int total = (MODE == MODE_EVAL) ? 0 : A.n_steps;
         // "any replica of the pack still live" flag of step it lives in slot it % 3: a slot
         // is cleared two steps before it is used again, so a wave that lags behind (no block
-        // barrier between two steps' barrier A in some modes) still reads its own step's flag
-        int aslot = 0;
-        int chk = 0;                     // FIRE: moves since the last replica-wide check
-        for (int it = 0; it <= total; ++it, aslot = aslot == 2 ? 0 : aslot + 1) {
+        // barrier between two steps' barrier A in some modes) still reads its own step's flag.
+        // The slot is derived from the step, not carried from step to step: a loop-carried
+        // counter made the register allocator shuffle the cached stencils every step.
+        for (int it = 0; it <= total; ++it) {
+            const unsigned aslot = (unsigned)it % 3u;
             const int par = it & 1;
             float4 *sp = par ? s_pos1 : s_pos0;
             float4 *s_gres = par ? s_pos0 : s_pos1;
@@ -713,7 +714,7 @@ k_replicas(KArgs A) {
                 x = x + (0.5f * A.dt) * v;
             }
             if (live) s_any[aslot] = 1;
-            if (tid == 0) s_any[aslot == 2 ? 0 : aslot + 1] = 0;
+            if (tid == 0) s_any[aslot == 2u ? 0u : aslot + 1u] = 0;
             if (sub == 0) sp[slot] = make_float4(x.x, x.y, x.z, 0.f);
             lds_sync();                                          // A: positions visible
             if (s_any[aslot] == 0) break;                        // every replica of the pack is done
@@ -818,87 +819,97 @@ k_replicas(KArgs A) {
             }
             // --- intramolecular: torsion terms once per term, pairs/bonds/angles per atom
             float e_intra = 0.f;
-            if (A.include_intra) {
-                float fx = 0.f, fy = 0.f, fz = 0.f;
-                if (live) {
-                    for (int q = at * LPA + sub; q < nt; q += n * LPA) {
-                        float4 oA, oB;
-                        e_intra += torsion_term(reinterpret_cast<const TorDef *>(s_topo + ti.o_tor)[q], sp, rbase,
-                                                oA, oB);
-                        s_tres[2 * (lr * nt + q)] = oA;
-                        s_tres[2 * (lr * nt + q) + 1] = oB;
-                    }
-                    if constexpr (CACHE && STORE != STORE_TRI) {
-                        fx = pfx; fy = pfy; fz = pfz;
-                        e_intra += 0.5f * pe;
-                    } else {
-                        float e = 0.f;
-                        pair_range<LPA, WANT_E>(A, sp, s_plq, rbase, 0, n, x, me, ex, sub, fx, fy, fz, e);
-                        e_intra += 0.5f * e;
-                    }
-                    e_intra += bond_angle_terms<LPA, WANT_E>(A, sp, rbase, abase, at, sub, x, fx, fy, fz);
+            // this lane's torsion terms (results to LDS), non-bonded pairs, bonds and angles
+            auto intra_terms = [&](float &fx, float &fy, float &fz) {
+                for (int q = at * LPA + sub; q < nt; q += n * LPA) {
+                    float4 oA, oB;
+                    e_intra += torsion_term(reinterpret_cast<const TorDef *>(s_topo + ti.o_tor)[q], sp, rbase, oA, oB);
+                    s_tres[2 * (lr * nt + q)] = oA;
+                    s_tres[2 * (lr * nt + q) + 1] = oB;
                 }
-                if constexpr (LPA > 1) {                         // the atom's sub-lanes' shares
+                if constexpr (CACHE && STORE != STORE_TRI) {
+                    fx = pfx; fy = pfy; fz = pfz;
+                    e_intra += 0.5f * pe;
+                } else {
+                    float e = 0.f;
+                    pair_range<LPA, WANT_E>(A, sp, s_plq, rbase, 0, n, x, me, ex, sub, fx, fy, fz, e);
+                    e_intra += 0.5f * e;
+                }
+                e_intra += bond_angle_terms<LPA, WANT_E>(A, sp, rbase, abase, at, sub, x, fx, fy, fz);
+            };
+            // the atom's shares of its incident torsion terms: F_i = A, F_j = -(1+p) A + q B,
+            // F_k = p A - (1+q) B, F_l = B (incidence code: term << 2 | slot)
+            auto torsion_shares = [&](float &fx, float &fy, float &fz) {
+                const int *tinc = reinterpret_cast<const int *>(s_topo + ti.o_tinc);
+                if constexpr (MODE == MODE_NVE) {
+                    // one branch-free loop per slot group (the incidences are stored grouped)
+                    const int4 *itg = reinterpret_cast<const int4 *>(s_topo + ((n + 1) >> 1));
+                    const int4 r = itg[at];
+                    const int e3 = itg[at + 1].x;
+                    const float4 *tr = s_tres + 2 * lr * nt;
+                    for (int c = r.x + sub; c < r.y; c += LPA) {
+                        const float4 ra = tr[2 * (tinc[c] >> 2)];
+                        fx += ra.x; fy += ra.y; fz += ra.z;
+                    }
+                    for (int c = r.y + sub; c < r.z; c += LPA) {
+                        const int q = tinc[c] >> 2;
+                        const float4 ra = tr[2 * q], rb = tr[2 * q + 1];
+                        const float ca = -(1.f + ra.w);
+                        fx += ca * ra.x + rb.w * rb.x; fy += ca * ra.y + rb.w * rb.y; fz += ca * ra.z + rb.w * rb.z;
+                    }
+                    for (int c = r.z + sub; c < r.w; c += LPA) {
+                        const int q = tinc[c] >> 2;
+                        const float4 ra = tr[2 * q], rb = tr[2 * q + 1];
+                        const float cb = -(1.f + rb.w);
+                        fx += ra.w * ra.x + cb * rb.x; fy += ra.w * ra.y + cb * rb.y; fz += ra.w * ra.z + cb * rb.z;
+                    }
+                    for (int c = r.w + sub; c < e3; c += LPA) {
+                        const float4 rb = tr[2 * (tinc[c] >> 2) + 1];
+                        fx += rb.x; fy += rb.y; fz += rb.z;
+                    }
+                } else {
+                    // one loop over the incidences, the slot from the code (the FIRE and
+                    // Langevin kernels run faster in this form)
+                    const int2 itc = reinterpret_cast<const int2 *>(s_topo)[at];
+                    for (int c = itc.x + sub; c < itc.x + itc.y; c += LPA) {
+                        const int code = tinc[c];
+                        const int q = code >> 2, slot = code & 3;
+                        const float4 ra = s_tres[2 * (lr * nt + q)], rb = s_tres[2 * (lr * nt + q) + 1];
+                        float ca, cb;
+                        if (slot == 0) { ca = 1.f; cb = 0.f; }
+                        else if (slot == 3) { ca = 0.f; cb = 1.f; }
+                        else if (slot == 1) { ca = -(1.f + ra.w); cb = rb.w; }
+                        else { ca = ra.w; cb = -(1.f + rb.w); }
+                        fx += ca * ra.x + cb * rb.x; fy += ca * ra.y + cb * rb.y; fz += ca * ra.z + cb * rb.z;
+                    }
+                }
+            };
+            if (A.include_intra) {
+                if constexpr (LPA == 1) {
+                    // (this form keeps the register allocation of the cached stencils stable)
+                    if (live) {
+                        float fx = 0.f, fy = 0.f, fz = 0.f;
+                        intra_terms(fx, fy, fz);
+                        F = F + make_float3(fx, fy, fz);
+                    }
+                    lds_sync();                                  // B: torsion results visible
+                    if (live) {
+                        float fx = 0.f, fy = 0.f, fz = 0.f;
+                        torsion_shares(fx, fy, fz);
+                        F = F + make_float3(fx, fy, fz);
+                    }
+                } else {
+                    // partial sums of the atom's sub-lanes, summed across them
+                    float fx = 0.f, fy = 0.f, fz = 0.f;
+                    if (live) intra_terms(fx, fy, fz);
                     fx = sub_sum<LPA>(fx); fy = sub_sum<LPA>(fy); fz = sub_sum<LPA>(fz);
                     e_intra = sub_sum<LPA>(e_intra);
                     if (live) F = F + make_float3(fx, fy, fz);
-                } else if (live) {
-                    F = F + make_float3(fx, fy, fz);
-                }
-                lds_sync();                                      // B: torsion results visible
-                fx = 0.f; fy = 0.f; fz = 0.f;
-                if (live) {
-                    // the atom's shares of its incident terms: F_i = A, F_j = -(1+p) A + q B,
-                    // F_k = p A - (1+q) B, F_l = B (incidence code: term << 2 | slot)
-                    const int *tinc = reinterpret_cast<const int *>(s_topo + ti.o_tinc);
-                    if constexpr (MODE == MODE_NVE) {
-                        // one branch-free loop per slot group (the incidences are stored grouped)
-                        const int4 *itg = reinterpret_cast<const int4 *>(s_topo + ((n + 1) >> 1));
-                        const int4 r = itg[at];
-                        const int e3 = itg[at + 1].x;
-                        const float4 *tr = s_tres + 2 * lr * nt;
-                        for (int c = r.x + sub; c < r.y; c += LPA) {
-                            const float4 ra = tr[2 * (tinc[c] >> 2)];
-                            fx += ra.x; fy += ra.y; fz += ra.z;
-                        }
-                        for (int c = r.y + sub; c < r.z; c += LPA) {
-                            const int q = tinc[c] >> 2;
-                            const float4 ra = tr[2 * q], rb = tr[2 * q + 1];
-                            const float ca = -(1.f + ra.w);
-                            fx += ca * ra.x + rb.w * rb.x; fy += ca * ra.y + rb.w * rb.y; fz += ca * ra.z + rb.w * rb.z;
-                        }
-                        for (int c = r.z + sub; c < r.w; c += LPA) {
-                            const int q = tinc[c] >> 2;
-                            const float4 ra = tr[2 * q], rb = tr[2 * q + 1];
-                            const float cb = -(1.f + rb.w);
-                            fx += ra.w * ra.x + cb * rb.x; fy += ra.w * ra.y + cb * rb.y; fz += ra.w * ra.z + cb * rb.z;
-                        }
-                        for (int c = r.w + sub; c < e3; c += LPA) {
-                            const float4 rb = tr[2 * (tinc[c] >> 2) + 1];
-                            fx += rb.x; fy += rb.y; fz += rb.z;
-                        }
-                    } else {
-                        // one loop over the incidences, the slot from the code (the FIRE and
-                        // Langevin kernels run faster in this form)
-                        const int2 itc = reinterpret_cast<const int2 *>(s_topo)[at];
-                        for (int c = itc.x + sub; c < itc.x + itc.y; c += LPA) {
-                            const int code = tinc[c];
-                            const int q = code >> 2, slot = code & 3;
-                            const float4 ra = s_tres[2 * (lr * nt + q)], rb = s_tres[2 * (lr * nt + q) + 1];
-                            float ca, cb;
-                            if (slot == 0) { ca = 1.f; cb = 0.f; }
-                            else if (slot == 3) { ca = 0.f; cb = 1.f; }
-                            else if (slot == 1) { ca = -(1.f + ra.w); cb = rb.w; }
-                            else { ca = ra.w; cb = -(1.f + rb.w); }
-                            fx += ca * ra.x + cb * rb.x; fy += ca * ra.y + cb * rb.y; fz += ca * ra.z + cb * rb.z;
-                        }
-                    }
-                }
-                if constexpr (LPA > 1) {
+                    lds_sync();                                  // B: torsion results visible
+                    fx = 0.f; fy = 0.f; fz = 0.f;
+                    if (live) torsion_shares(fx, fy, fz);
                     fx = sub_sum<LPA>(fx); fy = sub_sum<LPA>(fy); fz = sub_sum<LPA>(fz);
                     if (live) F = F + make_float3(fx, fy, fz);
-                } else if (live) {
-                    F = F + make_float3(fx, fy, fz);
                 }
             }
             if (live) e_atom = e_grid + e_intra;
@@ -906,11 +917,10 @@ k_replicas(KArgs A) {
 
             if (MODE == MODE_EVAL) break;
 
+            // (step-derived, not loop-carried: a loop-carried counter here makes the register
+            // allocator shuffle the cached stencils between registers every step)
             bool between_checks = false;
-            if constexpr (MODE == MODE_FIRE_CHECKED) {
-                between_checks = chk != 0 && it < total;
-                if (++chk == A.check_every) chk = 0;
-            }
+            if constexpr (MODE == MODE_FIRE_CHECKED) between_checks = it % A.check_every != 0 && it < total;
             if (between_checks) {
                 // a move between checks: no sums over the replica, a plain kick and capped
                 // move with the current dt (block-uniform condition: no barrier is skipped
