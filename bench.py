@@ -8,13 +8,16 @@ accounting every step.  One benchmark step = one gff_relax_batch launch that adv
 every replica by 5000 MD steps (grid interpolation + intramolecular field + integrator,
 all inside the kernel).  value = replica-steps/s over the K timed launches.
 
-Prints one JSON line.  Roofline: the dominant kernel is the replica kernel; its algorithmic
-traffic is 64 stencil nodes x 3 channels x (4 B FP32 | 2 B FP16) per atom per force
-evaluation, divided by the kernel's mean launch time from HIP events on its stream.
-`traffic` (fabric bytes per launch) and `valu` (VALU wave instructions per launch, and
-their share of the issue slots in the measured time) come from rocprofv3 counters stored
-below with the digests of the kernel sources they were taken on; both are null once those
-sources change.
+Prints one JSON line.  Roofline: the dominant kernel is the replica kernel.  Its binding
+resource is VALU issue, so the record is an ALU roofline: the method's algorithmic work, about
+68 kflop per replica-step of the 38-atom molecule (38 interpolations of about 0.75 kflop plus
+about 40 kflop of intramolecular field), divided by the kernel's mean launch time from HIP
+events on its stream, against the FP32 vector peak.  The memory roofline of the same launch
+(64 stencil nodes x 3 channels x 4 B per atom per force evaluation, against the 8 TB/s HBM
+peak) is reported beside it under `memory`.  `traffic` (fabric bytes per launch) and `valu`
+(VALU wave instructions per launch, and their share of the issue slots in the measured time)
+come from rocprofv3 counters stored below with the digests of the kernel sources they were
+taken on; both are null once those sources change.
 """
 from __future__ import annotations
 
@@ -30,6 +33,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# FP32 vector peak from the unit counts: 256 CUs x 4 SIMDs x 16 lanes x 2 flop per FMA x 2.4 GHz
+# = 78.6 TFLOP/s in scalar FP32 instructions, twice that with packed FP32 (two FMAs per lane);
+# the kernels here are built without packed FP32 instructions
+FP32_PEAK_TFLOPS = 157.3
+FP32_UNPACKED_PEAK_TFLOPS = 78.6
+# algorithmic work per replica-step of the 38-atom molecule: 38 atom-interpolations of about
+# 0.75 kflop (channel pre-mix and tensor-product contraction) and about 40 kflop of the
+# intramolecular field (each non-bonded pair, bond, angle and torsion once)
+FLOP_PER_REPLICA_STEP = 68e3
 
 # Fabric-side traffic of the replica kernel (L2 misses to MALL/HBM) from two rocprofv3 --pmc
 # passes, FETCH_SIZE then WRITE_SIZE, in KiB for one launch of the workload named by the key
@@ -40,13 +52,13 @@ COUNTER_SCALE = {"fetch": 2.0, "write": 1.0}
 MEASURED_TRAFFIC = {
     ("f32", 16384, 5000, 192): {
         "sources": {"paper_2508_15522_amd/csrc/gff_relax.hip":
-                    "421638986581c61a4522949cf5f9e2245df2c91650c26a5a03a4282045bff62b",
+                    "0cb74bbff61139f57fec96bd3bfb20ede2c9ff705cdd56c51188a357e04de99f",
                     "paper_2508_15522_amd/csrc/gff_internal.hpp":
                     "678e935cc46abbe009d1a756ca08f31bb22802c80aff928cdac16a63e6c8f54e",
                     "paper_2508_15522_amd/csrc/gff_host.hip":
                     "2aa04dd935f3d23fd37d27ccea38d3373c1936d34b561ec069f5a5d707862209"},
-        "fetch_kib": 292717012.375, "write_kib": 100353.9375,
-        "valu_insts": 192352849774.0,          # SQ_INSTS_VALU (wave instructions) of the launch
+        "fetch_kib": 292915146.0, "write_kib": 100353.4375,
+        "valu_insts": 190484586196.0,          # SQ_INSTS_VALU (wave instructions) of the launch
     },
 }
 # FP32 VALU issue slots per second: 256 CUs x 4 SIMDs x 2.4 GHz / 4 cycles per wave64 instruction
@@ -211,6 +223,9 @@ def main():
     evals = args.md_steps + 1
     alg_bytes = n_rep * mol.n * evals * 64 * 3 * bpn
     achieved = alg_bytes / kern_avg / 1e9
+    # algorithmic flops: the per-replica-step work of the 38-atom molecule over every replica-step
+    alg_flops = FLOP_PER_REPLICA_STEP * rs
+    tflops = alg_flops / kern_avg / 1e12
     res = {
         "metric": "replica-steps/s",
         "value": value,
@@ -238,22 +253,24 @@ def main():
         "grid_build_fit_s": build_s,
         "nve_max_abs_drift_eV": float(np.nanmax(drift[:, 2])),
         "nonfinite_replicas": int(((status & G.REP_NONFINITE) != 0).sum()),
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
+        # the kernel is bound by VALU issue (valu.issue_frac): the register stencil cache removes
+        # three quarters of the gather traffic, so HBM is not what limits it.  On the method's
+        # own roofline (about 2.3 flop per gathered byte, below the FP32 ridge) the memory roof
+        # would bind; that fraction is `memory.frac`.
+        "roofline": {"bound": "alu", "achieved": tflops, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": tflops / FP32_PEAK_TFLOPS,
                      "traffic": measured_traffic(args.storage, n_rep, args.md_steps, block),
-                     "effective_GBps": achieved,
-                     "valu": valu_utilisation(args.storage, n_rep, args.md_steps, block, kern_avg),
                      "kernel": f"k_replicas<{args.storage},NVE>",
-                     "bytes_per_launch": alg_bytes,
-                     # the algorithmic intensity (about 2.3 flop per gathered byte) is below the
-                     # FP32 ridge, so the memory roofline bounds the method; the resource the
-                     # kernel actually saturates is VALU issue (valu.issue_frac), because the
-                     # register stencil cache removes most of the gather traffic
-                     "binding_resource": "valu_issue"},
+                     "flop_per_replica_step": FLOP_PER_REPLICA_STEP, "flop_per_launch": alg_flops,
+                     "peak_unpacked": FP32_UNPACKED_PEAK_TFLOPS,
+                     "frac_unpacked": tflops / FP32_UNPACKED_PEAK_TFLOPS,
+                     "valu": valu_utilisation(args.storage, n_rep, args.md_steps, block, kern_avg),
+                     "memory": {"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                "frac": achieved / HBM_PEAK_GBS, "bytes_per_launch": alg_bytes}},
     }
     tr = res["roofline"]["traffic"]
-    res["roofline"]["fabric_GBps"] = tr / kern_avg / 1e9 if tr else None
-    res["roofline"]["fabric_frac"] = tr / kern_avg / 1e9 / HBM_PEAK_GBS if tr else None
+    res["roofline"]["memory"]["fabric_GBps"] = tr / kern_avg / 1e9 if tr else None
+    res["roofline"]["memory"]["fabric_frac"] = tr / kern_avg / 1e9 / HBM_PEAK_GBS if tr else None
     # interpolation alone: one evaluation launch (grid part only, no stencil reuse) over the
     # same atoms, repeated
     F = torch.empty_like(st0["pos"])
@@ -270,7 +287,7 @@ def main():
     res["eval_launch_s"] = ev_s
     log(f"eval_forces (grid only): {res['eval_interpolations_per_s']:.3e} interpolations/s, {ev_s * 1e3:.3f} ms per launch")
     res["gather_probe"] = gather_probe(grid, log)
-    res["roofline"]["serving_probe_GBps"] = res["gather_probe"]["grid_coefficients"]
+    res["roofline"]["memory"]["serving_probe_GBps"] = res["gather_probe"]["grid_coefficients"]
     # the evaluation launch in the probe's own unit: every atom reads 16 z-column segments of
     # four padded 16-byte nodes (64 B each, the probe's chunk), of which 48 B are coefficients
     chunk_bytes = n_rep * mol.n * 16 * (64 if args.storage == "f32" else 32)

@@ -183,7 +183,8 @@ void gff_topology_destroy(gff_topology *topo);
  * or 4; 0 means 1), floor(block / (lanes_per_atom n)) replicas per block (at most
  * reps_per_block if > 0).  grid_blocks <= 0: one block per pack.  Several lanes per atom
  * split an atom's non-bonded partners, bonded terms and the replica's torsion terms (and,
- * at four, give every atom its own gather quad): for batches too small to fill the GPU.
+ * at four, give every atom its own gather quad): for batches too small to fill the GPU and
+ * for batches of large molecules, whose pair work per lane grows with the molecule.
  * They apply to FIRE, NVE and Langevin launches on FP32 and FP16 B-spline grids; other
  * launches on such a plan use one lane per atom on the same packing.  Results depend on
  * lanes_per_atom only through the FP32 summation order of the split sums. */
@@ -376,11 +377,11 @@ void gff_graph_destroy(gff_graph *graph);
  * `params` for every block size 64..1024 (multiple of 64, >= the largest molecule) with the
  * densest packing and, when that gives fewer than two packs per compute unit, with at most
  * 1, 2, 4 or 8 replicas per block; each with the default grid and with persistent grids of
- * 1-4 blocks per compute unit; on FP32/FP16 B-spline grids, for batches of fewer atoms than
- * 256 per compute unit, all of this again with 2 and 4 lanes per atom (Section
+ * 1-4 blocks per compute unit; on FP32/FP16 B-spline grids all of this again with 2 lanes
+ * per atom and, for batches of fewer atoms than 256 per compute unit, with 4 (Section
  * "Configuration sampling on GPU": the GPU has far more cores than a small molecule has
- * atoms); on copies of `state`; returns the fastest shape and its replica-steps/s
- * (nullable). */
+ * atoms, and a large molecule's pair work splits across lanes); on copies of `state`;
+ * returns the fastest shape and its replica-steps/s (nullable). */
 gff_status gff_autotune(const gff_grid *grid, const gff_topology *topo, int n_rep, const int *rep_type_h,
                         const gff_relax_params *params, const gff_state *state, gff_launch *best,
                         float *best_rate, void *stream);

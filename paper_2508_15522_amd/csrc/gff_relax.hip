@@ -474,12 +474,14 @@ __device__ __forceinline__ void pair_range(const KArgs &A, const float4 *sp, con
             const float ddx = xi.x - pj.x, ddy = xi.y - pj.y, ddz = xi.z - pj.z;
             const float r2 = ddx * ddx + ddy * ddy + ddz * ddz;
             const bool skip = (m >> (j - jb)) & 1u;
-            const float rinv = __builtin_amdgcn_rsqf(skip ? 1.f : r2);
+            // an excluded pair (the atom itself included, r2 = 0) gets 1/r = 0: then r = 0,
+            // e^{-alpha r} = 1 and the force factor g / r is 0 with no further select
+            const float rinv = skip ? 0.f : __builtin_amdgcn_rsqf(r2);
             const float r = r2 * rinv;
             const float u = __builtin_amdgcn_exp2f(-A.alpha_l2e * r);
             const float eu = me.x * qj.x * u * u, el = 0.5f * me.y * qj.y * u, ec = keQ * qj.z * rinv;
             const float g = A.alpha * (2.f * eu - el) + ec * rinv;      // -dE/dr
-            const float sc = skip ? 0.f : g * rinv;
+            const float sc = g * rinv;
             fx += sc * ddx; fy += sc * ddy; fz += sc * ddz;
             if constexpr (WITH_E) e += skip ? 0.f : (eu - el + ec);
         }

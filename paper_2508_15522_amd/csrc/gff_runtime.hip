@@ -57,9 +57,9 @@ extern "C" void gff_graph_destroy(gff_graph *g) {
 }
 
 // Measured choice of the launch shape for a batch: every candidate block size (and, per
-// block size, the packings below, persistent grids of 1-4 blocks per CU and, for small
-// batches on B-spline grids, 2 or 4 lanes per atom) runs `params` on
-// a copy of the caller's state; the fastest (replica-steps per second) wins.
+// block size, the packings below, persistent grids of 1-4 blocks per CU and, on B-spline
+// grids, 2 lanes per atom, and 4 for small batches) runs `params` on a copy of the caller's
+// state; the fastest (replica-steps per second) wins.
 // Candidates that the device cannot launch are skipped.  The caller's state is untouched.
 extern "C" gff_status gff_autotune(const gff_grid *grid, const gff_topology *topo, int n_rep, const int *rep_type_h,
                                    const gff_relax_params *params, const gff_state *state, gff_launch *best,
@@ -102,13 +102,15 @@ extern "C" gff_status gff_autotune(const gff_grid *grid, const gff_topology *top
     gff_status rc = GFF_OK;
     // replicas per block: the densest packing, and when that leaves fewer than two packs per
     // compute unit, sparser packings (at most 1, 2, 4, 8 replicas per block) that spread a
-    // small batch over more of the GPU; lanes per atom 2 and 4 (B-spline grids) when the batch
-    // has fewer atoms than one wave per SIMD of the GPU
+    // small batch over more of the GPU.  Lanes per atom on B-spline grids: 2 for every batch
+    // (two lanes share a large molecule's non-bonded partners: faster on the uneven-size batch
+    // even when it fills the GPU), 4 when the batch has fewer atoms than one wave per SIMD
     const int rpb_cand[5] = {0, 1, 2, 4, 8};
     const bool bspline = grid->storage == GFF_STORE_F32 || grid->storage == GFF_STORE_F16;
     const bool small = (long)n_atoms < 4L * 64 * n_cu;
     for (int lpa = 1; lpa <= 4 && rc == GFF_OK; lpa *= 2) {
-    if (lpa > 1 && !(bspline && small)) break;
+    if (lpa > 1 && !bspline) break;
+    if (lpa == 4 && !small) break;
     for (int bt = 64; bt <= 1024 && rc == GFF_OK; bt += 64) {
         if (bt < max_n * lpa) continue;
         int dense_packs = -1, last_packs = -1;

@@ -55,3 +55,14 @@ def test_learned_gain_with_training_counts_the_training_time_against_the_learned
     cmp = {"learned": {"distinct_minima": 86, "seconds": 2.88}, "uniform": {"minima_per_s": 58 / 2.82},
            "training": {"train_s": 0.61}}
     assert bench._gain_with_training(cmp) == pytest.approx((86 / (2.88 + 0.61)) / (58 / 2.82), rel=1e-15)
+
+
+def test_alu_peaks_follow_from_the_unit_counts():
+    """FP32 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 flop per FMA x 2.4 GHz in scalar
+    instructions, twice that with packed FP32."""
+    unpacked = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+    assert bench.FP32_UNPACKED_PEAK_TFLOPS == pytest.approx(unpacked, rel=1e-3)
+    assert bench.FP32_PEAK_TFLOPS == pytest.approx(2 * unpacked, rel=1e-3)
+    # the issue-slot peak the VALU utilisation is taken against: one wave64 FP32 instruction
+    # per SIMD every 4 cycles
+    assert bench.VALU_ISSUE_PEAK * 64 * 2 / 1e12 == pytest.approx(unpacked, rel=1e-12)

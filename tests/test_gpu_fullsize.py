@@ -131,9 +131,13 @@ def test_c5_fire_large_grid_full_size_sampled():
     _fire_check(grid, Bref, [mol], rep_type, pos, plan, topo, 10, _sample(n_rep))
 
 
-def test_c3_sizes_autotuned_full_size_sampled():
+@pytest.mark.parametrize("forced", [None, (256, 0, 0, 2)])
+def test_c3_sizes_autotuned_full_size_sampled(forced):
+    """The uneven-size workload in its autotuned launch shape and, explicitly, in the shape the
+    autotuner picks for it on this GPU (256-thread blocks, two lanes per atom); sampled
+    replicas of every size against the oracle."""
     D.require_gpu()
-    announce("full size: 4096 replicas of 8 sizes FIRE, autotuned launch")
+    announce(f"full size: 4096 replicas of 8 sizes FIRE, {'autotuned launch' if forced is None else forced}")
     cfg = configs.GRID_SMALL
     grid, Bref = _grid(cfg, 23)
     mols = S.molecule_types("sizes")
@@ -144,9 +148,12 @@ def test_c3_sizes_autotuned_full_size_sampled():
                 for t, m in enumerate(mols)]
     pos = [next(per_type[t]) for t in rep_type]
     topo = G.Topology(mols)
-    st0 = D.fire_state(G.Plan(topo, rep_type), pos)
-    launch, _ = AT.launch_for(grid, topo, rep_type, G.relax_params(G.MODE_FIRE, 20, True, f_conv=1e-4), st0,
-                              use_cache=False)
+    if forced is None:
+        st0 = D.fire_state(G.Plan(topo, rep_type), pos)
+        launch, _ = AT.launch_for(grid, topo, rep_type, G.relax_params(G.MODE_FIRE, 20, True, f_conv=1e-4), st0,
+                                  use_cache=False)
+    else:
+        launch = forced
     announce(f"  launch {launch}")
     plan = G.Plan(topo, rep_type, *launch)
     idx = _sample(n_rep, extra=range(8, 16))                   # every molecule size
