@@ -115,6 +115,8 @@ def main():
     ap.add_argument("--no-f16", action="store_true", help="skip the FP16-grid arm")
     ap.add_argument("--no-minima", action="store_true", help="skip the learned-vs-uniform minima/s comparison")
     ap.add_argument("--no-c5", action="store_true", help="skip the large-substrate (c5) record")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the chain (c1) and uneven-size (c3) records (autotuned launches)")
     ap.add_argument("--compare-langevin", action="store_true",
                     help="also time the same replicas under Langevin dynamics (BAOAB, 300 K, gamma 0.01/fs)")
     ap.add_argument("--compare-trilinear", action="store_true",
@@ -146,6 +148,8 @@ def main():
     args.minima = not args.no_minima
     if not args.no_c5 and "c5" not in args.extra:
         args.extra = list(args.extra) + ["c5"]
+    if not args.no_small:
+        args.extra = list(args.extra) + [w for w in ("c1", "c3") if w not in args.extra]
     if args.gpus != 1:
         print(f"bench.py: runs on one GPU only (asked for --gpus {args.gpus}); "
               "replicas are independent, so more GPUs would each run their own share", file=sys.stderr)
