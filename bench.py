@@ -52,12 +52,12 @@ COUNTER_SCALE = {"fetch": 2.0, "write": 1.0}
 MEASURED_TRAFFIC = {
     ("f32", 16384, 5000, 192): {
         "sources": {"paper_2508_15522_amd/csrc/gff_relax.hip":
-                    "0cb74bbff61139f57fec96bd3bfb20ede2c9ff705cdd56c51188a357e04de99f",
+                    "648a9fd0ef30ca566446b298525987fe752b4fa18154a8888378b5349eaaeaaf",
                     "paper_2508_15522_amd/csrc/gff_internal.hpp":
                     "678e935cc46abbe009d1a756ca08f31bb22802c80aff928cdac16a63e6c8f54e",
                     "paper_2508_15522_amd/csrc/gff_host.hip":
                     "2aa04dd935f3d23fd37d27ccea38d3373c1936d34b561ec069f5a5d707862209"},
-        "fetch_kib": 292915146.0, "write_kib": 100353.4375,
+        "fetch_kib": 292520047.9375, "write_kib": 100363.1875,
         "valu_insts": 190484586196.0,          # SQ_INSTS_VALU (wave instructions) of the launch
     },
 }

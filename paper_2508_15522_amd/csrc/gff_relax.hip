@@ -75,6 +75,7 @@ struct KArgs {
     float dt0;
     double *E_pts; int *steps_pts; unsigned *st_pts; float *pos_pts;
     DirectView d;                       // all-atom comparison mode only
+    float half_inv_alpha;               // 1 / (2 alpha): pair energies summed times alpha (FIRE)
 };
 
 __device__ __forceinline__ void lds_sync() {
@@ -455,13 +456,17 @@ __device__ __forceinline__ int stencil_id(const GridView &g, int4 ki) {
 // Non-bonded pairs (i, j) of this lane's atom i with j in [j0, j1) that are more than two
 // bonds apart: Morse with depth eps_i eps_j at R_i + R_j factorised as
 // P_i P_j e^{-2 alpha r} - L_i L_j e^{-alpha r}/2, plus k_e Q_i Q_j / r.  Adds the force on i
-// to (fx, fy, fz) and the full pair energies to e (the caller halves the sum).  Ranges are
+// to (fx, fy, fz) and the full pair energies to e (the caller halves the sum).  FOLD (the
+// FIRE kernels): the Morse factor alpha of -dE/dr is folded into the atom's factors, one
+// multiply per pair fewer, and e receives alpha times the pair energies (the caller scales
+// the sum by 1 / (2 alpha)); every FIRE kernel forms the same forces.  Ranges are
 // block-uniform; consecutive ranges accumulate in the order of one pass over [0, n).
-template <int LPA, bool WITH_E>
+template <int LPA, bool WITH_E, bool FOLD>
 __device__ __forceinline__ void pair_range(const KArgs &A, const float4 *sp, const float4 *splq, int rbase, int j0,
                                            int j1, float3 xi, float4 me, uint4 ex, int sub, float &fx, float &fy,
                                            float &fz, float &e) {
     const float keQ = A.ke * me.z;
+    const float Pi = FOLD ? A.alpha * me.x : me.x, Li = FOLD ? (0.5f * A.alpha) * me.y : 0.5f * me.y;
     for (int jb = j0 & ~31; jb < j1; jb += 32) {
         const int w = jb >> 5;
         const unsigned m = w == 0 ? ex.x : (w == 1 ? ex.y : (w == 2 ? ex.z : ex.w));
@@ -479,11 +484,16 @@ __device__ __forceinline__ void pair_range(const KArgs &A, const float4 *sp, con
             const float rinv = skip ? 0.f : __builtin_amdgcn_rsqf(r2);
             const float r = r2 * rinv;
             const float u = __builtin_amdgcn_exp2f(-A.alpha_l2e * r);
-            const float eu = me.x * qj.x * u * u, el = 0.5f * me.y * qj.y * u, ec = keQ * qj.z * rinv;
-            const float g = A.alpha * (2.f * eu - el) + ec * rinv;      // -dE/dr
+            const float eu = Pi * qj.x * u * u, el = Li * qj.y * u, ec = keQ * qj.z * rinv;
+            float g;                                                    // -dE/dr
+            if constexpr (FOLD) g = (2.f * eu - el) + ec * rinv;
+            else g = A.alpha * (2.f * eu - el) + ec * rinv;
             const float sc = g * rinv;
             fx += sc * ddx; fy += sc * ddy; fz += sc * ddz;
-            if constexpr (WITH_E) e += skip ? 0.f : (eu - el + ec);
+            if constexpr (WITH_E) {
+                if constexpr (FOLD) e += skip ? 0.f : (eu - el) + A.alpha * ec;
+                else e += skip ? 0.f : (eu - el + ec);
+            }
         }
     }
 }
@@ -780,14 +790,14 @@ k_replicas(KArgs A) {
                         const bool need = id != cid[rnd] && id >= 0;
                         RawNode<STORE> c[8];
                         if (need) quad_issue<STORE>(gv, quad_addr<STORE>(gv, ki, quad_s), 0, c);
-                        if (pairs) pair_range<LPA, WANT_E>(A, sp, s_plq, rbase, (2 * rnd) * n / (2 * R),
+                        if (pairs) pair_range<LPA, WANT_E, FIRE>(A, sp, s_plq, rbase, (2 * rnd) * n / (2 * R),
                                                    (2 * rnd + 1) * n / (2 * R), x, me, ex, sub, pfx, pfy, pfz, pe);
                         if (need) {
                             const float4 po = s_plq[o];
                             quad_mix<STORE>(c, po.x * gv.s0, po.y * gv.s1, po.z * gv.s2, 0, cm[rnd]);
                             quad_issue<STORE>(gv, quad_addr<STORE>(gv, ki, quad_s), 2, c);
                         }
-                        if (pairs) pair_range<LPA, WANT_E>(A, sp, s_plq, rbase, (2 * rnd + 1) * n / (2 * R),
+                        if (pairs) pair_range<LPA, WANT_E, FIRE>(A, sp, s_plq, rbase, (2 * rnd + 1) * n / (2 * R),
                                                    (2 * rnd + 2) * n / (2 * R), x, me, ex, sub, pfx, pfy, pfz, pe);
                         if (need) {
                             const float4 po = s_plq[o];
@@ -823,19 +833,34 @@ k_replicas(KArgs A) {
             float e_intra = 0.f;
             // this lane's torsion terms (results to LDS), non-bonded pairs, bonds and angles
             auto intra_terms = [&](float &fx, float &fy, float &fz) {
-                for (int q = at * LPA + sub; q < nt; q += n * LPA) {
-                    float4 oA, oB;
-                    e_intra += torsion_term(reinterpret_cast<const TorDef *>(s_topo + ti.o_tor)[q], sp, rbase, oA, oB);
-                    s_tres[2 * (lr * nt + q)] = oA;
-                    s_tres[2 * (lr * nt + q) + 1] = oB;
+                if constexpr (FIRE) {
+                    // a block-uniform loop (its counter stays scalar): fewer registers in the
+                    // FIRE kernels, whose register allocation it suits
+                    for (int qb = 0; qb < nt; qb += n * LPA) {
+                        const int q = qb + at * LPA + sub;
+                        if (q < nt) {
+                            float4 oA, oB;
+                            e_intra += torsion_term(reinterpret_cast<const TorDef *>(s_topo + ti.o_tor)[q], sp, rbase,
+                                                    oA, oB);
+                            s_tres[2 * (lr * nt + q)] = oA;
+                            s_tres[2 * (lr * nt + q) + 1] = oB;
+                        }
+                    }
+                } else {
+                    for (int q = at * LPA + sub; q < nt; q += n * LPA) {
+                        float4 oA, oB;
+                        e_intra += torsion_term(reinterpret_cast<const TorDef *>(s_topo + ti.o_tor)[q], sp, rbase, oA, oB);
+                        s_tres[2 * (lr * nt + q)] = oA;
+                        s_tres[2 * (lr * nt + q) + 1] = oB;
+                    }
                 }
                 if constexpr (CACHE && STORE != STORE_TRI) {
                     fx = pfx; fy = pfy; fz = pfz;
-                    e_intra += 0.5f * pe;
+                    e_intra += (FIRE ? A.half_inv_alpha : 0.5f) * pe;
                 } else {
                     float e = 0.f;
-                    pair_range<LPA, WANT_E>(A, sp, s_plq, rbase, 0, n, x, me, ex, sub, fx, fy, fz, e);
-                    e_intra += 0.5f * e;
+                    pair_range<LPA, WANT_E, FIRE>(A, sp, s_plq, rbase, 0, n, x, me, ex, sub, fx, fy, fz, e);
+                    e_intra += (FIRE ? A.half_inv_alpha : 0.5f) * e;
                 }
                 e_intra += bond_angle_terms<LPA, WANT_E>(A, sp, rbase, abase, at, sub, x, fx, fy, fz);
             };
@@ -1163,6 +1188,7 @@ static void fill_common(KArgs &A, const gff_topology *topo, const gff_plan *plan
     A.t = topo->dev;
     A.alpha = topo->alpha;
     A.alpha_l2e = topo->alpha * 1.4426950408889634f;
+    A.half_inv_alpha = 0.5f / topo->alpha;
     A.ke = topo->ke;
     A.packs = plan->d_packs; A.pack_reps = plan->d_pack_reps; A.atom_off = plan->d_atom_off;
     A.n_packs = plan->n_packs; A.N = plan->n_atoms; A.tres_max = plan->tres_max;
