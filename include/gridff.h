@@ -300,7 +300,9 @@ typedef struct {
  *
  * Outputs: d_E_rep [n_rep] (FP64 total energy at the last evaluation), d_fnorm_rep
  * [n_rep] (|F|_2 there, FP32), d_steps_rep [n_rep] (moves made), d_drift_rep nullable.
- * One kernel launch runs the whole step loop. */
+ * One kernel launch runs the whole step loop.  The FIRE loop forms forces only; when
+ * d_E_rep is given, a second launch evaluates the energies at the final positions (those of
+ * the last evaluation: a converged replica stops moving). */
 gff_status gff_relax_batch(const gff_grid *grid, const gff_topology *topo, const gff_plan *plan,
                            const gff_relax_params *params, const gff_state *state,
                            double *d_E_rep, float *d_fnorm_rep, int *d_steps_rep,
