@@ -788,20 +788,38 @@ k_replicas(KArgs A) {
                         const int4 ki = s_gi[o];
                         const int id = stencil_id(gv, ki);
                         const bool need = id != cid[rnd] && id >= 0;
-                        RawNode<STORE> c[8];
-                        if (need) quad_issue<STORE>(gv, quad_addr<STORE>(gv, ki, quad_s), 0, c);
-                        if (pairs) pair_range<LPA, WANT_E, FIRE>(A, sp, s_plq, rbase, (2 * rnd) * n / (2 * R),
-                                                   (2 * rnd + 1) * n / (2 * R), x, me, ex, sub, pfx, pfy, pfz, pe);
-                        if (need) {
-                            const float4 po = s_plq[o];
-                            quad_mix<STORE>(c, po.x * gv.s0, po.y * gv.s1, po.z * gv.s2, 0, cm[rnd]);
-                            quad_issue<STORE>(gv, quad_addr<STORE>(gv, ki, quad_s), 2, c);
-                        }
-                        if (pairs) pair_range<LPA, WANT_E, FIRE>(A, sp, s_plq, rbase, (2 * rnd + 1) * n / (2 * R),
-                                                   (2 * rnd + 2) * n / (2 * R), x, me, ex, sub, pfx, pfy, pfz, pe);
-                        if (need) {
-                            const float4 po = s_plq[o];
-                            quad_mix<STORE>(c, po.x * gv.s0, po.y * gv.s1, po.z * gv.s2, 2, cm[rnd]);
+                        if constexpr (LPA == 4) {
+                            // one cached plane leaves registers to issue the whole reload at
+                            // once: one memory latency per step, covered by the pair loop
+                            RawNode<STORE> c[8], c2[8];
+                            if (need) {
+                                const QuadAddr qa = quad_addr<STORE>(gv, ki, quad_s);
+                                quad_issue<STORE>(gv, qa, 0, c);
+                                quad_issue<STORE>(gv, qa, 2, c2);
+                            }
+                            if (pairs) pair_range<LPA, WANT_E, FIRE>(A, sp, s_plq, rbase, (2 * rnd) * n / (2 * R),
+                                                       (2 * rnd + 2) * n / (2 * R), x, me, ex, sub, pfx, pfy, pfz, pe);
+                            if (need) {
+                                const float4 po = s_plq[o];
+                                quad_mix<STORE>(c, po.x * gv.s0, po.y * gv.s1, po.z * gv.s2, 0, cm[rnd]);
+                                quad_mix<STORE>(c2, po.x * gv.s0, po.y * gv.s1, po.z * gv.s2, 2, cm[rnd]);
+                            }
+                        } else {
+                            RawNode<STORE> c[8];
+                            if (need) quad_issue<STORE>(gv, quad_addr<STORE>(gv, ki, quad_s), 0, c);
+                            if (pairs) pair_range<LPA, WANT_E, FIRE>(A, sp, s_plq, rbase, (2 * rnd) * n / (2 * R),
+                                                       (2 * rnd + 1) * n / (2 * R), x, me, ex, sub, pfx, pfy, pfz, pe);
+                            if (need) {
+                                const float4 po = s_plq[o];
+                                quad_mix<STORE>(c, po.x * gv.s0, po.y * gv.s1, po.z * gv.s2, 0, cm[rnd]);
+                                quad_issue<STORE>(gv, quad_addr<STORE>(gv, ki, quad_s), 2, c);
+                            }
+                            if (pairs) pair_range<LPA, WANT_E, FIRE>(A, sp, s_plq, rbase, (2 * rnd + 1) * n / (2 * R),
+                                                       (2 * rnd + 2) * n / (2 * R), x, me, ex, sub, pfx, pfy, pfz, pe);
+                            if (need) {
+                                const float4 po = s_plq[o];
+                                quad_mix<STORE>(c, po.x * gv.s0, po.y * gv.s1, po.z * gv.s2, 2, cm[rnd]);
+                            }
                         }
                         cid[rnd] = id;
                         const float4 r = quad_contract(cm[rnd], s_gt[o], quad_s, id >= 0);
