@@ -473,26 +473,57 @@ __device__ __forceinline__ void pair_range(const KArgs &A, const float4 *sp, con
         const int js0 = max(j0, jb), je = min(j1, jb + 32);
         // with several lanes per atom, sub-lane u takes the partners j = u (mod LPA)
         const int js = LPA == 1 ? js0 : js0 + ((sub - js0) & (LPA - 1));
-        for (int j = js; j < je; j += LPA) {
-            const float4 pj = sp[rbase + j];
-            const float4 qj = splq[rbase + j];
-            const float ddx = xi.x - pj.x, ddy = xi.y - pj.y, ddz = xi.z - pj.z;
-            const float r2 = ddx * ddx + ddy * ddy + ddz * ddz;
-            const bool skip = (m >> (j - jb)) & 1u;
-            // an excluded pair (the atom itself included, r2 = 0) gets 1/r = 0: then r = 0,
-            // e^{-alpha r} = 1 and the force factor g / r is 0 with no further select
-            const float rinv = skip ? 0.f : __builtin_amdgcn_rsqf(r2);
-            const float r = r2 * rinv;
-            const float u = __builtin_amdgcn_exp2f(-A.alpha_l2e * r);
-            const float eu = Pi * qj.x * u * u, el = Li * qj.y * u, ec = keQ * qj.z * rinv;
-            float g;                                                    // -dE/dr
-            if constexpr (FOLD) g = (2.f * eu - el) + ec * rinv;
-            else g = A.alpha * (2.f * eu - el) + ec * rinv;
-            const float sc = g * rinv;
-            fx += sc * ddx; fy += sc * ddy; fz += sc * ddz;
-            if constexpr (WITH_E) {
-                if constexpr (FOLD) e += skip ? 0.f : (eu - el) + A.alpha * ec;
-                else e += skip ? 0.f : (eu - el + ec);
+        if constexpr (LPA == 4) {
+            // two partners per pass, both read before either is computed: a small batch leaves
+            // a wave alone on its SIMD, which would otherwise wait out every LDS read
+            auto pair = [&](int j, const float4 pj, const float4 qj) {
+                const float ddx = xi.x - pj.x, ddy = xi.y - pj.y, ddz = xi.z - pj.z;
+                const float r2 = ddx * ddx + ddy * ddy + ddz * ddz;
+                const bool skip = (m >> (j - jb)) & 1u;
+                const float rinv = skip ? 0.f : __builtin_amdgcn_rsqf(r2);   // as below
+                const float r = r2 * rinv;
+                const float u = __builtin_amdgcn_exp2f(-A.alpha_l2e * r);
+                const float eu = Pi * qj.x * u * u, el = Li * qj.y * u, ec = keQ * qj.z * rinv;
+                float g;
+                if constexpr (FOLD) g = (2.f * eu - el) + ec * rinv;
+                else g = A.alpha * (2.f * eu - el) + ec * rinv;
+                const float sc = g * rinv;
+                fx += sc * ddx; fy += sc * ddy; fz += sc * ddz;
+                if constexpr (WITH_E) {
+                    if constexpr (FOLD) e += skip ? 0.f : (eu - el) + A.alpha * ec;
+                    else e += skip ? 0.f : (eu - el + ec);
+                }
+            };
+            int j = js;
+            for (; j + LPA < je; j += 2 * LPA) {
+                const float4 pa = sp[rbase + j], qa = splq[rbase + j];
+                const float4 pb = sp[rbase + j + LPA], qb = splq[rbase + j + LPA];
+                pair(j, pa, qa);
+                pair(j + LPA, pb, qb);
+            }
+            if (j < je) pair(j, sp[rbase + j], splq[rbase + j]);
+        } else {
+            for (int j = js; j < je; j += LPA) {
+                const float4 pj = sp[rbase + j];
+                const float4 qj = splq[rbase + j];
+                const float ddx = xi.x - pj.x, ddy = xi.y - pj.y, ddz = xi.z - pj.z;
+                const float r2 = ddx * ddx + ddy * ddy + ddz * ddz;
+                const bool skip = (m >> (j - jb)) & 1u;
+                // an excluded pair (the atom itself included, r2 = 0) gets 1/r = 0: then r = 0,
+                // e^{-alpha r} = 1 and the force factor g / r is 0 with no further select
+                const float rinv = skip ? 0.f : __builtin_amdgcn_rsqf(r2);
+                const float r = r2 * rinv;
+                const float u = __builtin_amdgcn_exp2f(-A.alpha_l2e * r);
+                const float eu = Pi * qj.x * u * u, el = Li * qj.y * u, ec = keQ * qj.z * rinv;
+                float g;                                                    // -dE/dr
+                if constexpr (FOLD) g = (2.f * eu - el) + ec * rinv;
+                else g = A.alpha * (2.f * eu - el) + ec * rinv;
+                const float sc = g * rinv;
+                fx += sc * ddx; fy += sc * ddy; fz += sc * ddz;
+                if constexpr (WITH_E) {
+                    if constexpr (FOLD) e += skip ? 0.f : (eu - el) + A.alpha * ec;
+                    else e += skip ? 0.f : (eu - el + ec);
+                }
             }
         }
     }
