@@ -52,7 +52,7 @@ COUNTER_SCALE = {"fetch": 2.0, "write": 1.0}
 MEASURED_TRAFFIC = {
     ("f32", 16384, 5000, 192): {
         "sources": {"paper_2508_15522_amd/csrc/gff_relax.hip":
-                    "d37bcff69816b147a8e2b6af7bb0b7c7e74dbca29a7b1c8712db9ee255e580fe",
+                    "4965f4e9f6752dc59c092d16e5b5892f2ca1f65e2fafb0cc86af1599f60d2e1c",
                     "paper_2508_15522_amd/csrc/gff_internal.hpp":
                     "678e935cc46abbe009d1a756ca08f31bb22802c80aff928cdac16a63e6c8f54e",
                     "paper_2508_15522_amd/csrc/gff_host.hip":

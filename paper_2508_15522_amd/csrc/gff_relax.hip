@@ -475,7 +475,9 @@ __device__ __forceinline__ void pair_range(const KArgs &A, const float4 *sp, con
         const int js = LPA == 1 ? js0 : js0 + ((sub - js0) & (LPA - 1));
         if constexpr (LPA == 4) {
             // two partners per pass, both read before either is computed: a small batch leaves
-            // a wave alone on its SIMD, which would otherwise wait out every LDS read
+            // a wave alone on its SIMD, which would otherwise wait out every LDS read.  (The
+            // other lane layouts keep the loop below as written: routed through this helper
+            // they compile to more register copies.)
             auto pair = [&](int j, const float4 pj, const float4 qj) {
                 const float ddx = xi.x - pj.x, ddy = xi.y - pj.y, ddz = xi.z - pj.z;
                 const float r2 = ddx * ddx + ddy * ddy + ddz * ddz;
