@@ -52,13 +52,13 @@ COUNTER_SCALE = {"fetch": 2.0, "write": 1.0}
 MEASURED_TRAFFIC = {
     ("f32", 16384, 5000, 192): {
         "sources": {"paper_2508_15522_amd/csrc/gff_relax.hip":
-                    "4965f4e9f6752dc59c092d16e5b5892f2ca1f65e2fafb0cc86af1599f60d2e1c",
+                    "9283bd68fec64c5728cf3bb3bf9b5c73e503c9c5c0bc6365b4ee3760253969ac",
                     "paper_2508_15522_amd/csrc/gff_internal.hpp":
-                    "678e935cc46abbe009d1a756ca08f31bb22802c80aff928cdac16a63e6c8f54e",
+                    "292688bf231d8aa97cae1d155c53d9cd5057b10c7087da7ad24bc2be08d79351",
                     "paper_2508_15522_amd/csrc/gff_host.hip":
                     "2aa04dd935f3d23fd37d27ccea38d3373c1936d34b561ec069f5a5d707862209"},
-        "fetch_kib": 292520047.9375, "write_kib": 100363.1875,
-        "valu_insts": 190484586196.0,          # SQ_INSTS_VALU (wave instructions) of the launch
+        "fetch_kib": 214912281.9375, "write_kib": 100342.1875,
+        "valu_insts": 190632080689.0,          # SQ_INSTS_VALU (wave instructions) of the launch
     },
 }
 # FP32 VALU issue slots per second: 256 CUs x 4 SIMDs x 2.4 GHz / 4 cycles per wave64 instruction

@@ -115,9 +115,13 @@ gff_status gff_fit_bspline(const gff_grid_spec *spec, const double *d_V, double 
                            void *d_work, size_t work_bytes, void *stream);
 
 /* Storage cast of fitted coefficients into the evaluation layout:
- * coef[i][j][p][c4], p = 0 .. nz+2 holds z node p-1 with even-mirror padding
- * (node -1 -> 1, node nz -> nz-2, node nz+1 -> nz-3), c4 = (Pauli, London, Coulomb, 0)
- * (F16: (Pauli, London, Coulomb, Pauli residual)).
+ * coef[i][j][b][r][c4], padded z plane p = 0 .. nz+2 holding z node p-1 with even-mirror
+ * padding (node -1 -> 1, node nz -> nz-2, node nz+1 -> nz-3), c4 = (Pauli, London,
+ * Coulomb, 0) (F16: (Pauli, London, Coulomb, Pauli residual)).  Each column is stored as
+ * (nz-1)/5 + 1 overlapping z blocks of 8 slots: slot r of block b holds plane 5b + r (zero
+ * past plane nz+2).  The four planes k .. k+3 an interpolation in z cell k reads are slots
+ * k mod 5 .. k mod 5 + 3 of block k / 5, one 128-byte (F32) or 64-byte (F16) aligned unit
+ * when d_coef is 128-byte aligned, which keeps every column read inside one cache line.
  * GFF_STORE_F32: float; GFF_STORE_F16: IEEE half h_c of b_c / s_c (round to nearest even),
  * with per-channel scale s_c = 2^(ceil(log2 max|b_c|) - 15) written to d_scale[0..2]
  * (d_scale[3] = 0); the fourth half holds l = half(b_P / s_P - h_P), the rounding residual

@@ -248,10 +248,16 @@ __global__ void k_scales_one(float *scale) {
 template <int STORE>
 __global__ void __launch_bounds__(256) k_pack(const double *B, int nx, int ny, int nz, const float *scale, void *out) {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    const int nzp = nz + 3;
-    if (t >= (long)nx * ny * nzp) return;
-    const int p = (int)(t % nzp);
-    const long ij = t / nzp;
+    const int cn = col_nodes(nz);
+    if (t >= (long)nx * ny * cn) return;
+    const int q = (int)(t % cn);
+    const long ij = t / cn;
+    const int p = kZStep * (q / kZBlock) + q % kZBlock;    // padded plane of this slot
+    if (p > nz + 2) {                                       // past the last window: never read
+        if constexpr (STORE == GFF_STORE_F32) reinterpret_cast<float4 *>(out)[t] = make_float4(0.f, 0.f, 0.f, 0.f);
+        else reinterpret_cast<ushort4 *>(out)[t] = make_ushort4(0, 0, 0, 0);
+        return;
+    }
     int k = p - 1;
     if (k < 0) k = -k;
     if (k > nz - 1) k = 2 * (nz - 1) - k;
@@ -512,7 +518,7 @@ extern "C" gff_status gff_fit_bspline(const gff_grid_spec *spec, const double *d
 
 extern "C" size_t gff_grid_bytes(const gff_grid_spec *spec, int storage) {
     if (!spec_ok(spec)) return 0;
-    const size_t nodes = (size_t)spec->nx * spec->ny * (spec->nz + 3);
+    const size_t nodes = (size_t)spec->nx * spec->ny * col_nodes(spec->nz);
     if (storage == GFF_STORE_F32) return nodes * 4 * sizeof(float);
     if (storage == GFF_STORE_F16) return nodes * 4 * sizeof(uint16_t);
     if (storage == GFF_STORE_TRILINEAR) return (size_t)spec->nx * spec->ny * spec->nz * 3 * sizeof(float4);
@@ -526,7 +532,7 @@ extern "C" gff_status gff_pack_grid(const gff_grid_spec *spec, const double *d_B
         return GFF_EUNSUPPORTED;
     if (storage == GFF_STORE_F16 && !d_scale) return GFF_EINVAL;
     hipStream_t s = (hipStream_t)stream;
-    const long nodes = (long)spec->nx * spec->ny * (spec->nz + 3);
+    const long nodes = (long)spec->nx * spec->ny * col_nodes(spec->nz);
     const unsigned nb = (unsigned)((nodes + 255) / 256);
     if (storage == GFF_STORE_F32) {
         if (d_scale) hipLaunchKernelGGL(k_scales_one, dim3(1), dim3(64), 0, s, d_scale);

@@ -10,6 +10,18 @@
 namespace gff {
 
 constexpr int kMaxAtoms = 128;             // atoms per molecule type (4 x 32-bit exclusion words)
+
+// Evaluation layout of a B-spline grid along z: a column's padded planes p = 0 .. nz+2
+// (plane p holds node p-1) are stored as overlapping blocks of kZBlock nodes, block b
+// holding planes kZStep b .. kZStep b + kZBlock - 1.  The four planes k .. k+3 that an
+// interpolation in cell k reads all lie in block k / kZStep, so with a block of 8 nodes
+// (128 bytes F32, 64 bytes F16, aligned to that size) every column window is one L2 line
+// instead of straddling two for three cells in eight; the cost is 8/5 of the plain column.
+constexpr int kZBlock = 8, kZStep = 5;
+__host__ __device__ constexpr int col_nodes(int nz) { return ((nz - 1) / kZStep + 1) * kZBlock; }
+// position in the column of padded plane k (k = 0 .. nz-1), the window's first node
+__host__ __device__ constexpr int window_node(int k) { return k + (kZBlock - kZStep) * (int)((unsigned)k / kZStep); }
+
 constexpr float kEvPerAmuA2Fs2 = 103.6426965268f;  // 1 amu A^2 / fs^2 in eV
 constexpr double kDefaultKe = 14.3996454784;
 

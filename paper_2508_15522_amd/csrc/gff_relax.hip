@@ -38,7 +38,8 @@ struct GridView {
     const void *coef;
     float x0, y0, z0, idx, idy, idz;
     float dx, dy, dz, zmax;              // zmax = nz - 1
-    int nx, ny, nzp;                     // nzp = nz + 3 padded planes
+    int nx, ny, nzp;                     // nodes per stored column: col_nodes(nz) (B-spline
+                                         // storages, z blocks), nz (trilinear)
     float s0, s1, s2;                    // per-channel decode scales (filled on the device)
     const float *scale;                  // F16: device scales [4]; NULL for F32
     unsigned bytes;                      // size of the coefficient array
@@ -131,7 +132,7 @@ __device__ __forceinline__ int wrap_index(float q, int n) {
 }
 
 template <int STORE>
-__device__ __forceinline__ float4 load_node_buf(__amdgpu_buffer_rsrc_t r, int off) {
+__device__ __forceinline__ float4 load_node_buf(__amdgpu_buffer_rsrc_t r, unsigned off) {
     if constexpr (STORE == GFF_STORE_F32) {
         const auto v = __builtin_amdgcn_raw_buffer_load_b96(r, off, 0, 0);
         return make_float4(__uint_as_float(v[0]), __uint_as_float(v[1]), __uint_as_float(v[2]), 0.f);
@@ -182,7 +183,7 @@ __device__ __forceinline__ float grid_eval(const GridView &g, float x, float y, 
         float yv = 0.f, yy = 0.f, yz = 0.f;
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            const int col = (ix[a] * g.ny + jy[b]) * g.nzp + k;   // padded plane k holds node k-1
+            const int col = (ix[a] * g.ny + jy[b]) * g.nzp + window_node(k);   // plane k holds node k-1
             float m[4];
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
@@ -304,7 +305,8 @@ __device__ __forceinline__ float sub_sum(float v) {
     return v;
 }
 
-// Hand-off of one atom's grid lookup: owner lane -> the quad that gathers for it.
+// Hand-off of one atom's grid lookup: owner lane -> the quad that gathers for it; k is the
+// slot in the stored column of the first plane of the cell's z window (window_node).
 struct GridKey { int i, j, k, valid; };
 
 // Owner side: cell indices and in-cell offsets (same rules as grid_eval).
@@ -321,13 +323,14 @@ __device__ __forceinline__ GridKey grid_key(const GridView &g, float x, float y,
     float qz = cell_split(z - g.z0, g.dz, g.idz, tz);
     if (qz < 0.f) { qz = 0.f; tz = 0.f; fl |= GFF_REP_OUT_OF_DOMAIN; }
     if (qz > g.zmax || (qz == g.zmax && tz > 0.f)) return key;         // above the grid: zero
-    key.i = wrap_index(qx, g.nx); key.j = wrap_index(qy, g.ny); key.k = (int)qz; key.valid = 1;
+    key.i = wrap_index(qx, g.nx); key.j = wrap_index(qy, g.ny); key.k = window_node((int)qz); key.valid = 1;
     t = make_float4(tx, ty, tz, 0.f);
     return key;
 }
 
-// Quad side, fetch: lane s of the quad loads node k-1+s of each of the 16 columns (so the
-// quad reads each column as one contiguous 64-byte (F32) / 32-byte (F16) segment) and
+// Quad side, fetch: lane s of the quad loads slot key.k + s, z node k-1+s of cell k, of
+// each of the 16 columns (so the quad reads each column as one contiguous 64-byte (F32) /
+// 32-byte (F16) segment inside one z block, hence inside one 128-byte line) and
 // mixes the channels with the atom's (P, L, Q): m[4a+b] is the mixed coefficient of
 // column (i-1+a, j-1+b) on the lane's plane.
 template <int STORE>
@@ -340,15 +343,15 @@ __device__ __forceinline__ void quad_fetch(const GridView &g, GridKey key, float
     jy[0] = (j == 0 ? g.ny : j) - 1; jy[1] = j;
     jy[2] = (j + 1 == g.ny) ? 0 : j + 1; jy[3] = (j + 2 >= g.ny) ? j + 2 - g.ny : j + 2;
     const float Ps = P * g.s0, Ls = L * g.s1, Qs = Q * g.s2;
-    // 32-bit byte offsets into a buffer resource (out-of-range offsets would read 0)
-    constexpr int NB = STORE == GFF_STORE_F32 ? 16 : 8;
-    const int col_stride = g.nzp * NB;
-    int yoff[4];
+    // 32-bit unsigned byte offsets into a buffer resource (out-of-range offsets would read 0)
+    constexpr unsigned NB = STORE == GFF_STORE_F32 ? 16 : 8;
+    const unsigned col_stride = (unsigned)g.nzp * NB;
+    unsigned yoff[4];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) yoff[b] = jy[b] * col_stride + (key.k + s) * NB;
+    for (int b = 0; b < 4; ++b) yoff[b] = (unsigned)jy[b] * col_stride + (unsigned)(key.k + s) * NB;
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-        const int xoff = ix[a] * g.ny * col_stride;
+        const unsigned xoff = (unsigned)ix[a] * (unsigned)g.ny * col_stride;
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
             const float4 c = load_node_buf<STORE>(g.rsrc, xoff + yoff[b]);
@@ -360,7 +363,7 @@ __device__ __forceinline__ void quad_fetch(const GridView &g, GridKey key, float
 // Quad side, split fetch for overlapping the loads with other work: quad_issue loads the
 // nodes of x-planes a0, a0+1 (8 columns) of the lane's plane; quad_mix decodes and mixes
 // them into m[4 a0 .. 4 a0 + 7] with the same arithmetic as quad_fetch.
-struct QuadAddr { int xoff[4], yoff[4]; };
+struct QuadAddr { unsigned xoff[4], yoff[4]; };
 template <int STORE>
 __device__ __forceinline__ QuadAddr quad_addr(const GridView &g, int4 ki, int s) {
     const int i = ki.x, j = ki.y;
@@ -369,13 +372,13 @@ __device__ __forceinline__ QuadAddr quad_addr(const GridView &g, int4 ki, int s)
     ix[2] = (i + 1 == g.nx) ? 0 : i + 1; ix[3] = (i + 2 >= g.nx) ? i + 2 - g.nx : i + 2;
     jy[0] = (j == 0 ? g.ny : j) - 1; jy[1] = j;
     jy[2] = (j + 1 == g.ny) ? 0 : j + 1; jy[3] = (j + 2 >= g.ny) ? j + 2 - g.ny : j + 2;
-    constexpr int NB = STORE == GFF_STORE_F32 ? 16 : 8;
-    const int col_stride = g.nzp * NB;
+    constexpr unsigned NB = STORE == GFF_STORE_F32 ? 16 : 8;
+    const unsigned col_stride = (unsigned)g.nzp * NB;
     QuadAddr q;
 #pragma unroll
-    for (int b = 0; b < 4; ++b) q.yoff[b] = jy[b] * col_stride + (ki.z + s) * NB;
+    for (int b = 0; b < 4; ++b) q.yoff[b] = (unsigned)jy[b] * col_stride + (unsigned)(ki.z + s) * NB;
 #pragma unroll
-    for (int a = 0; a < 4; ++a) q.xoff[a] = ix[a] * g.ny * col_stride;
+    for (int a = 0; a < 4; ++a) q.xoff[a] = (unsigned)ix[a] * (unsigned)g.ny * col_stride;
     return q;
 }
 // Raw node words as loaded (F32: three channel floats; F16: two words of packed halves);
@@ -385,7 +388,7 @@ template <> struct RawNode<GFF_STORE_F32> { unsigned w[3]; };
 template <> struct RawNode<GFF_STORE_F16> { unsigned w[2]; };
 
 template <int STORE>
-__device__ __forceinline__ RawNode<STORE> load_raw(__amdgpu_buffer_rsrc_t r, int off) {
+__device__ __forceinline__ RawNode<STORE> load_raw(__amdgpu_buffer_rsrc_t r, unsigned off) {
     RawNode<STORE> n;
     if constexpr (STORE == GFF_STORE_F32) {
         const auto v = __builtin_amdgcn_raw_buffer_load_b96(r, off, 0, 0);
@@ -447,7 +450,7 @@ __device__ __forceinline__ float4 quad_contract(const float m[16], float4 t, int
     return make_float4(quad_sum(E), quad_sum(Ex), quad_sum(Ey), quad_sum(Ez));
 }
 
-// Linear index of the stencil's base node, the key of a cached stencil (-1: no stencil).
+// Linear index of the stencil's first stored slot, the key of a cached stencil (-1: none).
 // It fits in an int: the coefficient array is addressed with 32-bit byte offsets.
 __device__ __forceinline__ int stencil_id(const GridView &g, int4 ki) {
     return ki.w ? (ki.x * g.ny + ki.y) * g.nzp + ki.z : -1;
@@ -1214,7 +1217,7 @@ static gff_status make_view(const gff_grid *gr, GridView &g) {
     g.idx = 1.f / gr->dx; g.idy = 1.f / gr->dy; g.idz = 1.f / gr->dz;
     g.dx = gr->dx; g.dy = gr->dy; g.dz = gr->dz;
     g.zmax = (float)(gr->nz - 1);
-    g.nx = gr->nx; g.ny = gr->ny; g.nzp = gr->nz + 3;
+    g.nx = gr->nx; g.ny = gr->ny; g.nzp = col_nodes(gr->nz);
     if (gr->storage == STORE_TRI) {      // unpadded nodes, plain global loads (64-bit addressing)
         g.nzp = gr->nz;
         if ((double)gr->nx * gr->ny * gr->nz >= 2147483647.0) return GFF_EUNSUPPORTED;   // 32-bit cell ids
@@ -1223,8 +1226,8 @@ static gff_status make_view(const gff_grid *gr, GridView &g) {
         g.scale = nullptr;
         return GFF_OK;
     }
-    const double bytes = (double)gr->nx * gr->ny * (gr->nz + 3) * (gr->storage == GFF_STORE_F32 ? 16 : 8);
-    if (bytes >= 2147483647.0) return GFF_EUNSUPPORTED;    // 32-bit buffer offsets
+    const double bytes = (double)gr->nx * gr->ny * g.nzp * (gr->storage == GFF_STORE_F32 ? 16 : 8);
+    if (bytes >= 4294967295.0) return GFF_EUNSUPPORTED;    // 32-bit unsigned buffer offsets
     g.bytes = (unsigned)bytes;
     g.s0 = g.s1 = g.s2 = 1.f;
     g.scale = nullptr;

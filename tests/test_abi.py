@@ -59,8 +59,12 @@ def test_invalid_arguments_rejected_without_device(lib):
     lib.gff_grid_bytes.restype = C.c_size_t
     assert lib.gff_grid_bytes(C.byref(spec), 0) == 0
     spec = G.grid_spec(8, 8, 8, 0.0, 0.0, 1.0, 0.1)
-    assert lib.gff_grid_bytes(C.byref(spec), 0) == 8 * 8 * 11 * 16
-    assert lib.gff_grid_bytes(C.byref(spec), 1) == 8 * 8 * 11 * 8
+    # columns of z blocks of 8 nodes starting every 5 padded planes: nz = 8 -> 2 blocks
+    assert lib.gff_grid_bytes(C.byref(spec), 0) == 8 * 8 * 16 * 16
+    assert lib.gff_grid_bytes(C.byref(spec), 1) == 8 * 8 * 16 * 8
+    for nz, blocks in ((4, 1), (5, 1), (6, 2), (11, 3), (150, 30)):
+        spec = G.grid_spec(8, 8, nz, 0.0, 0.0, 1.0, 0.1)
+        assert lib.gff_grid_bytes(C.byref(spec), 0) == 8 * 8 * 8 * blocks * 16
     # workspace queries are host arithmetic
     lib.gff_fit_workspace_bytes.restype = C.c_size_t
     assert lib.gff_fit_workspace_bytes(C.byref(spec)) > 0

@@ -88,23 +88,36 @@ def test_interp_points_full_grid_random_coefficients(storage):
 
 def test_pack_layout_f32_and_f16_bitexact():
     """The storage cast is exact: F32 is the rounded coefficient, F16 the RNE half of
-    b / s_c (plus the RNE half of the Pauli channel's residual); plane p holds node p-1
-    with even-mirror padding."""
+    b / s_c (plus the RNE half of the Pauli channel's residual).  Padded plane p holds node
+    p-1 with even-mirror padding; each column stores blocks of 8 slots, block b holding
+    planes 5b .. 5b+7 (slots past plane nz+2 are zero), so that the window of planes
+    k .. k+3 of every cell k lies inside one block."""
     announce("pack layout")
     nx, ny, nz = 9, 7, 11
     spec = _spec(nx, ny, nz)
     B = S.random_coefficients(nx, ny, nz, 3, (1.0, 3e-3, 70.0))
     B[0, 0, 0, 0] = 0.0
-    kk = np.arange(-1, nz + 2)
+    cn = ((nz - 1) // 5 + 1) * 8
+    q = np.arange(cn)
+    plane = 5 * (q // 8) + q % 8
+    used = plane <= nz + 2
+    kk = plane[used] - 1
     kk = np.where(kk < 0, -kk, kk)
     kk = np.where(kk > nz - 1, 2 * (nz - 1) - kk, kk)
+    # every cell's window k .. k+3 sits in one block, at slots k + 3 (k // 5) + s
+    for k in range(nz):
+        w = k + 3 * (k // 5)
+        assert w // 8 == (w + 3) // 8 and list(plane[w:w + 4]) == [k, k + 1, k + 2, k + 3]
     g32 = D.pack_from_coefficients(B, spec, G.STORE_F32, 1.0, 1.0)
-    c32 = g32.coef.cpu().numpy().view(np.float32).reshape(nx, ny, nz + 3, 4)
+    assert g32.coef.numel() == nx * ny * cn * 16
+    c32 = g32.coef.cpu().numpy().view(np.float32).reshape(nx, ny, cn, 4)
     for c in range(3):
-        assert np.array_equal(c32[..., c], B[c][:, :, kk].astype(np.float32))
-    assert (c32[..., 3] == 0).all()
+        assert np.array_equal(c32[:, :, used, c], B[c][:, :, kk].astype(np.float32))
+    assert (c32[:, :, used, 3] == 0).all() and (c32[:, :, ~used] == 0).all()
     g16 = D.pack_from_coefficients(B, spec, G.STORE_F16, 1.0, 1.0)
-    c16 = g16.coef.cpu().numpy().view(np.uint16).reshape(nx, ny, nz + 3, 4)
+    c16 = g16.coef.cpu().numpy().view(np.uint16).reshape(nx, ny, cn, 4)
+    assert (c16[:, :, ~used] == 0).all()
+    c16 = c16[:, :, used]
     _, s = O.fp16_quantize(B)
     for c in range(3):
         ref = (B[c][:, :, kk] / s[c]).astype(np.float16).view(np.uint16)
