@@ -7,6 +7,8 @@ Euclidean norm).  Energies are compared with 2e-5 eV per atom (about 64 terms of
 size |P b| ~ 0.05 eV at 2^-24 relative rounding, plus the FP32 rounding of the
 fractional coordinate).
 """
+import types
+
 import numpy as np
 import pytest
 import torch
@@ -217,3 +219,49 @@ def test_eval_forces_batch_with_intra(block, storage):
     torch.cuda.synchronize()
     # same device function; the mixing coefficients differ only by FP32 rounding of alpha
     assert (F0 - F1).abs().max().item() < 1e-5
+
+
+def test_eval_forces_on_a_grid_beyond_2_gib():
+    """A 1024 x 1024 x 86 FP32 grid stores 2.42e9 bytes (144 z slots per column), so the
+    stencils of molecules placed over the last x columns are read at buffer offsets above
+    2^31; grid and intramolecular forces, energies and flags against the oracle, with the
+    same bounds as the small-grid batch test."""
+    nx = ny = 1024
+    nz = 86
+    announce(f"eval_forces on a {nx}x{ny}x{nz} grid (above 2 GiB)")
+    Lx = Ly = nx * 0.1
+    spec = _spec(nx, ny, nz)
+    assert G.grid_bytes(spec, G.STORE_F32) == nx * ny * 144 * 16 > 2 ** 31
+    B = S.random_coefficients(nx, ny, nz, 13, COEF_SCALE)
+    grid = D.pack_from_coefficients(B, spec, G.STORE_F32, Lx, Ly)
+    geo = grid.geometry
+    mol = S.mol_pah38()
+    n_rep = 32
+    strip = types.SimpleNamespace(Lx=10.0, Ly=Ly, z_top=0.0)
+    pos = S.place_replicas(mol, n_rep, strip, 4242, h_range=(2.0, 3.0))
+    pos[:, :, 0] += Lx - 10.0                       # over the last hundred x columns (and across the wrap)
+    pos = S.f32(pos)
+    flat = pos.reshape(-1, 3)
+    i = np.floor(np.mod(flat[:, 0] - geo["x0"], Lx) / geo["dx"]).astype(np.int64)
+    j = np.floor(np.mod(flat[:, 1] - geo["y0"], Ly) / geo["dy"]).astype(np.int64)
+    assert ((i * ny + j) * 144 * 16 >= 2 ** 31).mean() > 0.5
+    topo = G.Topology([mol])
+    rep_type = np.zeros(n_rep, np.int32)
+    plan = G.Plan(topo, rep_type, block_threads=192)
+    dpos = D.soa(plan, list(pos))
+    F = torch.empty_like(dpos)
+    Ea = torch.empty(plan.n_atoms, device="cuda")
+    Er = torch.empty(plan.n_rep, dtype=torch.float64, device="cuda")
+    st = torch.empty(plan.n_rep, dtype=torch.int32, device="cuda")
+    G.eval_forces(grid.desc, topo, plan, True, dpos, F, Ea, Er, st)
+    torch.cuda.synchronize()
+    del grid
+    Fo, Ero, Eao, sto = O.eval_batch(B, geo, [mol], rep_type, flat)
+    Fg = F.cpu().numpy().T.astype(np.float64)
+    dF = np.linalg.norm(Fg - Fo, axis=1)
+    announce(f"  max |dF| = {dF.max():.3e} (max |F| {np.abs(Fo).max():.2f}); max |dE_rep| = "
+             f"{np.abs(Er.cpu().numpy() - Ero).max():.3e}")
+    assert dF.max() < 1e-4 * max(1.0, np.abs(Fo).max() / 10)
+    assert np.abs(Ea.cpu().numpy() - Eao).max() < 2e-5
+    assert (np.abs(Er.cpu().numpy() - Ero) < 2e-5 * mol.n + 1e-5 * np.abs(Ero)).all()
+    assert np.array_equal(st.cpu().numpy(), sto)
