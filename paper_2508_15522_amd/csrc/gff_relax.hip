@@ -508,6 +508,10 @@ __device__ __forceinline__ void pair_range(const KArgs &A, const float4 *sp, con
             }
             if (j < je) pair(j, sp[rbase + j], splq[rbase + j]);
         } else {
+            // unrolled by two at two lanes per atom only: at one lane per atom the unrolled
+            // loop moves spills into the step loop
+            constexpr int UNROLL = LPA == 2 ? 2 : 1;
+#pragma unroll UNROLL
             for (int j = js; j < je; j += LPA) {
                 const float4 pj = sp[rbase + j];
                 const float4 qj = splq[rbase + j];
