@@ -147,7 +147,9 @@ gff_status gff_pack_grid(const gff_grid_spec *spec, const double *d_B, int stora
  * coordinates strictly above the last node z0 + (nz-1) dz contribute zero.  A
  * GFF_STORE_TRILINEAR grid interpolates the stored nodal energy and force of each channel
  * trilinearly in the cell, mixed with the atom's (P, L, Q); its force is therefore not the
- * gradient of its energy. */
+ * gradient of its energy.  F32 and F16 grids are read through 32-bit buffer offsets: a grid
+ * of gff_grid_bytes >= 4 GiB - 1 is rejected with GFF_EUNSUPPORTED by every call that
+ * evaluates it (a trilinear table needs nx*ny*nz < 2^31). */
 typedef struct {
     int storage;             /* GFF_STORE_F32, GFF_STORE_F16 or GFF_STORE_TRILINEAR */
     int nx, ny, nz;
