@@ -72,6 +72,23 @@ def test_invalid_arguments_rejected_without_device(lib):
     assert lib.gff_mlp_n_params(1) == 96 * 256 + 256 + 2 * (256 * 256 + 256) + 41 * 256 + 41 + 32
 
 
+def test_grid_size_limit_of_buffer_offsets(lib):
+    """B-spline grids are read through 32-bit buffer offsets: the evaluation calls accept a
+    grid of up to 4 GiB - 1 and reject a larger one before any device work (n = 0 here, so
+    the stand-in pointers are never dereferenced)."""
+    from paper_2508_15522_amd import gridff as G
+    fake = C.c_void_p(0x1000)
+    scale = C.c_void_p(0x2000)
+    # 1024 x 1024 x 86: 144 slots per column, 2.42e9 bytes in F32
+    g = G.Grid(G.STORE_F32, 1024, 1024, 86, 0, 0, 0, 0.1, 0.1, 0.1, fake, None)
+    assert lib.gff_interp_points(C.byref(g), 0, None, None, None, None, None) == 0
+    # 1024 x 1024 x 160: 256 slots per column, exactly 2^32 bytes in F32, half that in F16
+    g = G.Grid(G.STORE_F32, 1024, 1024, 160, 0, 0, 0, 0.1, 0.1, 0.1, fake, None)
+    assert lib.gff_interp_points(C.byref(g), 0, None, None, None, None, None) == -2
+    g = G.Grid(G.STORE_F16, 1024, 1024, 160, 0, 0, 0, 0.1, 0.1, 0.1, fake, scale)
+    assert lib.gff_interp_points(C.byref(g), 0, None, None, None, None, None) == 0
+
+
 def test_soa_layout_helpers_roundtrip():
     from paper_2508_15522_amd import synth as S
     m = S.mol_chain24()
