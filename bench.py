@@ -487,12 +487,17 @@ def run_scans(grid, log, n_paths=4096):
     diagonal at 3.3 A (0.1 A steps over one diagonal period, 5000 moves per point with a
     force threshold of 0 so that every point takes all of them, the paper's timing
     protocol).  Each scan is one fused launch (gff_relax_scan); the detachment is also run
-    point by point (one launch per point) for comparison.  Wall time of the whole scan."""
+    point by point (one launch per point) for comparison.  Wall time of the whole scan.
+    The detachment runs two lanes per atom in 256-thread blocks: its paths need very
+    different numbers of moves, its wall time is that of the slowest path, and two lanes
+    per atom shorten a lone block's move; the drag, where every path takes every move, runs
+    one lane per atom in 192-thread blocks, the throughput layout."""
     import torch
     from paper_2508_15522_amd import device as D, gridff as G, scans as SC, synth as S
     mol = S.mol_pah38()
     topo = G.Topology([mol])
     plan = G.Plan(topo, np.zeros(n_paths, np.int32), block_threads=192)
+    plan_lat = G.Plan(topo, np.zeros(n_paths, np.int32), block_threads=256, lanes_per_atom=2)
     sub = S.rocksalt_slab(2, 3)
     start = list(S.f32(S.place_replicas(mol, n_paths, sub, S.SEED_PLACE * 7, h_range=(3.0, 3.5))))
     held = np.full(n_paths, mol.elem.index("O"), np.int32)
@@ -500,9 +505,9 @@ def run_scans(grid, log, n_paths=4096):
     z = 1.3 + 0.1 * np.arange(188)
     tg = SC.detachment_targets(start, held, z)
     for name, fn in (("detachment", SC.restrained_scan_fused), ("detachment_point_by_point", SC.restrained_scan)):
-        r = fn(grid, topo, plan, start, held, tg, f_conv=1e-3, max_steps=5000)
+        r = fn(grid, topo, plan_lat, start, held, tg, f_conv=1e-3, max_steps=5000)
         moves = int(r["steps"].sum())
-        out[name] = {"paths": n_paths, "points": len(z), "seconds": r["seconds"],
+        out[name] = {"paths": n_paths, "points": len(z), "launch": [256, 0, 0, 2], "seconds": r["seconds"],
                      "scan_points_per_s": n_paths * len(z) / r["seconds"], "replica_steps_per_s": moves / r["seconds"],
                      "mean_moves_per_point": moves / (n_paths * len(z)),
                      "converged_fraction": float(((r["status"] & G.REP_CONVERGED) != 0).mean())}
@@ -512,13 +517,13 @@ def run_scans(grid, log, n_paths=4096):
     tg = SC.drag_targets(start, held, (1.0, 1.0), 0.1, npts, height=3.3)
     r = SC.restrained_scan_fused(grid, topo, plan, start, held, tg, f_conv=0.0, max_steps=5000)
     moves = int(r["steps"].sum())
-    out["drag"] = {"paths": n_paths, "points": npts, "seconds": r["seconds"],
+    out["drag"] = {"paths": n_paths, "points": npts, "launch": [192, 0, 0, 1], "seconds": r["seconds"],
                    "scan_points_per_s": n_paths * npts / r["seconds"], "replica_steps_per_s": moves / r["seconds"],
                    "moves_per_point": moves / (n_paths * npts)}
     log(f"drag scan: {out['drag']}")
     out["workload"] = ("pah38 on the 2x2x3 slab (112x112x150 FP32 grid), 4096 paths, one rim O held: "
-                       "detachment 1.3-20 A (188 points, FIRE to 1e-3 eV/A, <= 5000 moves); drag along the "
-                       "diagonal at 3.3 A, 0.1 A steps, 5000 moves per point")
+                       "detachment 1.3-20 A (188 points, FIRE to 1e-3 eV/A, <= 5000 moves; two lanes per atom); "
+                       "drag along the diagonal at 3.3 A, 0.1 A steps, 5000 moves per point (one lane per atom)")
     return out
 
 
