@@ -368,7 +368,7 @@ def compare_learned_vs_uniform(grid, mol, collect_minima=50_000, collect_rep=409
             say(f"collect round {r}: converged {rs.converged}/{rs.proposals}, new {rs.new_minima}, "
                 f"mean steps {rs.fire_steps_converged:.0f}, {rs.seconds:.2f} s; {got} minima so far")
         r += 1
-    collect_s = time.time() - t0
+    collect_s, collect_rounds = time.time() - t0, r
     tg = torch.cat(targets, 0).contiguous()
     m = tg.shape[0]
     ntors = torch.full((m,), len(mol.rot_quads), dtype=torch.int32, device="cuda")
@@ -436,7 +436,8 @@ def compare_learned_vs_uniform(grid, mol, collect_minima=50_000, collect_rep=409
     res["gain_minima_per_s_flow"] = (res["learned"]["flow"]["minima_per_s"] /
                                      max(res["uniform"]["flow"]["minima_per_s"], 1e-12))
     res["training"] = dict(minima=m, distinct=arch.count(), steps=train_steps, loss_first=hist[0][1],
-                           loss_last=hist[-1][1], collect_s=collect_s, train_s=train_s, collect_rounds=r)
+                           loss_last=hist[-1][1], collect_s=collect_s, train_s=train_s,
+                           collect_rounds=collect_rounds)
     res["gain_minima_per_s"] = res["learned"]["minima_per_s"] / max(res["uniform"]["minima_per_s"], 1e-12)
     res["gain_minima_per_s_rmsd"] = (res["learned"]["minima_per_s_rmsd"] /
                                      max(res["uniform"]["minima_per_s_rmsd"], 1e-12))
