@@ -52,7 +52,7 @@ COUNTER_SCALE = {"fetch": 2.0, "write": 1.0}
 MEASURED_TRAFFIC = {
     ("f32", 16384, 5000, 192): {
         "sources": {"paper_2508_15522_amd/csrc/gff_relax.hip":
-                    "0d157670ff69f58c7b6fb4dc5b2c5e64b8f6b03f93cb84f3867916f32ca66c3f",
+                    "9dc9019c3b2ac01344b26dfaa5a1347af45c3a2681ff828ec5b3c877fe659e02",
                     "paper_2508_15522_amd/csrc/gff_internal.hpp":
                     "292688bf231d8aa97cae1d155c53d9cd5057b10c7087da7ad24bc2be08d79351",
                     "paper_2508_15522_amd/csrc/gff_host.hip":

@@ -99,19 +99,6 @@ __device__ __forceinline__ void bspline_weights(float t, float w[4], float d[4])
     d[3] = 0.5f * t2;
 }
 
-template <int STORE>
-__device__ __forceinline__ float4 load_node(const void *coef, int node) {
-    if constexpr (STORE == GFF_STORE_F32) {
-        return reinterpret_cast<const float4 *>(coef)[node];
-    } else {
-        // halves (Pauli, London, Coulomb, Pauli residual)
-        uint2 h = reinterpret_cast<const uint2 *>(coef)[node];
-        __half2 a = *reinterpret_cast<__half2 *>(&h.x), b = *reinterpret_cast<__half2 *>(&h.y);
-        float2 fa = __half22float2(a), fb = __half22float2(b);
-        return make_float4(fa.x + fb.y, fa.y, fb.x, 0.f);
-    }
-}
-
 // Cell index q and in-cell offset t in [0,1] of a coordinate r (relative to the grid origin)
 // on an axis with spacing h.  The remainder r - q h is formed with a single rounding (fma),
 // so t carries no error proportional to |r| / h (far lateral images stay accurate).
@@ -145,61 +132,6 @@ __device__ __forceinline__ float4 load_node_buf(__amdgpu_buffer_rsrc_t r, unsign
     }
 }
 
-// Grid energy E = P V^P + L V^L + Q V^C at (x,y,z) and its gradient.  Channels are
-// pre-mixed per node (linearity), then contracted along z (16 columns), y (4 rows), x.
-// Index arithmetic never leaves the grid: x,y wrap, z is clamped to the first plane
-// below (flag OUT_OF_DOMAIN), points above the last plane contribute zero, and
-// non-finite coordinates skip the gather and return NaN.
-template <int STORE>
-__device__ __forceinline__ float grid_eval(const GridView &g, float x, float y, float z,
-                                           float P, float L, float Q,
-                                           float &gx, float &gy, float &gz, unsigned &fl) {
-    gx = gy = gz = 0.f;
-    if (!(__builtin_isfinite(x) && __builtin_isfinite(y) && __builtin_isfinite(z))) {
-        fl |= GFF_REP_NONFINITE;
-        gx = gy = gz = __builtin_nanf("");
-        return __builtin_nanf("");
-    }
-    float tx, ty, tz;
-    const float qx = cell_split(x - g.x0, g.dx, g.idx, tx);
-    const float qy = cell_split(y - g.y0, g.dy, g.idy, ty);
-    float qz = cell_split(z - g.z0, g.dz, g.idz, tz);
-    if (qz < 0.f) { qz = 0.f; tz = 0.f; fl |= GFF_REP_OUT_OF_DOMAIN; }     // evaluated on z0
-    if (qz > g.zmax || (qz == g.zmax && tz > 0.f)) return 0.f;            // above the grid
-    float wx[4], dx[4], wy[4], dy[4], wz[4], dz[4];
-    bspline_weights(tx, wx, dx);
-    bspline_weights(ty, wy, dy);
-    bspline_weights(tz, wz, dz);
-    const int i = wrap_index(qx, g.nx), j = wrap_index(qy, g.ny), k = (int)qz;   // k in [0, nz-1]
-    int ix[4], jy[4];
-    ix[0] = (i == 0 ? g.nx : i) - 1; ix[1] = i;
-    ix[2] = (i + 1 == g.nx) ? 0 : i + 1; ix[3] = (i + 2 >= g.nx) ? i + 2 - g.nx : i + 2;
-    jy[0] = (j == 0 ? g.ny : j) - 1; jy[1] = j;
-    jy[2] = (j + 1 == g.ny) ? 0 : j + 1; jy[3] = (j + 2 >= g.ny) ? j + 2 - g.ny : j + 2;
-    const float Ps = P * g.s0, Ls = L * g.s1, Qs = Q * g.s2;
-    float E = 0.f, Ex = 0.f, Ey = 0.f, Ez = 0.f;
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        float yv = 0.f, yy = 0.f, yz = 0.f;
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int col = (ix[a] * g.ny + jy[b]) * g.nzp + window_node(k);   // plane k holds node k-1
-            float m[4];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const float4 q = load_node<STORE>(g.coef, col + c);
-                m[c] = Ps * q.x + Ls * q.y + Qs * q.z;
-            }
-            const float zv = wz[0] * m[0] + wz[1] * m[1] + wz[2] * m[2] + wz[3] * m[3];
-            const float zd = dz[0] * m[0] + dz[1] * m[1] + dz[2] * m[2] + dz[3] * m[3];
-            yv += wy[b] * zv; yy += dy[b] * zv; yz += wy[b] * zd;
-        }
-        E += wx[a] * yv; Ex += dx[a] * yv; Ey += wx[a] * yy; Ez += wx[a] * yz;
-    }
-    gx = Ex * g.idx; gy = Ey * g.idy; gz = Ez * g.idz;
-    return E;
-}
-
 // ---- trilinear scheme (stored nodal value and index-space gradient per channel)
 struct TriKey {
     int i, j, k;
@@ -207,8 +139,8 @@ struct TriKey {
     int state;                            // 0 in the grid, 1 above it (zero), 2 non-finite
 };
 
-// Cell and in-cell offsets with the domain rules of grid_eval; a point exactly on the last
-// plane uses the cell below it at offset 1.
+// Cell and in-cell offsets with the domain rules of grid_key (B-spline); a point exactly on
+// the last plane uses the cell below it at offset 1.
 __device__ __forceinline__ TriKey tri_key(const GridView &g, float x, float y, float z, unsigned &fl) {
     TriKey K{0, 0, 0, 0.f, 0.f, 0.f, 0};
     if (!(__builtin_isfinite(x) && __builtin_isfinite(y) && __builtin_isfinite(z))) {
@@ -309,7 +241,9 @@ __device__ __forceinline__ float sub_sum(float v) {
 // slot in the stored column of the first plane of the cell's z window (window_node).
 struct GridKey { int i, j, k, valid; };
 
-// Owner side: cell indices and in-cell offsets (same rules as grid_eval).
+// Owner side: cell indices and in-cell offsets.  Index arithmetic never leaves the grid:
+// x, y wrap, z below the first plane is clamped to it (flag OUT_OF_DOMAIN), points above
+// the last plane get no stencil (zero), non-finite coordinates none either (flag NONFINITE).
 __device__ __forceinline__ GridKey grid_key(const GridView &g, float x, float y, float z, float4 &t, unsigned &fl) {
     GridKey key{0, 0, 0, 0};
     t = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -1178,14 +1112,36 @@ k_replicas(KArgs A) {
     }
 }
 
-// Atom-parallel interpolation of independent points (no molecules).
+// Interpolation of independent points (no molecules).  B-spline storages: a quad of lanes
+// per point, the replica kernel's gather and contraction (lane s loads the window's plane s
+// of the 16 columns, one cache line per column; the quad sums the partial contractions), so
+// a wave keeps 16 points' column reads in flight in 16-byte pieces.  Trilinear: a lane per
+// point.  Index arithmetic never leaves the grid: x, y wrap, z below the grid is evaluated on
+// the first plane, points above the last plane contribute zero, non-finite coordinates give
+// NaN without a gather.
 template <int STORE>
 __global__ void __launch_bounds__(256) k_points(GridView g, int n, const float *pos, const float *plq,
                                                 float *F, float *E) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
     unsigned fl = 0;
-    if constexpr (STORE == STORE_TRI) {
+    if constexpr (STORE != STORE_TRI) {
+        const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+        const int p = (int)(t >> 2), s = (int)(t & 3);
+        if (p >= n) return;                          // whole quads: p is the same on a quad's lanes
+        fetch_scales(g);
+        float4 tt;
+        const GridKey key = grid_key(g, pos[p], pos[p + n], pos[p + 2 * n], tt, fl);
+        float m[16];
+        if (key.valid) quad_fetch<STORE>(g, key, plq[p], plq[p + n], plq[p + 2 * n], s, m);
+        const float4 r = quad_contract(m, tt, s, key.valid != 0);
+        if (s == 0) {
+            float e = r.x, fx = -r.y * g.idx, fy = -r.z * g.idy, fz = -r.w * g.idz;
+            if (fl & GFF_REP_NONFINITE) e = fx = fy = fz = __builtin_nanf("");
+            F[p] = fx; F[p + n] = fy; F[p + 2 * n] = fz;
+            if (E) E[p] = e;
+        }
+    } else {
+        const int p = blockIdx.x * blockDim.x + threadIdx.x;
+        if (p >= n) return;
         const TriKey K = tri_key(g, pos[p], pos[p + n], pos[p + 2 * n], fl);
         float e = 0.f;
         float3 f = make_float3(0.f, 0.f, 0.f);
@@ -1198,13 +1154,6 @@ __global__ void __launch_bounds__(256) k_points(GridView g, int n, const float *
             e = tri_interp(g, q, K, f);
         }
         F[p] = f.x; F[p + n] = f.y; F[p + 2 * n] = f.z;
-        if (E) E[p] = e;
-    } else {
-        fetch_scales(g);
-        float gx, gy, gz;
-        const float e = grid_eval<STORE>(g, pos[p], pos[p + n], pos[p + 2 * n], plq[p], plq[p + n],
-                                         plq[p + 2 * n], gx, gy, gz, fl);
-        F[p] = -gx; F[p + n] = -gy; F[p + 2 * n] = -gz;
         if (E) E[p] = e;
     }
 }
@@ -1547,12 +1496,12 @@ extern "C" gff_status gff_interp_points(const gff_grid *grid, int n, const float
     if (rc != GFF_OK) return rc;
     hipStream_t s = (hipStream_t)stream;
     if (n == 0) return GFF_OK;
-    const int blocks = (n + 255) / 256;
+    const unsigned blocks = (unsigned)((n + 255L) / 256), quad_blocks = (unsigned)((4L * n + 255) / 256);
     if (grid->storage == GFF_STORE_F32)
-        hipLaunchKernelGGL(k_points<GFF_STORE_F32>, dim3(blocks), dim3(256), 0, s, g, n, d_pos, d_plq, d_F, d_E);
+        hipLaunchKernelGGL(k_points<GFF_STORE_F32>, dim3(quad_blocks), dim3(256), 0, s, g, n, d_pos, d_plq, d_F, d_E);
     else if (grid->storage == STORE_TRI)
         hipLaunchKernelGGL(k_points<STORE_TRI>, dim3(blocks), dim3(256), 0, s, g, n, d_pos, d_plq, d_F, d_E);
     else
-        hipLaunchKernelGGL(k_points<GFF_STORE_F16>, dim3(blocks), dim3(256), 0, s, g, n, d_pos, d_plq, d_F, d_E);
+        hipLaunchKernelGGL(k_points<GFF_STORE_F16>, dim3(quad_blocks), dim3(256), 0, s, g, n, d_pos, d_plq, d_F, d_E);
     return hip_status(hipGetLastError());
 }

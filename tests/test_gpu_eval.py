@@ -210,7 +210,7 @@ def test_eval_forces_batch_with_intra(block, storage):
     nat = np.array([mols[t].n for t in rep_type])
     assert (np.abs(Er.cpu().numpy() - Ero) < 2e-5 * nat + 1e-5 * np.abs(Ero)).all()
     assert np.array_equal(st.cpu().numpy(), sto)
-    # grid-only evaluation equals the atom-parallel interpolation bit for bit
+    # grid-only evaluation against the point interpolation (the same quad gather and contraction)
     F0 = torch.empty_like(dpos)
     G.eval_forces(grid.desc, topo, plan, False, dpos, F0, None, None, None)
     plq = torch.from_numpy(np.ascontiguousarray(mixing_for(mols, rep_type).T, np.float32)).cuda()
